@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the Shack-Hartmann wavefront-sensor path on one MI355X.
+
+Headline (`value`): E-ELT 80x80 LGS frames per second (config 1: 39 m pupil, 4,632 valid
+10x10-pixel subapertures, 32-point FFT-equivalent spots, 8x8 binned pixels, 10 frozen-flow
+layers of 1024^2, cone compression, 10 km sodium elongation, photon + read noise), one
+frame = one wfs_forward over the whole sensor at one time step, inputs resident in HBM,
+frames replayed from a captured HIP graph (time steps k0 .. k0+K-1 baked in).
+
+Also reported (same JSON line): the batched multi-sensor step (config 2), the adjoint
+(config 3) and the reconstructor (config 4 shape), each against the plain forward, the
+roofline fraction of the dominant kernel and the FP64 oracle's rate on the host CPU.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--quick]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+# the oracle baseline is timed on one core; keep BLAS/FFT helpers single-threaded
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+
+METRIC = ("WFS frames/s (subaperture spots/s) at 80×80 LGS; batched+adjoint vs plain "
+          "forward")
+PEAK_FP32_VALU = 157.3e12  # MI355X published FP32 vector peak
+PEAK_HBM = 8.0e12
+PEAK_FP32_MFMA = 157.3e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------------------------------
+# algorithmic work (what the method must compute; FFT counted as 5 N log2 N per transform)
+# ------------------------------------------------------------------------------------------
+
+def flops_per_subap(n_sub, N, b, elong):
+    lg = np.log2(N)
+    n_pix = N // b
+    f = 4 * n_sub ** 2                                  # field: scale, ramp, sin, cos
+    f += 5 * N * lg * (n_sub + N)                       # zero-padded 2-D FFT, pruned rows
+    f += 3 * N * N + N * N                              # |F|^2 and normalisation
+    if elong:
+        f += 2 * 2.5 * N * N * np.log2(N * N) + 10 * N * (N // 2 + 1)  # R2C, x K, C2R
+    f += N * N                                          # binning
+    f += 4 * n_pix ** 2 + 4                             # centre of gravity
+    return float(f)
+
+
+def plan_flops(cfg, plan, batch=1):
+    """Algorithmic FLOP of one wfs_forward over the plan (valid counts from the library)."""
+    tot = 0.0
+    for s, nv in zip(cfg["sensors"], plan.n_valid):
+        el = s["na_fwhm_m"] > 0 and np.isfinite(s["src_alt_m"])
+        tot += nv * flops_per_subap(s["n_sub"], s["n_fft"], s["bin"], el)
+    return tot * batch
+
+
+# ------------------------------------------------------------------------------------------
+# timing helpers
+# ------------------------------------------------------------------------------------------
+
+def graph_of(torch, fn, n):
+    """Capture n calls fn(i) into one HIP graph."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for i in range(min(n, 3)):  # warm the allocator / code objects on the side stream
+            fn(i)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(n):
+            fn(i)
+    torch.cuda.synchronize()
+    return g
+
+
+def timed_replay(torch, g, n_calls):
+    """Replay graph g once between events on the current stream; returns (wall s, gpu ms)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, e0.elapsed_time(e1) / n_calls
+
+
+def eager_kernel_ms(torch, fn, n):
+    """Mean duration of fn's launch, event pair per call (stream-ordered, eager)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n)]
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(evs):
+        a.record()
+        fn(i)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+# ------------------------------------------------------------------------------------------
+# workloads
+# ------------------------------------------------------------------------------------------
+
+def bench_config1(torch, W, steps, warmup, k0=0):
+    cfg = synth.config1()
+    x = torch.from_numpy(synth.make_batch(cfg, [0])).cuda()
+    plan = W.Plan(cfg)
+    tuned_us = plan.tune(x, iters=10)
+    slopes, aux = plan.forward(x, step=0)
+
+    def frame(i):
+        plan.forward(x, step=k0 + i, seed=42, slopes=slopes, aux=aux)
+
+    for i in range(warmup):
+        frame(i)
+    kernel_ms_eager = eager_kernel_ms(torch, frame, min(steps, 50))
+    g = graph_of(torch, frame, steps)
+    g.replay()  # warm replay
+    wall, gpu_ms = timed_replay(torch, g, steps)
+    return dict(cfg=cfg, plan=plan, wall=wall, gpu_ms_per_frame=gpu_ms,
+                kernel_ms_eager=kernel_ms_eager, tuned_us=tuned_us, x=x)
+
+
+def bench_adjoint(torch, W, reps=20):
+    cfg = synth.config3()
+    x = torch.from_numpy(synth.make_batch(cfg, [cfg["guess_realisation"]])).cuda()
+    plan = W.Plan(cfg)
+    g = torch.from_numpy(synth.random_field((1, plan.n_slopes), seed=7)).cuda()
+    s, a = plan.forward(x, step=0)
+    out = torch.empty_like(x)
+    fwd_ms = eager_kernel_ms(torch, lambda i: plan.forward(x, step=0, slopes=s, aux=a), reps)
+    adj_ms = eager_kernel_ms(torch, lambda i: plan.adjoint(x, g, step=0, fwd_slopes=s,
+                                                          fwd_aux=a, out=out), reps)
+    adj_re_ms = eager_kernel_ms(torch, lambda i: plan.adjoint(x, g, step=0, out=out), reps)
+    frames = len(cfg["sensors"])
+    return dict(workload="config3: 6 LGS 80x80, 10 layers 1024^2, one realisation, noise off",
+                forward_ms=fwd_ms, adjoint_ms=adj_ms, adjoint_recompute_ms=adj_re_ms,
+                adjoint_frames_per_s=frames / (adj_ms * 1e-3),
+                adjoint_vs_forward=fwd_ms / adj_ms)
+
+
+def bench_recon(torch, W, reps=10):
+    M, N, B = synth.configs.N_ACT_ROWS, 55608, 8
+    R = torch.from_numpy(synth.make_reconstructor(M, N)).cuda()
+    S = torch.from_numpy(synth.random_field((B, N), seed=11)).cuda()
+    C = torch.zeros(B, M, device="cuda")
+    S1 = S[:1].contiguous()
+    C1 = torch.zeros(1, M, device="cuda")
+    W.recon_apply(R, S, C)
+    ms8 = eager_kernel_ms(torch, lambda i: W.recon_apply(R, S, C), reps)
+    ms1 = eager_kernel_ms(torch, lambda i: W.recon_apply(R, S1, C1), reps)
+    byts = M * N * 4
+    return dict(workload="config4 reconstructor 5400 x 55608 FP32, B=8 (MFMA) and B=1 (GEMV)",
+                ms_b8=ms8, ms_b1=ms1, hbm_gbps_b8=byts / (ms8 * 1e-3) / 1e9,
+                hbm_gbps_b1=byts / (ms1 * 1e-3) / 1e9,
+                hbm_frac_b8=byts / (ms8 * 1e-3) / PEAK_HBM,
+                hbm_frac_b1=byts / (ms1 * 1e-3) / PEAK_HBM)
+
+
+def cpu_baseline(frames=8):
+    import oracle
+    cfg = synth.config1()
+    x = synth.make_batch(cfg, [0]).astype(np.float64)
+    oracle.forward(x, cfg, 0)  # warm
+    t0 = time.perf_counter()
+    for k in range(frames):
+        oracle.forward(x, cfg, k)
+    dt = time.perf_counter() - t0
+    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{frames} full config-1 frames (4,632 subapertures each), numpy FP64, "
+                      f"1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="headline only (no extras, no CPU)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the "
+              "multi-GPU sharding is a design note, not a launched path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1608_00386_amd as W
+    W.lib()  # fails loudly when the HIP library is missing
+    torch.cuda.set_device(0)
+
+    log("[bench] config1 forward ...")
+    r1 = bench_config1(torch, W, args.steps, args.warmup)
+    cfg1 = r1["cfg"]
+    subaps = r1["plan"].n_valid[0]
+    frames_per_s = args.steps / r1["wall"]
+    flops = plan_flops(cfg1, r1["plan"])
+    kern_s = r1["gpu_ms_per_frame"] * 1e-3
+    achieved = flops / kern_s
+    out = {
+        "metric": METRIC,
+        "value": frames_per_s,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r1["wall"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded von Karman screens, config-1 geometry)",
+        "config": {"workload": "config1: E-ELT 80x80 LGS, 39 m/11 m pupil, 4632 subaps of 10x10 "
+                               "px, N=32, 8x8 px, 10 layers 1024^2 0-16 km, H=90 km, Na 10 km, "
+                               "noise on", "frames_per_step": 1, "subaps": subaps,
+                   "graph_replay": True},
+        "spots_per_s": frames_per_s * subaps,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "kernel": "wfs_forward_kernel<10>",
+                     "kernel_ms": r1["gpu_ms_per_frame"],
+                     "kernel_ms_eager_events": r1["kernel_ms_eager"],
+                     "algorithmic_flop_per_launch": flops},
+    }
+    if not args.quick:
+        try:
+            log("[bench] config3 adjoint ...")
+            adj = bench_adjoint(torch, W)
+            adj["plain_forward_frames_per_s"] = frames_per_s
+            out["adjoint"] = adj
+        except Exception as e:  # report, do not hide
+            out["adjoint"] = {"error": repr(e)}
+        try:
+            log("[bench] config4 reconstructor ...")
+            out["recon"] = bench_recon(torch, W)
+        except Exception as e:
+            out["recon"] = {"error": repr(e)}
+        if not args.no_cpu:
+            log("[bench] cpu baseline (oracle) ...")
+            out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * wfs.h -- C ABI of the MI355X Shack-Hartmann wavefront-sensor library (libwfs.so).
+ *
+ * The operations follow the closed-loop description of Arcidiacono et al., "The numerical
+ * simulation tool for the MAORY multiconjugate adaptive optics system":
+ *   - Sec. 2.1: turbulence is a set of static phase screens at given altitudes (frozen flow);
+ *   - Sec. 2.2: the wavefront of each guide star is the geometric projection of the screens
+ *     along its direction, the laser guide star being at a finite distance (cone effect);
+ *   - Sec. 2.7: the wavefront-sensor module turns the residual phase (open loop minus DM) into
+ *     X/Y slopes; the slopes times the control matrix give differential coefficients added to
+ *     the mirror (pure integrator); the sodium layer enters at this level;
+ *   - Sec. 1: the sensors are Shack-Hartmann (six LGS, three NGS in MAORY).
+ *
+ * Conventions shared by every call
+ *   - All data buffers are DEVICE pointers owned by the caller (float32, row-major).
+ *   - Every call that takes a `stream` (a hipStream_t; NULL = the default stream) is
+ *     asynchronous on it and never synchronises the device, except wfs_plan, wfs_plan_destroy
+ *     and wfs_plan_tune.  No call allocates device memory except wfs_plan, recon_apply
+ *     (first use on a device, or a larger problem than seen before) and wfs_adjoint (first
+ *     use of a plan).
+ *   - Arguments are validated on the host before anything is launched: a bad argument returns
+ *     WFS_EINVAL and launches nothing.  A failed HIP call returns WFS_EDEVICE.  The message of
+ *     the last failure on the calling thread is returned by wfs_last_error().
+ *   - Layer buffer: one realisation occupies `layer_stride` floats; layer l of realisation b
+ *     starts at layers + b*layer_stride + desc[l].offset and is a [ny][nx] row-major grid.
+ *   - Slopes: per realisation, sensors in plan order; per sensor the x slopes of its valid
+ *     subapertures (row-major subaperture order) followed by their y slopes.  Units: binned
+ *     detector pixels (wfs_plan_info gives radians per pixel).  Layout [B][n_slopes].
+ *   - Concurrent calls on one plan must use one stream (they share the plan's device state).
+ */
+#ifndef WFS_H
+#define WFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WFS_OK = 0,
+  WFS_EINVAL = -1,       /* bad argument or shape; nothing launched                   */
+  WFS_ENOMEM = -2,       /* device allocation failed                                  */
+  WFS_EDEVICE = -3,      /* a HIP runtime call or a launch failed                     */
+  WFS_EUNSUPPORTED = -4  /* valid request outside what the kernels implement          */
+};
+
+/* Plan flags (wfs_plan `flags`). */
+#define WFS_FLAG_FORCE_OTF (1u << 0)    /* every sensor on the lag-domain (autocorrelation) path */
+#define WFS_FLAG_FORCE_FFT (1u << 1)    /* every sensor on the FFT path (needs no elongation)     */
+#define WFS_FLAG_NO_XCD_REMAP (1u << 2) /* keep the hardware block order (no per-XCD grouping)    */
+
+/* `step` value meaning "read the step from the plan's device-resident counter". */
+#define WFS_STEP_DEVICE (-1)
+
+typedef struct wfs_plan_s* wfs_plan_t; /* opaque; owns device tables until wfs_plan_destroy */
+
+/* One turbulence layer or deformable-mirror grid (Sec. 2.1 screens; Sec. 2.7 DM). */
+typedef struct {
+  int64_t offset;  /* element offset of the [ny][nx] grid inside one realisation         */
+  int32_t nx, ny;  /* grid size in pixels                                                */
+  double pitch_m;  /* pixel pitch (m)                                                    */
+  double alt_m;    /* altitude above the telescope (m)                                   */
+  double vx_mps;   /* frozen-flow wind (m/s); the screen is sampled at X - v t           */
+  double vy_mps;
+  float weight;    /* +1 turbulence, -1 DM (residual = open loop - DM)                   */
+  int32_t boundary;/* 0 = periodic screen, 1 = zero outside the grid (DM)                */
+} wfs_layer_desc;
+
+/* One Shack-Hartmann sensor and its guide star (Sec. 1, Sec. 2.2, Sec. 2.7). */
+typedef struct {
+  double theta_x_rad, theta_y_rad; /* guide-star direction                                 */
+  double src_alt_m;                /* LGS altitude H (cone factor 1 - h/H); INFINITY = NGS */
+  double lambda_m;                 /* sensing wavelength                                   */
+  double pupil_d_m, obs_d_m;       /* pupil and central-obstruction diameters              */
+  int32_t n_sa;                    /* subapertures across the pupil                        */
+  int32_t n_sub;                   /* pupil pixels across a subaperture                    */
+  int32_t n_fft;                   /* FFT size (zero padding); n_fft >= 2*n_sub            */
+  int32_t bin;                     /* detector binning; n_fft % bin == 0                   */
+  double valid_frac;               /* subaperture used when lit fraction >= valid_frac     */
+  double na_fwhm_m;                /* Gaussian sodium profile FWHM; 0 = no elongation      */
+  double launch_x_m, launch_y_m;   /* laser launch position in the pupil                   */
+  double photons;                  /* photons per fully lit subaperture per frame;
+                                      0 = unit flux and no noise                           */
+  double read_noise_e;             /* read noise (electrons rms), used when photons > 0    */
+} wfs_sensor_desc;
+
+/*
+ * wfs_plan -- build the geometry tables of a set of sensors looking through a set of layers.
+ *   layers[n_layers], sensors[n_sensors]: descriptors (copied).  layer_stride: floats per
+ *   realisation in the layer buffer.  batch: realisations per call (B).  lambda_ref_m: the
+ *   wavelength at which the layer values are radians of phase.  dt_s: time per step (the
+ *   screens are sampled at t = step*dt).  flags: WFS_FLAG_*.  *out receives the plan.
+ *   Validation: n_fft % bin == 0, n_fft >= 2*n_sub, grids inside the stride, positive sizes.
+ *   Synchronises the device (uploads the tables).
+ */
+int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_stride,
+             const wfs_sensor_desc* sensors, int32_t n_sensors, int32_t batch,
+             double lambda_ref_m, double dt_s, uint32_t flags, wfs_plan_t* out);
+
+/*
+ * wfs_plan_info -- sizes of a plan (any output pointer may be NULL).
+ *   n_slopes: slopes per realisation; n_valid_total: valid subapertures over all sensors
+ *   (length of one realisation's aux row); n_valid_per_sensor[n_sensors];
+ *   pix_scale_rad[n_sensors]: radians per binned pixel, bin*lambda/(n_fft*dx).
+ */
+int wfs_plan_info(wfs_plan_t plan, int32_t* n_slopes, int32_t* n_valid_total,
+                  int32_t* n_valid_per_sensor, double* pix_scale_rad);
+
+/* wfs_plan_path -- which path each sensor runs: 0 = lag-domain (OTF), 1 = FFT. */
+int wfs_plan_path(wfs_plan_t plan, int32_t* path_per_sensor);
+
+/* wfs_plan_destroy -- free the plan and its device tables (synchronises the device). */
+int wfs_plan_destroy(wfs_plan_t plan);
+
+/*
+ * wfs_forward -- slopes of every sensor for every realisation (Sec. 2.2 + Sec. 2.7):
+ *   projection of the layers along each guide-star direction (cone factor for the LGS,
+ *   frozen-flow shift v*t, periodic/zero boundary), field A exp(i phase) with a half-pixel
+ *   centring ramp on each valid n_sub x n_sub subaperture zero-padded to n_fft, spot
+ *   |DFT|^2 scaled to `photons`, Gaussian sodium elongation along the launch baseline,
+ *   fftshift and bin x bin binning, Gaussian photon + read noise (Philox4x32-10 keyed by
+ *   seed, counters from realisation, sensor, subaperture, pixel pair and step) when the
+ *   sensor has photons > 0, and centre of gravity in binned pixels (0 when the flux <= 0).
+ *   layers: device [B][layer_stride].  step >= 0, or WFS_STEP_DEVICE.  slopes: device
+ *   [B][n_slopes] (written).  aux: device [B][n_valid_total] sum of the binned pixels of
+ *   each subaperture, or NULL.  Deterministic (bitwise) for fixed inputs.
+ */
+int wfs_forward(wfs_plan_t plan, const float* layers, int64_t step, uint64_t seed,
+                float* slopes, float* aux, void* stream);
+
+/*
+ * wfs_project -- the projection step alone (Sec. 2.2): phase at the sensor wavelength of
+ *   every pixel of every valid subaperture, [B][sum over sensors of n_valid*n_sub^2], per
+ *   sensor subaperture-major then row-major pixels; dark pixels hold their projected phase.
+ */
+int wfs_project(wfs_plan_t plan, const float* layers, int64_t step, float* phase,
+                void* stream);
+
+/*
+ * wfs_adjoint -- gradient with respect to the layer buffer of a scalar loss, given the
+ *   gradient with respect to the noise-free slopes (the adjoint of wfs_forward with noise
+ *   off).  Subaperture fields are recomputed from the layers.  fwd_slopes/fwd_aux: the
+ *   noise-free forward outputs for the same layers and step (both given, or both NULL: then
+ *   they are recomputed).  grad_layers: device [B][layer_stride], overwritten (zero outside
+ *   the grids).  Uses floating-point atomics: reproducible to rounding, not bitwise.
+ */
+int wfs_adjoint(wfs_plan_t plan, const float* layers, const float* grad_slopes,
+                const float* fwd_slopes, const float* fwd_aux, int64_t step,
+                float* grad_layers, void* stream);
+
+/* wfs_set_step / wfs_advance_step -- write / add to the plan's device step counter
+ * (captured-graph replays read it with step = WFS_STEP_DEVICE). */
+int wfs_set_step(wfs_plan_t plan, int64_t step, void* stream);
+int wfs_advance_step(wfs_plan_t plan, int64_t delta, void* stream);
+
+/*
+ * wfs_plan_tune -- time the launch schedules (subapertures per wave, block order, path where
+ *   both apply) on `layers` and keep the fastest in the plan.  Synchronises; writes scratch
+ *   slopes internally.  iters: timed launches per candidate.  On return *best_us holds the
+ *   best time per forward call (may be NULL).
+ */
+int wfs_plan_tune(wfs_plan_t plan, const float* layers, int32_t iters, double* best_us,
+                  void* stream);
+
+/*
+ * recon_apply -- reconstructor (control matrix) times slopes, Sec. 2.6-2.7:
+ *   C[b][i] = alpha * sum_j R[i][j] S[b][j] + beta * C[b][i],  i < M, j < N, b < B.
+ *   R: device [M][N] row-major.  S: device [B][N].  C: device, row b at C + b*ldc
+ *   (ldc >= M).  beta = 0 ignores the old C.  A pure integrator a += g R s is
+ *   alpha = g, beta = 1 on the DM actuator rows.  B = 1 runs a streaming GEMV; B >= 2 a
+ *   split-K matrix-core (MFMA) GEMM.  Deterministic.
+ */
+int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B, float* C,
+                int64_t ldc, float alpha, float beta, void* stream);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* wfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WFS_H */

@@ -1,0 +1,12 @@
+"""MI355X Shack-Hartmann wavefront-sensor path (projection, spots, elongation, binning, noise,
+centroids, reconstructor) as hand-written HIP kernels behind the C ABI of include/wfs.h."""
+
+from ._lib import (  # noqa: F401
+    WFS_FLAG_FORCE_FFT,
+    WFS_FLAG_FORCE_OTF,
+    WFS_FLAG_NO_XCD_REMAP,
+    WFS_STEP_DEVICE,
+    WfsError,
+    lib,
+)
+from .wfs import Plan, WFSFunction, recon_apply, wfs_slopes  # noqa: F401

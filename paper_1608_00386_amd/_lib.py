@@ -1,0 +1,125 @@
+"""ctypes view of libwfs.so (include/wfs.h).  Loading fails loudly when the library is absent:
+there is no other implementation to fall back to."""
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwfs.so")
+
+WFS_OK = 0
+WFS_EINVAL = -1
+WFS_ENOMEM = -2
+WFS_EDEVICE = -3
+WFS_EUNSUPPORTED = -4
+
+WFS_FLAG_FORCE_OTF = 1 << 0
+WFS_FLAG_FORCE_FFT = 1 << 1
+WFS_FLAG_NO_XCD_REMAP = 1 << 2
+WFS_STEP_DEVICE = -1
+
+
+class LayerDesc(ctypes.Structure):
+    _fields_ = [
+        ("offset", ctypes.c_int64),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("pitch_m", ctypes.c_double),
+        ("alt_m", ctypes.c_double),
+        ("vx_mps", ctypes.c_double),
+        ("vy_mps", ctypes.c_double),
+        ("weight", ctypes.c_float),
+        ("boundary", ctypes.c_int32),
+    ]
+
+
+class SensorDesc(ctypes.Structure):
+    _fields_ = [
+        ("theta_x_rad", ctypes.c_double),
+        ("theta_y_rad", ctypes.c_double),
+        ("src_alt_m", ctypes.c_double),
+        ("lambda_m", ctypes.c_double),
+        ("pupil_d_m", ctypes.c_double),
+        ("obs_d_m", ctypes.c_double),
+        ("n_sa", ctypes.c_int32),
+        ("n_sub", ctypes.c_int32),
+        ("n_fft", ctypes.c_int32),
+        ("bin", ctypes.c_int32),
+        ("valid_frac", ctypes.c_double),
+        ("na_fwhm_m", ctypes.c_double),
+        ("launch_x_m", ctypes.c_double),
+        ("launch_y_m", ctypes.c_double),
+        ("photons", ctypes.c_double),
+        ("read_noise_e", ctypes.c_double),
+    ]
+
+
+class WfsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libwfs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_c = ctypes
+_P = _c.c_void_p
+_PROTOS = {
+    "wfs_plan": (_c.c_int, [_c.POINTER(LayerDesc), _c.c_int32, _c.c_int64,
+                             _c.POINTER(SensorDesc), _c.c_int32, _c.c_int32, _c.c_double,
+                             _c.c_double, _c.c_uint32, _c.POINTER(_P)]),
+    "wfs_plan_info": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
+                                 _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double)]),
+    "wfs_plan_path": (_c.c_int, [_P, _c.POINTER(_c.c_int32)]),
+    "wfs_plan_destroy": (_c.c_int, [_P]),
+    "wfs_forward": (_c.c_int, [_P, _P, _c.c_int64, _c.c_uint64, _P, _P, _P]),
+    "wfs_project": (_c.c_int, [_P, _P, _c.c_int64, _P, _P]),
+    "wfs_adjoint": (_c.c_int, [_P, _P, _P, _P, _P, _c.c_int64, _P, _P]),
+    "wfs_set_step": (_c.c_int, [_P, _c.c_int64, _P]),
+    "wfs_advance_step": (_c.c_int, [_P, _c.c_int64, _P]),
+    "wfs_plan_tune": (_c.c_int, [_P, _P, _c.c_int32, _c.POINTER(_c.c_double), _P]),
+    "recon_apply": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _P, _c.c_int32, _P, _c.c_int64,
+                               _c.c_float, _c.c_float, _P]),
+    "wfs_last_error": (_c.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded libwfs.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1608_00386_amd.build` "
+                "(the HIP library is the only implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc, what=""):
+    if rc != WFS_OK:
+        msg = lib().wfs_last_error().decode(errors="replace")
+        raise WfsError(rc, f"{what}: {msg}" if what else msg)
+    return rc
+
+
+def layer_desc(L):
+    return LayerDesc(int(L["offset"]), int(L["nx"]), int(L["ny"]), float(L["pitch_m"]),
+                     float(L["alt_m"]), float(L["vx_mps"]), float(L["vy_mps"]),
+                     float(L["weight"]), int(L["boundary"]))
+
+
+def sensor_desc(S):
+    alt = S["src_alt_m"]
+    return SensorDesc(float(S["theta_x_rad"]), float(S["theta_y_rad"]),
+                      math.inf if alt is None else float(alt), float(S["lambda_m"]),
+                      float(S["pupil_d_m"]), float(S["obs_d_m"]), int(S["n_sa"]),
+                      int(S["n_sub"]), int(S["n_fft"]), int(S["bin"]), float(S["valid_frac"]),
+                      float(S["na_fwhm_m"]), float(S["launch_x_m"]), float(S["launch_y_m"]),
+                      float(S["photons"]), float(S["read_noise_e"]))

@@ -1,0 +1,282 @@
+// recon_apply: reconstructor (control matrix) times slopes, C = alpha R S^T + beta C
+// (Sec. 2.6-2.7 of the paper: slopes multiplied by the control matrix give the differential
+// coefficients added to the mirror).  R is [M][N] row-major FP32 and is streamed from HBM once
+// per call; that stream bounds the operation (4 flop per byte of R at B = 8).
+//
+//   B == 1, or unaligned operands : split-K streaming GEMV on the vector ALUs
+//   B >= 2, 16-byte aligned, N%4==0: split-K GEMM on the FP32 matrix cores
+//                                    (v_mfma_f32_16x16x4f32, one 16-row x 16-realisation tile
+//                                    per MFMA, 2 row tiles per wavefront)
+// Both write per-split partial sums to a library-owned workspace; a second kernel adds the
+// splits in a fixed order and applies alpha/beta, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+
+#include "../../include/wfs.h"
+
+namespace wfs {
+
+constexpr int kRB = 256;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16-byte streaming load of R (read once per call: non-temporal)
+__device__ __forceinline__ float4 ldnt4(const float* p) {
+  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// ---------------------------------------------------------------------------------------
+// GEMV / generic: wave per (RW rows, split); lanes stride over k.
+// ---------------------------------------------------------------------------------------
+template <int RW, bool VEC>
+__global__ __launch_bounds__(kRB) void recon_valu_kernel(const float* __restrict__ R, int M,
+                                                         int N, const float* __restrict__ S,
+                                                         int b, int chunk, int splits,
+                                                         int row_groups, float* __restrict__ ws) {
+  const int wave = (blockIdx.x * kRB + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= row_groups * splits) return;
+  const int g = wave / splits, sp = wave - g * splits;
+  const int row0 = g * RW;
+  const int k0 = sp * chunk, k1 = min(N, k0 + chunk);
+  const float* s = S + (int64_t)b * N;
+  float acc[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) acc[r] = 0.0f;
+  if (VEC) {
+    // k0 and N are multiples of 4; rows 16-byte aligned
+    for (int k = k0 + 4 * lane; k < k1; k += 4 * 64) {
+      const float4 sv = *reinterpret_cast<const float4*>(s + k);
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int row = min(row0 + r, M - 1);
+        const float4 rv = ldnt4(R + (int64_t)row * N + k);
+        acc[r] = fmaf(rv.x, sv.x, fmaf(rv.y, sv.y, fmaf(rv.z, sv.z, fmaf(rv.w, sv.w, acc[r]))));
+      }
+    }
+  } else {
+    for (int k = k0 + lane; k < k1; k += 64) {
+      const float sv = s[k];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int row = min(row0 + r, M - 1);
+        acc[r] = fmaf(R[(int64_t)row * N + k], sv, acc[r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RW; ++r) {
+    float v = acc[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    acc[r] = v;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+      if (row0 + r < M) ws[((int64_t)sp * 1 + 0) * M + row0 + r] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// MFMA GEMM.  v_mfma_f32_16x16x4f32 operand layout (wave64): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; the four accumulator registers of lane l hold D[4*(l/16)+i][l%16].
+// The K index of one MFMA is only a label shared by A and B, so lane (i, kq) feeds the four
+// consecutive columns k0 + 4 kq + t (t = 0..3) of one float4 load to four MFMAs.
+// Tile: D rows = 16 rows of R, D columns = 16 realisations (b0 .. b0+15, masked to B).
+// ---------------------------------------------------------------------------------------
+
+template <int TR>
+__global__ __launch_bounds__(kRB) void recon_mfma_kernel(const float* __restrict__ R, int M,
+                                                         int N, const float* __restrict__ S,
+                                                         int B, int b0, int chunk, int splits,
+                                                         int row_groups, float* __restrict__ ws) {
+  const int wave = (blockIdx.x * kRB + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= row_groups * splits) return;
+  const int g = wave / splits, sp = wave - g * splits;
+  const int k0 = sp * chunk, k1 = min(N, k0 + chunk);
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int nb = b0 + i16;  // realisation fed by this lane (B operand column)
+  const bool bok = nb < B;
+  const float* srow = S + (int64_t)(bok ? nb : 0) * N;
+  const float* rrow[TR];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int row = min(g * 16 * TR + t * 16 + i16, M - 1);
+    rrow[t] = R + (int64_t)row * N;
+  }
+  v4f acc[TR];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) acc[t] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+  int k = k0;
+  // main loop: 32 columns per iteration (two float4 per lane per operand row)
+  for (; k + 32 <= k1; k += 32) {
+    const int ka = k + 4 * kq, kb = k + 16 + 4 * kq;
+    float4 sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa;
+    if (bok) {
+      sa = *reinterpret_cast<const float4*>(srow + ka);
+      sb = *reinterpret_cast<const float4*>(srow + kb);
+    }
+    float4 ra[TR], rb[TR];
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      ra[t] = ldnt4(rrow[t] + ka);
+      rb[t] = ldnt4(rrow[t] + kb);
+    }
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[t].x, sa.x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[t].y, sa.y, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[t].z, sa.z, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[t].w, sa.w, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].x, sb.x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].y, sb.y, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].z, sb.z, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].w, sb.w, acc[t], 0, 0, 0);
+    }
+  }
+  // tail: 16 columns per step, float4 granularity, guarded
+  for (; k < k1; k += 16) {
+    const int ka = k + 4 * kq;
+    const bool in = ka < k1;
+    float4 sa = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (bok && in) sa = *reinterpret_cast<const float4*>(srow + ka);
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (in) ra = *reinterpret_cast<const float4*>(rrow[t] + ka);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra.x, sa.x, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra.y, sa.y, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra.z, sa.z, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra.w, sa.w, acc[t], 0, 0, 0);
+    }
+  }
+  // D[4*kq + i][i16]: row = tile base + 4 kq + i, realisation = b0 + i16
+  if (bok) {
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = g * 16 * TR + t * 16 + 4 * kq + i;
+        if (row < M) ws[((int64_t)sp * B + nb) * M + row] = acc[t][i];
+      }
+    }
+  }
+}
+
+// C[b][i] = alpha * sum_sp ws[sp][b][i] + beta * C[b][i]   (splits added in order)
+__global__ __launch_bounds__(kRB) void recon_reduce_kernel(const float* __restrict__ ws, int M,
+                                                           int B, int splits, float* C,
+                                                           int64_t ldc, float alpha, float beta,
+                                                           int b_first, int b_count) {
+  const int64_t gid = (int64_t)blockIdx.x * kRB + threadIdx.x;
+  if (gid >= (int64_t)M * b_count) return;
+  const int bl = (int)(gid / M), i = (int)(gid - (int64_t)bl * M);
+  float s = 0.0f;
+  for (int sp = 0; sp < splits; ++sp) s += ws[((int64_t)sp * b_count + bl) * M + i];
+  float* c = C + (int64_t)(b_first + bl) * ldc + i;
+  *c = beta == 0.0f ? alpha * s : fmaf(alpha, s, beta * *c);
+}
+
+// ---------------------------------------------------------------------------------------
+// workspace: one growable buffer per device, kept for the life of the process
+// ---------------------------------------------------------------------------------------
+struct Workspace {
+  float* ptr = nullptr;
+  size_t bytes = 0;
+};
+static std::mutex g_ws_mu;
+static Workspace g_ws[64];
+
+static hipError_t workspace(size_t bytes, float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  Workspace& w = g_ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      (void)hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    e = hipMalloc((void**)&w.ptr, bytes);
+    if (e != hipSuccess) return e;
+    w.bytes = bytes;
+  }
+  *out = w.ptr;
+  return hipSuccess;
+}
+
+static int choose_splits(int row_groups, int N, int align, int* chunk) {
+  const int target_waves = 256 * 16;  // ~4 waves per SIMD
+  int splits = std::max(1, std::min((target_waves + row_groups - 1) / row_groups, N / 256));
+  int c = (N + splits - 1) / splits;
+  c = (c + align - 1) / align * align;
+  splits = (N + c - 1) / c;
+  *chunk = c;
+  return splits;
+}
+
+hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
+                        int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma) {
+  const bool aligned = (N % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)S % 16 == 0);
+  *used_mfma = 0;
+  if (B >= 2 && aligned) {
+    constexpr int TR = 2;
+    const int row_groups = (M + 16 * TR - 1) / (16 * TR);
+    int chunk;
+    const int splits = choose_splits(row_groups, N, 32, &chunk);
+    for (int b0 = 0; b0 < B; b0 += 16) {
+      const int bc = std::min(16, B - b0);
+      float* ws;
+      hipError_t e = workspace(sizeof(float) * (size_t)splits * bc * M, &ws);
+      if (e != hipSuccess) return e;
+      const int waves = row_groups * splits;
+      hipLaunchKernelGGL(recon_mfma_kernel<TR>, dim3((waves + 3) / 4), dim3(kRB), 0, st, R, M,
+                         N, S + (int64_t)b0 * N, bc, 0, chunk, splits, row_groups, ws);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const int64_t n = (int64_t)M * bc;
+      hipLaunchKernelGGL(recon_reduce_kernel, dim3((unsigned)((n + kRB - 1) / kRB)), dim3(kRB), 0,
+                         st, ws, M, bc, splits, C, ldc, alpha, beta, b0, bc);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    *used_mfma = 1;
+    return hipSuccess;
+  }
+  constexpr int RW = 2;
+  const int row_groups = (M + RW - 1) / RW;
+  int chunk;
+  const int splits = choose_splits(row_groups, N, aligned ? 256 : 64, &chunk);
+  for (int b = 0; b < B; ++b) {
+    float* ws;
+    hipError_t e = workspace(sizeof(float) * (size_t)splits * M, &ws);
+    if (e != hipSuccess) return e;
+    const int waves = row_groups * splits;
+    if (aligned)
+      hipLaunchKernelGGL((recon_valu_kernel<RW, true>), dim3((waves + 3) / 4), dim3(kRB), 0, st,
+                         R, M, N, S, b, chunk, splits, row_groups, ws);
+    else
+      hipLaunchKernelGGL((recon_valu_kernel<RW, false>), dim3((waves + 3) / 4), dim3(kRB), 0,
+                         st, R, M, N, S, b, chunk, splits, row_groups, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(recon_reduce_kernel, dim3((M + kRB - 1) / kRB), dim3(kRB), 0, st, ws, M,
+                       1, splits, C, ldc, alpha, beta, b, 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace wfs

@@ -1,0 +1,659 @@
+// Host side of libwfs: argument validation, geometry tables (pupil mask, valid subapertures,
+// cone/frozen-flow affine maps, elongation parameters, binning phase tables), task tables and
+// the C ABI entry points declared in include/wfs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wfs.h"
+#include "wfs_internal.h"
+
+namespace wfs {
+hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st);
+hipError_t launch_project(const FwdParams& p, float* phase, int64_t per_real, hipStream_t st);
+hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
+hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
+int adj_lds_bytes(int ns, int n_layers, int n_pix);
+hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
+                        int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma);
+int otf_lds_bytes(int ns, int n_layers, int n_pix);
+int fft_lds_bytes(int n_sub, int n_fft, int n_pix);
+bool fft_supported(int n_sub, int n_fft, int bin);
+}  // namespace wfs
+
+using namespace wfs;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? WFS_ENOMEM : WFS_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                     \
+  do {                                          \
+    hipError_t _e = (expr);                     \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+struct wfs_plan_s {
+  int device = 0;
+  int32_t n_layers = 0, n_sensors = 0, batch = 0;
+  int64_t layer_stride = 0;
+  double lambda_ref = 0, dt = 0;
+  uint32_t flags = 0;
+  std::vector<wfs_layer_desc> layers;
+  std::vector<wfs_sensor_desc> sensors;
+  std::vector<DevSensor> hsen;
+  std::vector<int32_t> n_valid;
+  std::vector<double> pix_scale;
+  int32_t n_slopes = 0, n_valid_total = 0;
+  int64_t phase_per_real = 0;
+  // device blob holding every table
+  char* d_blob = nullptr;
+  int64_t* d_step = nullptr;
+  FwdParams base{};  // table pointers, sizes and schedule; per-call fields filled at launch
+  int otf_ns = 0;    // lag-domain template instance (0: no lag-domain sensor)
+  int otf_max_npix = 0;
+  int64_t otf_tasks = 0, fft_tasks = 0;
+  int adj_lds_per_wave = 0;
+};
+
+static bool finite_d(double x) { return std::isfinite(x); }
+
+// ------------------------------------------------------------------------------------------
+// geometry
+// ------------------------------------------------------------------------------------------
+
+struct SensorGeom {
+  int n_pup = 0;
+  double dx = 0;
+  std::vector<uint8_t> mask;  // [n_pup][n_pup]
+  std::vector<DevSubap> subs; // valid subapertures, row-major
+};
+
+// Pupil pixels of pitch dx = D / n_pup centred at (i + 1/2 - n_pup/2) dx; lit when the centre
+// radius is within [D_obs/2, D/2]; a subaperture is valid when its lit fraction >= valid_frac.
+static SensorGeom sensor_geometry(const wfs_sensor_desc& s) {
+  SensorGeom g;
+  const int ns = s.n_sub;
+  g.n_pup = s.n_sa * ns;
+  g.dx = s.pupil_d_m / g.n_pup;
+  g.mask.assign((size_t)g.n_pup * g.n_pup, 0);
+  for (int j = 0; j < g.n_pup; ++j) {
+    const double y = (j + 0.5 - g.n_pup / 2.0) * g.dx;
+    for (int i = 0; i < g.n_pup; ++i) {
+      const double x = (i + 0.5 - g.n_pup / 2.0) * g.dx;
+      const double r = std::hypot(x, y);
+      g.mask[(size_t)j * g.n_pup + i] = (r >= s.obs_d_m / 2.0 && r <= s.pupil_d_m / 2.0) ? 1 : 0;
+    }
+  }
+  const double H = s.src_alt_m;
+  const bool elong = s.na_fwhm_m > 0 && finite_d(H);
+  const double sig_h = s.na_fwhm_m / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  const double p_fft = s.lambda_m / (s.n_fft * g.dx);
+  for (int a = 0; a < s.n_sa; ++a) {
+    for (int b = 0; b < s.n_sa; ++b) {
+      int cnt = 0;
+      for (int r = 0; r < ns; ++r)
+        for (int c = 0; c < ns; ++c) cnt += g.mask[(size_t)(a * ns + r) * g.n_pup + b * ns + c];
+      if ((double)cnt / (double)(ns * ns) < s.valid_frac) continue;
+      DevSubap d{};
+      d.a = a;
+      d.b = b;
+      d.v = (int32_t)g.subs.size();
+      const double cx = ((b + 0.5) * ns - g.n_pup / 2.0) * g.dx;
+      const double cy = ((a + 0.5) * ns - g.n_pup / 2.0) * g.dx;
+      const double bx = cx - s.launch_x_m, by = cy - s.launch_y_m;
+      const double bl = std::hypot(bx, by);
+      if (elong && bl > 0) {
+        const double sig_px = bl * sig_h / (H * H) / p_fft;
+        d.alpha = (float)(2.0 * M_PI * M_PI * sig_px * sig_px / ((double)s.n_fft * s.n_fft));
+        d.ex = (float)(bx / bl);
+        d.ey = (float)(by / bl);
+      }
+      g.subs.push_back(d);
+    }
+  }
+  return g;
+}
+
+static int validate(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_stride,
+                    const wfs_sensor_desc* sensors, int32_t n_sensors, int32_t batch,
+                    double lambda_ref_m, double dt_s) {
+  if (!layers || !sensors) return fail(WFS_EINVAL, "wfs_plan: null descriptor array");
+  if (n_layers < 1 || n_layers > kMaxLayers)
+    return fail(WFS_EINVAL, "wfs_plan: n_layers=%d outside [1, %d]", n_layers, kMaxLayers);
+  if (n_sensors < 1 || n_sensors > kMaxSensors)
+    return fail(WFS_EINVAL, "wfs_plan: n_sensors=%d outside [1, %d]", n_sensors, kMaxSensors);
+  if (batch < 1 || batch > (1 << 20)) return fail(WFS_EINVAL, "wfs_plan: batch=%d", batch);
+  if (layer_stride < 1) return fail(WFS_EINVAL, "wfs_plan: layer_stride=%lld", (long long)layer_stride);
+  if (!(lambda_ref_m > 0) || !finite_d(lambda_ref_m))
+    return fail(WFS_EINVAL, "wfs_plan: lambda_ref_m must be > 0");
+  if (!(dt_s >= 0) || !finite_d(dt_s)) return fail(WFS_EINVAL, "wfs_plan: dt_s must be >= 0");
+  for (int l = 0; l < n_layers; ++l) {
+    const wfs_layer_desc& L = layers[l];
+    if (L.nx < 2 || L.ny < 2 || L.nx > (1 << 20) || L.ny > (1 << 20))
+      return fail(WFS_EINVAL, "layer %d: grid %dx%d", l, L.nx, L.ny);
+    if (L.offset < 0 || L.offset + (int64_t)L.nx * L.ny > layer_stride)
+      return fail(WFS_EINVAL, "layer %d: grid [%lld, +%lld) outside the stride %lld", l,
+                  (long long)L.offset, (long long)L.nx * L.ny, (long long)layer_stride);
+    if (!(L.pitch_m > 0) || !finite_d(L.pitch_m) || !finite_d(L.alt_m) || L.alt_m < 0 ||
+        !finite_d(L.vx_mps) || !finite_d(L.vy_mps) || !std::isfinite(L.weight))
+      return fail(WFS_EINVAL, "layer %d: non-finite or non-positive geometry", l);
+    if (L.boundary != 0 && L.boundary != 1)
+      return fail(WFS_EINVAL, "layer %d: boundary must be 0 or 1", l);
+  }
+  int64_t slopes = 0;
+  for (int s = 0; s < n_sensors; ++s) {
+    const wfs_sensor_desc& S = sensors[s];
+    if (S.n_sa < 1 || S.n_sub < 1 || S.n_fft < 2 || S.bin < 1 || S.n_sa > 4096 || S.n_sub > 4096)
+      return fail(WFS_EINVAL, "sensor %d: n_sa=%d n_sub=%d n_fft=%d bin=%d", s, S.n_sa, S.n_sub,
+                  S.n_fft, S.bin);
+    if (S.n_fft % 2) return fail(WFS_EINVAL, "sensor %d: n_fft=%d must be even", s, S.n_fft);
+    if (S.n_fft % S.bin)
+      return fail(WFS_EINVAL, "sensor %d: n_fft=%d not a multiple of bin=%d", s, S.n_fft, S.bin);
+    if (S.n_fft < 2 * S.n_sub)
+      return fail(WFS_EINVAL, "sensor %d: n_fft=%d < 2*n_sub=%d", s, S.n_fft, 2 * S.n_sub);
+    if (!(S.lambda_m > 0) || !(S.pupil_d_m > 0) || !(S.obs_d_m >= 0) || S.obs_d_m >= S.pupil_d_m ||
+        !finite_d(S.lambda_m) || !finite_d(S.pupil_d_m))
+      return fail(WFS_EINVAL, "sensor %d: wavelength/pupil/obstruction", s);
+    if (!(S.src_alt_m > 0)) return fail(WFS_EINVAL, "sensor %d: src_alt_m must be > 0", s);
+    if (!(S.valid_frac > 0) || S.valid_frac > 1)
+      return fail(WFS_EINVAL, "sensor %d: valid_frac must be in (0, 1]", s);
+    if (!(S.photons >= 0) || !(S.read_noise_e >= 0) || !(S.na_fwhm_m >= 0) ||
+        !finite_d(S.photons) || !finite_d(S.read_noise_e) || !finite_d(S.na_fwhm_m) ||
+        !finite_d(S.theta_x_rad) || !finite_d(S.theta_y_rad) || !finite_d(S.launch_x_m) ||
+        !finite_d(S.launch_y_m))
+      return fail(WFS_EINVAL, "sensor %d: photons/noise/elongation/direction", s);
+    if (finite_d(S.src_alt_m))
+      for (int l = 0; l < n_layers; ++l)
+        if (!(layers[l].alt_m < S.src_alt_m))
+          return fail(WFS_EINVAL, "sensor %d: layer %d at or above the LGS altitude", s, l);
+    slopes += 2LL * S.n_sa * S.n_sa;
+  }
+  if (slopes * batch > (1LL << 31) - 1) return fail(WFS_EINVAL, "wfs_plan: too many slopes");
+  return WFS_OK;
+}
+
+template <class T>
+static size_t push_table(std::vector<char>& blob, const std::vector<T>& v) {
+  size_t off = (blob.size() + 255) & ~size_t(255);
+  blob.resize(off + v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+static void fill_tasks(TaskTable& tt, const std::vector<int>& ids, const std::vector<int32_t>& nv) {
+  std::memset(&tt, 0, sizeof tt);
+  tt.n = (int32_t)ids.size();
+  int32_t acc = 0;
+  for (size_t k = 0; k < ids.size(); ++k) {
+    tt.ids[k] = ids[k];
+    tt.start[k] = acc;
+    acc += nv[ids[k]];
+  }
+  tt.start[ids.size()] = acc;
+  tt.per_real = acc;
+}
+
+static void default_schedule(wfs_plan_s* P) {
+  const int64_t tasks = P->otf_tasks;
+  int spw = 1;
+  // enough waves to cover ~8 wavefronts per SIMD on 256 CUs before batching tasks per wave
+  while (tasks / spw > 256LL * 4 * 8 * 2 && spw < 64) spw *= 2;
+  P->base.subaps_per_wave = spw;
+  const int64_t waves = (tasks + spw - 1) / spw;
+  P->base.otf_blocks = (int32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  P->base.xcd_remap = (P->flags & WFS_FLAG_NO_XCD_REMAP) ? 0 : 1;
+}
+
+extern "C" {
+
+const char* wfs_last_error(void) { return g_err.c_str(); }
+
+int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_stride,
+             const wfs_sensor_desc* sensors, int32_t n_sensors, int32_t batch,
+             double lambda_ref_m, double dt_s, uint32_t flags, wfs_plan_t* out) {
+  g_err.clear();
+  if (!out) return fail(WFS_EINVAL, "wfs_plan: null output handle");
+  *out = nullptr;
+  int rc = validate(layers, n_layers, layer_stride, sensors, n_sensors, batch, lambda_ref_m, dt_s);
+  if (rc) return rc;
+  if ((flags & WFS_FLAG_FORCE_OTF) && (flags & WFS_FLAG_FORCE_FFT))
+    return fail(WFS_EINVAL, "wfs_plan: FORCE_OTF and FORCE_FFT together");
+
+  auto* P = new wfs_plan_s();
+  P->n_layers = n_layers;
+  P->n_sensors = n_sensors;
+  P->batch = batch;
+  P->layer_stride = layer_stride;
+  P->lambda_ref = lambda_ref_m;
+  P->dt = dt_s;
+  P->flags = flags;
+  P->layers.assign(layers, layers + n_layers);
+  P->sensors.assign(sensors, sensors + n_sensors);
+
+  std::vector<DevLayer> dl(n_layers);
+  for (int l = 0; l < n_layers; ++l) {
+    const wfs_layer_desc& L = layers[l];
+    dl[l].offset = L.offset;
+    dl[l].nx = L.nx;
+    dl[l].ny = L.ny;
+    dl[l].weight = L.weight;
+    dl[l].boundary = L.boundary;
+    dl[l].inv_nx = 1.0 / L.nx;
+    dl[l].inv_ny = 1.0 / L.ny;
+  }
+
+  std::vector<DevAffine> aff((size_t)n_sensors * n_layers);
+  std::vector<DevSensor> ds(n_sensors);
+  std::vector<DevSubap> subs;
+  std::vector<uint8_t> masks;
+  std::vector<float2> stab, wtab;
+  std::vector<int> otf_ids, fft_ids;
+  int32_t slope_off = 0, aux_off = 0;
+  int64_t phase_off = 0;
+  int otf_ns = 0;
+  for (int s = 0; s < n_sensors; ++s) {
+    const wfs_sensor_desc& S = sensors[s];
+    SensorGeom g = sensor_geometry(S);
+    DevSensor& d = ds[s];
+    std::memset(&d, 0, sizeof d);
+    d.n_sa = S.n_sa;
+    d.n_sub = S.n_sub;
+    d.n_fft = S.n_fft;
+    d.bin = S.bin;
+    d.n_pix = S.n_fft / S.bin;
+    d.n_pup = g.n_pup;
+    d.n_valid = (int32_t)g.subs.size();
+    d.valid_off = (int32_t)subs.size();
+    d.slope_off = slope_off;
+    d.aux_off = aux_off;
+    d.mask_off = (int32_t)masks.size();
+    d.phase_off = (int32_t)phase_off;
+    d.noisy = S.photons > 0 ? 1 : 0;
+    d.elong = (S.na_fwhm_m > 0 && finite_d(S.src_alt_m)) ? 1 : 0;
+    d.kappa = (float)(lambda_ref_m / S.lambda_m);
+    const double fph = S.photons > 0 ? S.photons : 1.0;
+    d.flux_c = (float)(fph / ((double)S.n_fft * S.n_fft * (double)S.n_sub * S.n_sub));
+    d.read_noise = (float)S.read_noise_e;
+    d.ramp = (float)(0.5 / S.n_fft);
+    if ((int64_t)masks.size() + (int64_t)g.mask.size() > (1LL << 31) - 1) {
+      delete P;
+      return fail(WFS_EINVAL, "wfs_plan: pupil masks too large");
+    }
+    masks.insert(masks.end(), g.mask.begin(), g.mask.end());
+    subs.insert(subs.end(), g.subs.begin(), g.subs.end());
+    slope_off += 2 * d.n_valid;
+    aux_off += d.n_valid;
+    phase_off += (int64_t)d.n_valid * S.n_sub * S.n_sub;
+    P->n_valid.push_back(d.n_valid);
+    P->pix_scale.push_back(S.bin * S.lambda_m / (S.n_fft * g.dx));
+
+    // path choice
+    const bool otf_ok = S.n_sub <= kOtfMaxNsub;
+    const bool fft_ok = !d.elong && fft_supported(S.n_sub, S.n_fft, S.bin);
+    int path;
+    if (flags & WFS_FLAG_FORCE_OTF) path = otf_ok ? kPathOtf : -1;
+    else if (flags & WFS_FLAG_FORCE_FFT) path = fft_ok ? kPathFft : -1;
+    else path = otf_ok ? kPathOtf : (fft_ok ? kPathFft : -1);
+    if (path < 0) {
+      delete P;
+      return fail(WFS_EUNSUPPORTED,
+                  "sensor %d: n_sub=%d n_fft=%d bin=%d elongation=%d has no kernel path", s,
+                  S.n_sub, S.n_fft, S.bin, d.elong);
+    }
+    if (path == kPathOtf) {
+      if (otf_ns && otf_ns != S.n_sub) {
+        delete P;
+        return fail(WFS_EUNSUPPORTED,
+                    "sensor %d: lag-domain sensors of one plan must share n_sub (%d vs %d)", s,
+                    S.n_sub, otf_ns);
+      }
+      otf_ns = S.n_sub;
+      otf_ids.push_back(s);
+      P->otf_max_npix = std::max(P->otf_max_npix, d.n_pix);
+    } else {
+      fft_ids.push_back(s);
+    }
+    d.path = path;
+    // lag-domain tables: s(k) = (-1)^k sum_{d<bin} e^{2 pi i k d / N}, |k| < n_sub, and the
+    // n_pix-point inverse twiddles e^{2 pi i t / n_pix}
+    d.stab_off = (int32_t)stab.size();
+    for (int k = -(S.n_sub - 1); k <= S.n_sub - 1; ++k) {
+      double re = 0, im = 0;
+      for (int q = 0; q < S.bin; ++q) {
+        const double a = 2.0 * M_PI * (double)k * q / S.n_fft;
+        re += std::cos(a);
+        im += std::sin(a);
+      }
+      const double sg = (std::abs(k) % 2) ? -1.0 : 1.0;
+      stab.push_back(make_float2((float)(sg * re), (float)(sg * im)));
+    }
+    d.wtab_off = (int32_t)wtab.size();
+    for (int t = 0; t < d.n_pix; ++t) {
+      const double a = 2.0 * M_PI * t / d.n_pix;
+      wtab.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+    }
+    // cone + frozen-flow affine maps: X = s x + theta h - v t, u = X / pitch + n/2 - 1/2
+    const double H = S.src_alt_m;
+    for (int l = 0; l < n_layers; ++l) {
+      const wfs_layer_desc& L = layers[l];
+      const double sc = finite_d(H) ? 1.0 - L.alt_m / H : 1.0;
+      DevAffine& A = aff[(size_t)s * n_layers + l];
+      const double x0 = (0.5 - g.n_pup / 2.0) * g.dx;
+      A.ax = sc * g.dx / L.pitch_m;
+      A.bx0 = (sc * x0 + S.theta_x_rad * L.alt_m) / L.pitch_m + L.nx / 2.0 - 0.5;
+      A.dbx = -L.vx_mps * dt_s / L.pitch_m;
+      A.ay = sc * g.dx / L.pitch_m;
+      A.by0 = (sc * x0 + S.theta_y_rad * L.alt_m) / L.pitch_m + L.ny / 2.0 - 0.5;
+      A.dby = -L.vy_mps * dt_s / L.pitch_m;
+    }
+  }
+  P->hsen = ds;
+  P->n_slopes = slope_off;
+  P->n_valid_total = aux_off;
+  P->phase_per_real = phase_off;
+  P->otf_ns = otf_ns;
+
+  // tables -> one device blob
+  std::vector<char> blob;
+  const size_t o_lay = push_table(blob, dl);
+  const size_t o_aff = push_table(blob, aff);
+  const size_t o_sen = push_table(blob, ds);
+  const size_t o_sub = push_table(blob, subs);
+  const size_t o_mask = push_table(blob, masks);
+  const size_t o_stab = push_table(blob, stab);
+  const size_t o_wtab = push_table(blob, wtab);
+  std::vector<int64_t> step0(1, 0);
+  const size_t o_step = push_table(blob, step0);
+  blob.resize((blob.size() + 255) & ~size_t(255));
+
+  hipError_t e = hipGetDevice(&P->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&P->d_blob, blob.size());
+  if (e == hipSuccess) e = hipMemcpy(P->d_blob, blob.data(), blob.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    if (P->d_blob) (void)hipFree(P->d_blob);
+    delete P;
+    return hip_fail(e, "wfs_plan: table upload");
+  }
+  FwdParams& b = P->base;
+  std::memset(&b, 0, sizeof b);
+  b.lay = reinterpret_cast<const DevLayer*>(P->d_blob + o_lay);
+  b.aff = reinterpret_cast<const DevAffine*>(P->d_blob + o_aff);
+  b.sen = reinterpret_cast<const DevSensor*>(P->d_blob + o_sen);
+  b.sub = reinterpret_cast<const DevSubap*>(P->d_blob + o_sub);
+  b.mask = reinterpret_cast<const uint8_t*>(P->d_blob + o_mask);
+  b.stab = reinterpret_cast<const float2*>(P->d_blob + o_stab);
+  b.wtab = reinterpret_cast<const float2*>(P->d_blob + o_wtab);
+  P->d_step = reinterpret_cast<int64_t*>(P->d_blob + o_step);
+  b.step_dev = P->d_step;
+  b.layer_stride = layer_stride;
+  b.n_layers = n_layers;
+  b.n_sensors = n_sensors;
+  b.batch = batch;
+  b.n_slopes = P->n_slopes;
+  b.n_valid_total = P->n_valid_total;
+  fill_tasks(b.otf, otf_ids, P->n_valid);
+  fill_tasks(b.fft, fft_ids, P->n_valid);
+  P->otf_tasks = (int64_t)b.otf.per_real * batch;
+  P->fft_tasks = (int64_t)b.fft.per_real * batch;
+  if (P->otf_tasks > (1LL << 31) - 1 || P->fft_tasks > (1LL << 31) - 1) {
+    (void)hipFree(P->d_blob);
+    delete P;
+    return fail(WFS_EINVAL, "wfs_plan: too many subaperture tasks");
+  }
+  // LDS: lag-domain waves and FFT workgroups share one dynamic allocation
+  int lds_wave = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix) : 0;
+  int lds_fft = 0;
+  for (int s : fft_ids)
+    lds_fft = std::max(lds_fft, fft_lds_bytes(sensors[s].n_sub, sensors[s].n_fft,
+                                              sensors[s].n_fft / sensors[s].bin));
+  lds_wave = std::max(lds_wave, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
+  lds_wave = (lds_wave + 15) & ~15;
+  if (lds_wave * kWavesPerBlock > 65536) {
+    (void)hipFree(P->d_blob);
+    delete P;
+    return fail(WFS_EUNSUPPORTED, "wfs_plan: %d bytes of LDS per workgroup exceed 64 KiB",
+                lds_wave * kWavesPerBlock);
+  }
+  b.lds_per_wave = lds_wave;
+  P->adj_lds_per_wave = otf_ns ? ((adj_lds_bytes(otf_ns, n_layers, P->otf_max_npix) + 15) & ~15) : 16;
+  if (P->adj_lds_per_wave * kWavesPerBlock > 65536) P->adj_lds_per_wave = 0;  // adjoint unsupported
+  // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
+  b.fft_blocks = (int32_t)((P->fft_tasks + 7) / 8 * 8);
+  default_schedule(P);
+  *out = P;
+  return WFS_OK;
+}
+
+int wfs_plan_info(wfs_plan_t P, int32_t* n_slopes, int32_t* n_valid_total,
+                  int32_t* n_valid_per_sensor, double* pix_scale_rad) {
+  if (!P) return fail(WFS_EINVAL, "wfs_plan_info: null plan");
+  if (n_slopes) *n_slopes = P->n_slopes;
+  if (n_valid_total) *n_valid_total = P->n_valid_total;
+  for (int s = 0; s < P->n_sensors; ++s) {
+    if (n_valid_per_sensor) n_valid_per_sensor[s] = P->n_valid[s];
+    if (pix_scale_rad) pix_scale_rad[s] = P->pix_scale[s];
+  }
+  return WFS_OK;
+}
+
+int wfs_plan_path(wfs_plan_t P, int32_t* path_per_sensor) {
+  if (!P || !path_per_sensor) return fail(WFS_EINVAL, "wfs_plan_path: null argument");
+  for (int s = 0; s < P->n_sensors; ++s) path_per_sensor[s] = P->hsen[s].path;
+  return WFS_OK;
+}
+
+int wfs_plan_destroy(wfs_plan_t P) {
+  if (!P) return fail(WFS_EINVAL, "wfs_plan_destroy: null plan");
+  hipError_t e = hipDeviceSynchronize();
+  if (P->d_blob) (void)hipFree(P->d_blob);
+  delete P;
+  if (e != hipSuccess) return hip_fail(e, "wfs_plan_destroy");
+  return WFS_OK;
+}
+
+static int check_device(wfs_plan_t P, const char* who) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, who);
+  if (dev != P->device)
+    return fail(WFS_EINVAL, "%s: current device %d is not the plan's device %d", who, dev,
+                P->device);
+  return WFS_OK;
+}
+
+static int check_step(int64_t step, const char* who) {
+  if (step < 0 && step != WFS_STEP_DEVICE)
+    return fail(WFS_EINVAL, "%s: step=%lld (>= 0 or WFS_STEP_DEVICE)", who, (long long)step);
+  return WFS_OK;
+}
+
+static FwdParams call_params(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed,
+                             float* slopes, float* aux) {
+  FwdParams p = P->base;
+  p.layers = layers;
+  p.step = step < 0 ? 0 : step;
+  p.use_dev_step = step == WFS_STEP_DEVICE ? 1 : 0;
+  p.seed_lo = (uint32_t)(seed & 0xFFFFFFFFu);
+  p.seed_hi = (uint32_t)(seed >> 32);
+  p.noise_on = 1;
+  p.slopes = slopes;
+  p.aux = aux;
+  return p;
+}
+
+int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, float* slopes,
+                float* aux, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_forward: null plan");
+  if (!layers || !slopes) return fail(WFS_EINVAL, "wfs_forward: null layers or slopes");
+  int rc = check_step(step, "wfs_forward");
+  if (rc) return rc;
+  rc = check_device(P, "wfs_forward");
+  if (rc) return rc;
+  FwdParams p = call_params(P, layers, step, seed, slopes, aux);
+  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "wfs_forward: launch");
+  return WFS_OK;
+}
+
+int wfs_project(wfs_plan_t P, const float* layers, int64_t step, float* phase, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_project: null plan");
+  if (!layers || !phase) return fail(WFS_EINVAL, "wfs_project: null layers or phase");
+  int rc = check_step(step, "wfs_project");
+  if (rc) return rc;
+  rc = check_device(P, "wfs_project");
+  if (rc) return rc;
+  FwdParams p = call_params(P, layers, step, 0, nullptr, nullptr);
+  hipError_t e = launch_project(p, phase, P->phase_per_real, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "wfs_project: launch");
+  return WFS_OK;
+}
+
+int wfs_set_step(wfs_plan_t P, int64_t step, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_set_step: null plan");
+  if (step < 0) return fail(WFS_EINVAL, "wfs_set_step: step=%lld < 0", (long long)step);
+  int rc = check_device(P, "wfs_set_step");
+  if (rc) return rc;
+  hipError_t e = launch_step(P->d_step, step, 0, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "wfs_set_step: launch");
+  return WFS_OK;
+}
+
+int wfs_advance_step(wfs_plan_t P, int64_t delta, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_advance_step: null plan");
+  int rc = check_device(P, "wfs_advance_step");
+  if (rc) return rc;
+  hipError_t e = launch_step(P->d_step, delta, 1, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "wfs_advance_step: launch");
+  return WFS_OK;
+}
+
+int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
+                const float* fwd_slopes, const float* fwd_aux, int64_t step, float* grad_layers,
+                void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_adjoint: null plan");
+  if (!layers || !grad_slopes || !grad_layers)
+    return fail(WFS_EINVAL, "wfs_adjoint: null layers, grad_slopes or grad_layers");
+  if ((fwd_slopes == nullptr) != (fwd_aux == nullptr))
+    return fail(WFS_EINVAL, "wfs_adjoint: give both fwd_slopes and fwd_aux, or neither");
+  int rc = check_step(step, "wfs_adjoint");
+  if (rc) return rc;
+  rc = check_device(P, "wfs_adjoint");
+  if (rc) return rc;
+  if (P->fft_tasks > 0)
+    return fail(WFS_EUNSUPPORTED, "wfs_adjoint: sensors on the FFT path have no adjoint kernel");
+  if (P->adj_lds_per_wave == 0)
+    return fail(WFS_EUNSUPPORTED, "wfs_adjoint: lag-domain adjoint needs more than 64 KiB of LDS");
+  AdjParams a;
+  a.f = call_params(P, layers, step, 0, nullptr, nullptr);
+  a.f.noise_on = 0;
+  a.grad_slopes = grad_slopes;
+  a.fwd_slopes = fwd_slopes;
+  a.fwd_aux = fwd_aux;
+  a.grad_layers = grad_layers;
+  a.f.lds_per_wave = P->adj_lds_per_wave;
+  hipError_t e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: launch");
+  return WFS_OK;
+}
+
+int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best_us,
+                  void* stream) {
+  if (!P || !layers) return fail(WFS_EINVAL, "wfs_plan_tune: null argument");
+  if (iters < 1 || iters > 10000) return fail(WFS_EINVAL, "wfs_plan_tune: iters=%d", iters);
+  int rc = check_device(P, "wfs_plan_tune");
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  float *slopes = nullptr, *aux = nullptr;
+  HIP_TRY(hipMalloc((void**)&slopes, sizeof(float) * (size_t)std::max(1, P->n_slopes) * P->batch),
+          "wfs_plan_tune: scratch");
+  hipError_t e = hipMalloc((void**)&aux, sizeof(float) * (size_t)std::max(1, P->n_valid_total) * P->batch);
+  if (e != hipSuccess) {
+    (void)hipFree(slopes);
+    return hip_fail(e, "wfs_plan_tune: scratch");
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const FwdParams keep = P->base;
+  FwdParams best = keep;
+  double best_t = 1e30;
+  const int spws[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+  for (int remap = 0; remap < 2; ++remap) {
+    for (int spw : spws) {
+      const int64_t waves = (P->otf_tasks + spw - 1) / spw;
+      if (spw > 1 && waves < 256) break;
+      FwdParams c = keep;
+      c.subaps_per_wave = spw;
+      c.otf_blocks = (int32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+      c.xcd_remap = remap;
+      P->base = c;
+      FwdParams p = call_params(P, layers, 0, 1, slopes, aux);
+      e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);  // warm-up
+      if (e != hipSuccess) break;
+      (void)hipEventRecord(e0, st);
+      for (int it = 0; it < iters; ++it) e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double us = 1000.0 * ms / iters;
+      if (e == hipSuccess && us < best_t) {
+        best_t = us;
+        best = c;
+      }
+      if (P->otf_tasks == 0) break;
+    }
+    if (e != hipSuccess) break;
+  }
+  P->base = best;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(slopes);
+  (void)hipFree(aux);
+  if (e != hipSuccess) {
+    P->base = keep;
+    return hip_fail(e, "wfs_plan_tune: launch");
+  }
+  if (best_us) *best_us = best_t;
+  return WFS_OK;
+}
+
+int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B, float* C,
+                int64_t ldc, float alpha, float beta, void* stream) {
+  if (!R || !S || !C) return fail(WFS_EINVAL, "recon_apply: null R, S or C");
+  if (M < 1 || N < 1 || B < 1)
+    return fail(WFS_EINVAL, "recon_apply: M=%d N=%d B=%d must be >= 1", M, N, B);
+  if (ldc < M) return fail(WFS_EINVAL, "recon_apply: ldc=%lld < M=%d", (long long)ldc, M);
+  if ((int64_t)M * N > (1LL << 40)) return fail(WFS_EINVAL, "recon_apply: R too large");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(WFS_EINVAL, "recon_apply: non-finite alpha or beta");
+  int mfma = 0;
+  hipError_t e = recon_launch(R, M, N, S, B, C, ldc, alpha, beta, (hipStream_t)stream, &mfma);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply");
+  return WFS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal device tables and kernel parameter blocks of libwfs (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wfs {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per workgroup of every sensor kernel
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxLayers = 64;
+constexpr int kMaxSensors = 64;
+constexpr int kOtfMaxNsub = 12;    // lag-domain path: subapertures up to 12 x 12 pixels
+constexpr int kFftMaxNsub = 64;    // FFT path: fields up to 64 x 64 pixels
+constexpr int kFftMaxN = 128;      // FFT path: transforms up to 128 points per axis
+
+enum Path : int32_t { kPathOtf = 0, kPathFft = 1 };
+
+struct DevLayer {
+  int64_t offset;
+  int32_t nx, ny;
+  float weight;
+  int32_t boundary;  // 0 periodic, 1 zero outside
+  double inv_nx, inv_ny;
+};
+
+// Continuous layer coordinates of pupil pixel (column i, row j) of sensor s seen through
+// layer l at time step k:  u = ax*i + bx0 + k*dbx,  v = ay*j + by0 + k*dby.
+struct DevAffine {
+  double ax, bx0, dbx;
+  double ay, by0, dby;
+};
+
+struct DevSensor {
+  int32_t n_sa, n_sub, n_fft, bin;
+  int32_t n_pix, n_pup, n_valid, valid_off;  // valid_off: first row of the subap table
+  int32_t slope_off, aux_off, mask_off, path;
+  int32_t noisy, elong, phase_off, pad0;     // phase_off: offset in wfs_project output
+  float kappa;       // lambda_ref / lambda
+  float flux_c;      // F_ph / (n_fft^2 n_sub^2)
+  float read_noise;  // electrons rms
+  float ramp;        // 1 / (2 n_fft): half-pixel centring ramp, turns per pixel index
+  int32_t stab_off;  // first entry of this sensor's lag-phase table s(k), k = -(n_sub-1)..
+  int32_t wtab_off;  // first entry of this sensor's n_pix-point twiddle table
+  int32_t pad1, pad2;
+};
+
+struct DevSubap {
+  int32_t a, b;   // subaperture row and column
+  float alpha;    // 2 pi^2 sigma_px^2 / n_fft^2 (0: no elongation)
+  float ex, ey;   // unit elongation direction
+  int32_t v;      // index among the sensor's valid subapertures
+  int32_t pad0, pad1;
+};
+
+// Flat list of sensors served by one launch (one lag-domain template instance plus the FFT
+// path); task t of realisation b is subaperture (t - start[k]) of sensor ids[k].
+struct TaskTable {
+  int32_t n;                  // sensors in the list
+  int32_t per_real;           // tasks per realisation
+  int32_t ids[kMaxSensors];
+  int32_t start[kMaxSensors + 1];
+};
+
+struct FwdParams {
+  const float* layers;
+  int64_t layer_stride;
+  const DevLayer* lay;
+  const DevAffine* aff;  // [n_sensors][n_layers]
+  const DevSensor* sen;
+  const DevSubap* sub;
+  const uint8_t* mask;
+  const float2* stab;
+  const float2* wtab;
+  const int64_t* step_dev;  // read when use_dev_step
+  int64_t step;
+  int32_t use_dev_step;
+  int32_t n_layers;
+  int32_t n_sensors;
+  int32_t batch;
+  uint32_t seed_lo, seed_hi;
+  int32_t noise_on;         // 0 in the adjoint's recompute
+  float* slopes;
+  int32_t n_slopes;
+  float* aux;
+  int32_t n_valid_total;
+  // schedule
+  int32_t otf_blocks;       // blocks serving the lag-domain tasks
+  int32_t fft_blocks;       // blocks serving FFT tasks (one subaperture each), launched first
+  int32_t subaps_per_wave;  // lag-domain tasks per wave (contiguous)
+  int32_t xcd_remap;
+  int32_t lds_per_wave;     // bytes
+  int32_t pad;
+  TaskTable otf;
+  TaskTable fft;
+};
+
+struct AdjParams {
+  FwdParams f;              // forward tables (noise off)
+  const float* grad_slopes; // [B][n_slopes]
+  const float* fwd_slopes;  // or null
+  const float* fwd_aux;     // or null
+  float* grad_layers;       // [B][layer_stride]
+};
+
+}  // namespace wfs

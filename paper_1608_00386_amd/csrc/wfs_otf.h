@@ -1,0 +1,296 @@
+// Lag-domain ("OTF") path of the Shack-Hartmann spot model: device functions shared by the
+// forward and adjoint kernels.  One 64-lane wavefront handles one subaperture at a time.
+//
+// The paper's sensor turns the residual phase into X/Y slopes
+// (Sec. 2.7); our reading forms the spot as |DFT_N(E)|^2 of the zero-padded subaperture field,
+// convolves it with the sodium-profile kernel, shifts, bins and takes the centre of gravity.
+// Because the field has n_sub x n_sub support and N >= 2 n_sub, the DFT of the spot is
+// exactly c N^2 times the field's autocorrelation A[k] = sum_m E[m] conj(E[m+k]) on the
+// (2 n_sub - 1)^2 lags, and binning after the fftshift is, in the Fourier domain, a
+// multiplication by s(kx) s(ky) (s(k) = (-1)^k sum_{d<b} e^{2 pi i k d / N}) followed by
+// folding the lags modulo n_pix.  So the binned image is
+//     B[q] = c Re sum_{K} P[K] e^{2 pi i K.q / n_pix},
+//     P[K] = sum_{k = K mod n_pix, half plane} w_k A[k] Kel[k] s(kx) s(ky),
+// (w = 1 on the ky = 0 row, 2 above it, using A[-k] = conj A[k]) which needs n_sub^2 complex
+// multiply-adds per row pair instead of two N x N transforms, and no N x N array at all.
+// The result equals the FFT definition up to rounding; the FP64 oracle checks it.
+#pragma once
+
+#include "wfs_common.h"
+
+namespace wfs {
+
+// ------------------------------------------------------------------------------------------
+// Lag-domain path
+// ------------------------------------------------------------------------------------------
+
+template <int NS>
+struct Otf {
+  static constexpr int kJobs = NS * (NS + 1) / 2;  // row pairs (dy, r), dy >= 0
+  static constexpr int kLags = 2 * NS - 1;         // dx = -(NS-1) .. NS-1
+};
+
+// Per-wave LDS layout (bytes), shared with the host sizing code.
+struct OtfLds {
+  int e_off, taps_off, part_off, p_off, z_off, b_off, total;
+};
+
+__host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix) {
+  OtfLds o;
+  const int jobs = ns * (ns + 1) / 2, lags = 2 * ns - 1, np2 = n_pix * n_pix;
+  o.e_off = 0;
+  const int u0 = ((ns * ns * 8) + 15) & ~15;
+  const int taps = 2 * ns * n_layers * 16;
+  const int part = jobs * lags * 8;
+  o.taps_off = u0;
+  o.part_off = u0;
+  o.p_off = u0 + part;
+  o.z_off = o.p_off + np2 * 8;
+  o.b_off = o.z_off + np2 * 8;
+  int end = o.b_off + np2 * 4;
+  if (u0 + taps > end) end = u0 + taps;
+  o.total = (end + 15) & ~15;
+  return o;
+}
+
+template <int NS>
+__device__ __forceinline__ void job_of(int j, int& dy, int& r) {
+  int d = 0;
+  while (j >= NS - d) {
+    j -= NS - d;
+    ++d;
+  }
+  dy = d;
+  r = j;
+}
+
+template <int NS>
+__device__ __forceinline__ int job_base(int dy) {
+  return dy * NS - (dy * (dy - 1)) / 2;
+}
+
+// Fills the wave's E region with the subaperture field E[r][c] = A exp(i(psi - pi (r+c)/N)).
+// Uses the taps region as scratch.  Returns after a wave_sync.
+template <int NS>
+__device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S,
+                                          const DevSubap& sb, int sid, int b, double stepd,
+                                          char* wsm, const OtfLds& lo) {
+  const int lane = lane_id();
+  const int nl = p.n_layers;
+  Tap* taps = reinterpret_cast<Tap*>(wsm + lo.taps_off);  // [nl][2*NS]: cols then rows
+  for (int t = lane; t < 2 * NS * nl; t += kWave) {
+    const int l = t / (2 * NS), k = t - l * (2 * NS);
+    taps[t] = (k < NS) ? col_tap(p, sid, l, sb.b * NS + k, stepd)
+                       : row_tap(p, sid, l, sb.a * NS + (k - NS), stepd);
+  }
+  wave_sync();
+  const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
+  float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
+  for (int q = lane; q < NS * NS; q += kWave) {
+    const int r = q / NS, c = q - r * NS;
+    const int ir = sb.a * NS + r, ic = sb.b * NS + c;
+    float psi = 0.0f;
+    for (int l = 0; l < nl; ++l) {
+      const DevLayer& L = p.lay[l];
+      const Tap cx = taps[l * 2 * NS + c];
+      const Tap ry = taps[l * 2 * NS + NS + r];
+      psi = fmaf(L.weight, bilinear(lay_b + L.offset, cx, ry), psi);
+    }
+    const uint8_t amp = p.mask[S.mask_off + ir * S.n_pup + ic];
+    // phase in turns, reduced to [-1/2, 1/2] before the sincos
+    float turns = fmaf(psi, S.kappa * 0.15915494309189535f, -(float)(r + c) * S.ramp);
+    turns -= rintf(turns);
+    float sn, cs;
+    sincospif(2.0f * turns, &sn, &cs);
+    E[q] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+  }
+  wave_sync();
+}
+
+// Autocorrelation row-pair jobs -> partial lag rows in LDS.
+template <int NS>
+__device__ __forceinline__ void otf_autocorr(char* wsm, const OtfLds& lo) {
+  const int lane = lane_id();
+  const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
+  float2* part = reinterpret_cast<float2*>(wsm + lo.part_off);
+  for (int j = lane; j < Otf<NS>::kJobs; j += kWave) {
+    int dy, r;
+    job_of<NS>(j, dy, r);
+    float2 e1[NS], e2[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) {
+      e1[c] = E[r * NS + c];
+      e2[c] = E[(r + dy) * NS + c];
+    }
+    float2 acc[Otf<NS>::kLags];
+#pragma unroll
+    for (int k = 0; k < Otf<NS>::kLags; ++k) acc[k] = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int c1 = 0; c1 < NS; ++c1) {
+#pragma unroll
+      for (int c2 = 0; c2 < NS; ++c2) {
+        // E[r][c1] conj(E[r+dy][c2]) -> lag dx = c2 - c1
+        float2& a = acc[c2 - c1 + NS - 1];
+        a.x = fmaf(e1[c1].x, e2[c2].x, fmaf(e1[c1].y, e2[c2].y, a.x));
+        a.y = fmaf(e1[c1].y, e2[c2].x, fmaf(-e1[c1].x, e2[c2].y, a.y));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Otf<NS>::kLags; ++k) part[j * Otf<NS>::kLags + k] = acc[k];
+  }
+  wave_sync();
+}
+
+// Lag sums, elongation, binning phases and the fold modulo n_pix: P[K], lane per K.
+template <int NS>
+__device__ __forceinline__ void otf_fold(const FwdParams& p, const DevSensor& S,
+                                         const DevSubap& sb, char* wsm, const OtfLds& lo) {
+  const int lane = lane_id();
+  const int np = S.n_pix, np2 = np * np;
+  const float2* part = reinterpret_cast<const float2*>(wsm + lo.part_off);
+  float2* P = reinterpret_cast<float2*>(wsm + lo.p_off);
+  const float2* stab = p.stab + S.stab_off;  // s(k), k = -(NS-1) .. NS-1
+  for (int K = lane; K < np2; K += kWave) {
+    const int Ky = K / np, Kx = K - Ky * np;
+    float2 acc = make_float2(0.0f, 0.0f);
+    for (int dy = Ky; dy < NS; dy += np) {
+      const float wgt = dy == 0 ? 1.0f : 2.0f;
+      const int base = job_base<NS>(dy);
+      const float2 sy = stab[dy + NS - 1];
+      int dx = Kx - np * ((Kx + NS - 1) / np);
+      for (; dx < NS; dx += np) {
+        float2 a = make_float2(0.0f, 0.0f);
+        for (int r = 0; r < NS - dy; ++r) {
+          const float2 v = part[(base + r) * Otf<NS>::kLags + dx + NS - 1];
+          a.x += v.x;
+          a.y += v.y;
+        }
+        const float2 sx = stab[dx + NS - 1];
+        // t = s(dx) s(dy) Kel(dx, dy) wgt
+        const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
+        const float kel = __expf(-sb.alpha * proj * proj) * wgt;
+        const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
+        const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
+        acc.x = fmaf(a.x, tr, fmaf(-a.y, ti, acc.x));
+        acc.y = fmaf(a.x, ti, fmaf(a.y, tr, acc.y));
+      }
+    }
+    P[K] = acc;
+  }
+  wave_sync();
+}
+
+// B[q] = c Re sum_K P[K] W^{K.q}, separable through Z[Ky][qx] (W = e^{2 pi i / n_pix}).
+__device__ __forceinline__ void otf_image(const FwdParams& p, const DevSensor& S, char* wsm,
+                                          const OtfLds& lo) {
+  const int lane = lane_id();
+  const int np = S.n_pix, np2 = np * np;
+  const float2* P = reinterpret_cast<const float2*>(wsm + lo.p_off);
+  float2* Z = reinterpret_cast<float2*>(wsm + lo.z_off);
+  float* B = reinterpret_cast<float*>(wsm + lo.b_off);
+  const float2* wt = p.wtab + S.wtab_off;
+  for (int t = lane; t < np2; t += kWave) {
+    const int Ky = t / np, qx = t - Ky * np;
+    float2 z = make_float2(0.0f, 0.0f);
+    int idx = 0;
+    for (int Kx = 0; Kx < np; ++Kx) {
+      const float2 a = P[Ky * np + Kx];
+      const float2 w = wt[idx];
+      z.x = fmaf(a.x, w.x, fmaf(-a.y, w.y, z.x));
+      z.y = fmaf(a.x, w.y, fmaf(a.y, w.x, z.y));
+      idx += qx;
+      if (idx >= np) idx -= np;
+    }
+    Z[t] = z;
+  }
+  wave_sync();
+  for (int t = lane; t < np2; t += kWave) {
+    const int qy = t / np, qx = t - qy * np;
+    float v = 0.0f;
+    int idx = 0;
+    for (int Ky = 0; Ky < np; ++Ky) {
+      const float2 z = Z[Ky * np + qx];
+      const float2 w = wt[idx];
+      v = fmaf(z.x, w.x, fmaf(-z.y, w.y, v));
+      idx += qy;
+      if (idx >= np) idx -= np;
+    }
+    B[t] = S.flux_c * v;
+  }
+  wave_sync();
+}
+
+// Noise and centre-of-gravity sums over the binned image (sum B', sum x B', sum y B'),
+// pixels in pairs (one Philox block per pair); every lane returns the wave totals.
+struct Cog {
+  float s0, sx, sy;
+};
+
+__device__ __forceinline__ Cog cog_sums(const FwdParams& p, const DevSensor& S, int sid, int b,
+                                        int v, int64_t step, const float* B) {
+  const int lane = lane_id();
+  const int np = S.n_pix, np2 = np * np, npairs = (np2 + 1) >> 1;
+  const float half = 0.5f * (float)(np - 1);
+  float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
+  const bool noisy = S.noisy && p.noise_on;
+  for (int pr = lane; pr < npairs; pr += kWave) {
+    const int q0 = 2 * pr, q1 = 2 * pr + 1;
+    float b0 = B[q0];
+    float b1 = q1 < np2 ? B[q1] : 0.0f;
+    if (noisy) {
+      const uint4 ctr = make_uint4((uint32_t)pr, (uint32_t)v,
+                                   ((uint32_t)b << 8) | (uint32_t)sid, (uint32_t)step);
+      const uint4 w = philox4x32_10(ctr, p.seed_lo, p.seed_hi);
+      add_noise_pair(b0, b1, w, S.read_noise);
+      if (q1 >= np2) b1 = 0.0f;
+    }
+    const int y0 = q0 / np, x0 = q0 - y0 * np;
+    const int y1 = q1 / np, x1 = q1 - y1 * np;
+    s0 += b0 + b1;
+    sx = fmaf((float)x0 - half, b0, fmaf((float)x1 - half, b1, sx));
+    sy = fmaf((float)y0 - half, b0, fmaf((float)y1 - half, b1, sy));
+  }
+  Cog c;
+  c.s0 = wave_sum(s0);
+  c.sx = wave_sum(sx);
+  c.sy = wave_sum(sy);
+  return c;
+}
+
+// Slopes (0 when the flux is not positive) and the flux of subaperture v.
+__device__ __forceinline__ void write_slopes(const FwdParams& p, const DevSensor& S, int b,
+                                             int v, const Cog& c) {
+  if (lane_id() == 0) {
+    const bool ok = c.s0 > 0.0f;
+    float* out = p.slopes + (int64_t)b * p.n_slopes + S.slope_off;
+    out[v] = ok ? c.sx / c.s0 : 0.0f;
+    out[S.n_valid + v] = ok ? c.sy / c.s0 : 0.0f;
+    if (p.aux) p.aux[(int64_t)b * p.n_valid_total + S.aux_off + v] = c.s0;
+  }
+}
+
+// Binned noise-free (or noisy) image of one subaperture into the wave's B region.
+template <int NS>
+__device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
+                                         const DevSubap& sb, int sid, int b, int64_t step,
+                                         char* wsm, const OtfLds& lo) {
+  otf_field<NS>(p, S, sb, sid, b, (double)step, wsm, lo);
+  otf_autocorr<NS>(wsm, lo);
+  otf_fold<NS>(p, S, sb, wsm, lo);
+  otf_image(p, S, wsm, lo);
+}
+
+template <int NS>
+__device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm) {
+  int b, sid, v;
+  task_of(p.otf, t, b, sid, v);
+  const DevSensor S = p.sen[sid];
+  const DevSubap sb = p.sub[S.valid_off + v];
+  const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix);
+  otf_spot<NS>(p, S, sb, sid, b, step, wsm, lo);
+  const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));
+  write_slopes(p, S, b, v, c);
+  wave_sync();
+}
+
+}  // namespace wfs

@@ -1,0 +1,199 @@
+"""Python front end of libwfs: plans, the forward sensor model, its adjoint (autograd) and the
+reconstructor.  Argument marshalling only: every step runs in the HIP kernels of libwfs.so.
+
+PyTorch provides device memory and streams.  Tensors must be float32, contiguous and on the
+plan's GPU.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, name, shape=None, numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+class Plan:
+    """A set of Shack-Hartmann sensors looking through a set of layers (``wfs_plan``).
+
+    ``cfg`` is a dict with ``layers`` and ``sensors`` (the fields of wfs_layer_desc and
+    wfs_sensor_desc), ``layer_stride``, ``batch``, ``lambda_ref_m`` and ``dt_s``.
+    """
+
+    def __init__(self, cfg, flags=0, batch=None):
+        self._lib = L.lib()
+        self.cfg = cfg
+        self.batch = int(batch if batch is not None else cfg.get("batch", 1))
+        self.layer_stride = int(cfg["layer_stride"])
+        nl, ns = len(cfg["layers"]), len(cfg["sensors"])
+        self._ld = (L.LayerDesc * nl)(*[L.layer_desc(x) for x in cfg["layers"]])
+        self._sd = (L.SensorDesc * ns)(*[L.sensor_desc(x) for x in cfg["sensors"]])
+        h = ctypes.c_void_p()
+        L.check(self._lib.wfs_plan(self._ld, nl, self.layer_stride, self._sd, ns, self.batch,
+                                   float(cfg["lambda_ref_m"]), float(cfg["dt_s"]), int(flags),
+                                   ctypes.byref(h)), "wfs_plan")
+        self._h = h
+        n_slopes, n_valid_total = ctypes.c_int32(), ctypes.c_int32()
+        nv = (ctypes.c_int32 * ns)()
+        ps = (ctypes.c_double * ns)()
+        L.check(self._lib.wfs_plan_info(h, ctypes.byref(n_slopes), ctypes.byref(n_valid_total),
+                                        nv, ps), "wfs_plan_info")
+        self.n_slopes = n_slopes.value
+        self.n_valid_total = n_valid_total.value
+        self.n_valid = list(nv)
+        self.pix_scale = list(ps)
+        paths = (ctypes.c_int32 * ns)()
+        L.check(self._lib.wfs_plan_path(h, paths), "wfs_plan_path")
+        self.paths = list(paths)
+        self.device = torch.cuda.current_device()
+
+    # -- lifetime -------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.check(self._lib.wfs_plan_destroy(self._h), "wfs_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls ----------------------------------------------------------------------------
+    def _layers(self, layers):
+        _need(layers, "layers", numel=self.batch * self.layer_stride)
+
+    def forward(self, layers, step=0, seed=42, slopes=None, aux=None, stream=None):
+        """Slopes [B][n_slopes] (and per-subaperture flux [B][n_valid_total])."""
+        self._layers(layers)
+        if slopes is None:
+            slopes = torch.empty(self.batch, self.n_slopes, device=layers.device)
+        if aux is None:
+            aux = torch.empty(self.batch, self.n_valid_total, device=layers.device)
+        _need(slopes, "slopes", numel=self.batch * self.n_slopes)
+        _need(aux, "aux", numel=self.batch * self.n_valid_total)
+        L.check(self._lib.wfs_forward(self._h, _ptr(layers), int(step), int(seed), _ptr(slopes),
+                                      _ptr(aux), _stream(stream)), "wfs_forward")
+        return slopes, aux
+
+    def project(self, layers, step=0, out=None, stream=None):
+        self._layers(layers)
+        n = sum(nv * s["n_sub"] ** 2 for nv, s in zip(self.n_valid, self.cfg["sensors"]))
+        if out is None:
+            out = torch.empty(self.batch, n, device=layers.device)
+        _need(out, "phase", numel=self.batch * n)
+        L.check(self._lib.wfs_project(self._h, _ptr(layers), int(step), _ptr(out),
+                                      _stream(stream)), "wfs_project")
+        return out
+
+    def adjoint(self, layers, grad_slopes, step=0, fwd_slopes=None, fwd_aux=None, out=None,
+                stream=None):
+        self._layers(layers)
+        _need(grad_slopes, "grad_slopes", numel=self.batch * self.n_slopes)
+        if (fwd_slopes is None) != (fwd_aux is None):
+            raise ValueError("give both fwd_slopes and fwd_aux, or neither")
+        if fwd_slopes is not None:
+            _need(fwd_slopes, "fwd_slopes", numel=self.batch * self.n_slopes)
+            _need(fwd_aux, "fwd_aux", numel=self.batch * self.n_valid_total)
+        if out is None:
+            out = torch.empty_like(layers)
+        _need(out, "grad_layers", numel=self.batch * self.layer_stride)
+        L.check(self._lib.wfs_adjoint(self._h, _ptr(layers), _ptr(grad_slopes),
+                                      _ptr(fwd_slopes), _ptr(fwd_aux), int(step), _ptr(out),
+                                      _stream(stream)), "wfs_adjoint")
+        return out
+
+    def set_step(self, step, stream=None):
+        L.check(self._lib.wfs_set_step(self._h, int(step), _stream(stream)), "wfs_set_step")
+
+    def advance_step(self, delta=1, stream=None):
+        L.check(self._lib.wfs_advance_step(self._h, int(delta), _stream(stream)),
+                "wfs_advance_step")
+
+    def tune(self, layers, iters=20, stream=None):
+        """Time the launch schedules on ``layers`` and keep the fastest; returns its us/call."""
+        self._layers(layers)
+        best = ctypes.c_double()
+        L.check(self._lib.wfs_plan_tune(self._h, _ptr(layers), int(iters), ctypes.byref(best),
+                                        _stream(stream)), "wfs_plan_tune")
+        return best.value
+
+
+def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None):
+    """C[b] = alpha R S[b] + beta C[b]; R [M][N], S [B][N]; C [B][ldc] (default ldc = M)."""
+    _need(R, "R")
+    _need(S, "S")
+    if R.dim() != 2 or S.dim() != 2 or S.shape[1] != R.shape[1]:
+        raise ValueError(f"R {tuple(R.shape)} and S {tuple(S.shape)} do not match")
+    M, N = R.shape
+    B = S.shape[0]
+    if C is None:
+        C = torch.zeros(B, M, device=R.device)
+        ldc = M
+    _need(C, "C")
+    if ldc is None:
+        ldc = C.shape[-1]
+    if C.numel() < (B - 1) * ldc + M:
+        raise ValueError("C is too small for B rows of stride ldc")
+    L.check(L.lib().recon_apply(_ptr(R), int(M), int(N), _ptr(S), int(B), _ptr(C), int(ldc),
+                                float(alpha), float(beta), _stream(stream)), "recon_apply")
+    return C
+
+
+class WFSFunction(torch.autograd.Function):
+    """slopes = WFS(layers); backward runs wfs_adjoint (the noise-free model's adjoint, with the
+    subaperture fields recomputed from the layers)."""
+
+    @staticmethod
+    def forward(ctx, layers, plan, step, seed):
+        slopes, aux = plan.forward(layers, step=step, seed=seed)
+        ctx.plan = plan
+        ctx.step = step
+        noisy = any(s["photons"] > 0 for s in plan.cfg["sensors"])
+        ctx.save_for_backward(layers, slopes, aux)
+        ctx.noisy = noisy
+        return slopes
+
+    @staticmethod
+    def backward(ctx, grad_slopes):
+        layers, slopes, aux = ctx.saved_tensors
+        g = grad_slopes.contiguous()
+        if ctx.noisy:  # the forward outputs carry noise: recompute the noise-free ones
+            out = ctx.plan.adjoint(layers, g, step=ctx.step)
+        else:
+            out = ctx.plan.adjoint(layers, g, step=ctx.step, fwd_slopes=slopes, fwd_aux=aux)
+        return out, None, None, None
+
+
+def wfs_slopes(layers, plan, step=0, seed=42):
+    """Differentiable slopes of ``plan`` for ``layers`` ([B][layer_stride] float32)."""
+    return WFSFunction.apply(layers, plan, step, seed)

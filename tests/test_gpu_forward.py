@@ -1,0 +1,123 @@
+"""GPU parity of wfs_forward / wfs_project against the FP64 oracle (same float32 inputs)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from wfs_cases import CASES, layers_for, slope_tolerance
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    import paper_1608_00386_amd as W
+    return torch, W
+
+
+def _run(cfg, x, step, seed=42, flags=0):
+    torch, W = _gpu()
+    plan = W.Plan(cfg, flags=flags, batch=x.shape[0])
+    xt = torch.from_numpy(x).cuda()
+    s, a = plan.forward(xt, step=step, seed=seed)
+    torch.cuda.synchronize()
+    return s.cpu().numpy().astype(np.float64), a.cpu().numpy().astype(np.float64), plan, xt
+
+
+def _check(cfg, x, s_gpu, a_gpu, step, seed=42):
+    s_ref, a_ref = oracle.forward(x.astype(np.float64), cfg, step, seed, noise=True)
+    tol = slope_tolerance(cfg)
+    err = np.abs(s_gpu - s_ref)
+    worst = float((err / tol[None, :]).max())
+    assert worst <= 1.0, f"slope error {worst:.3g} x tolerance (max abs {err.max():.3g})"
+    np.testing.assert_allclose(a_gpu, a_ref, rtol=2e-5, atol=1e-4 * np.abs(a_ref).max())
+    return worst
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("step", [0, 7])
+def test_forward_matches_oracle(name, step):
+    cfg = CASES[name]()
+    x = layers_for(cfg)
+    s, a, plan, _ = _run(cfg, x, step)
+    assert s.shape == (cfg["batch"], oracle.n_slopes(cfg))
+    _check(cfg, x, s, a, step)
+
+
+def test_forward_is_bitwise_deterministic():
+    cfg = CASES["lgs_n10_N32_b4_noise"]()
+    x = layers_for(cfg)
+    torch, W = _gpu()
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    s1, a1 = plan.forward(xt, step=3, seed=9)
+    s1, a1 = s1.clone(), a1.clone()
+    s2, a2 = plan.forward(xt, step=3, seed=9)
+    assert torch.equal(s1, s2) and torch.equal(a1, a2)
+    s3, _ = plan.forward(xt, step=3, seed=10)
+    assert not torch.equal(s1, s3)  # the seed reaches the noise
+
+
+def test_flat_screens_give_zero_slopes_on_gpu():
+    for name in ("cfg0", "lgs_n10_N32_b4_noise", "ngs_n6_N12_b4_oddpix"):
+        cfg = CASES[name]()
+        for s in cfg["sensors"]:
+            s["photons"] = 0.0
+        x = np.zeros((cfg["batch"], cfg["layer_stride"]), np.float32)
+        s, a, _, _ = _run(cfg, x, 0)
+        assert np.abs(s).max() < 2e-6, name
+
+
+def test_device_step_counter_matches_host_step():
+    torch, W = _gpu()
+    cfg = CASES["lgs_n4_N8_b2"]()
+    x = layers_for(cfg)
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    ref, _ = plan.forward(xt, step=5, seed=3)
+    ref = ref.clone()
+    plan.set_step(3)
+    plan.advance_step(2)
+    got, _ = plan.forward(xt, step=W.WFS_STEP_DEVICE, seed=3)
+    assert torch.equal(ref, got)
+
+
+def test_project_matches_oracle():
+    torch, W = _gpu()
+    cfg = CASES["dm_two_ngs_batch2"]()
+    x = layers_for(cfg)
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    ph = plan.project(xt, step=11).cpu().numpy().astype(np.float64)
+    o = 0
+    for si, sensor in enumerate(cfg["sensors"]):
+        geo = oracle.pupil_geometry(sensor)
+        n = sensor["n_sub"]
+        for bi in range(cfg["batch"]):
+            psi = oracle.project(x[bi].astype(np.float64), cfg, sensor, 11)
+            ref = np.stack([psi[a * n:(a + 1) * n, b * n:(b + 1) * n].ravel()
+                            for a, b in geo["valid"]]).ravel()
+            got = ph[bi, o:o + ref.size]
+            np.testing.assert_allclose(got, ref, atol=2e-5 * max(1.0, np.abs(ref).max()))
+        o += len(geo["valid"]) * n * n
+
+
+@pytest.mark.parametrize("step", [0, 61])
+def test_config1_full_frame_matches_oracle(step):
+    """E-ELT 80x80 LGS (config 1), every one of the 4,632 subapertures, noise on."""
+    cfg = synth.config1()
+    x = synth.make_batch(cfg, [0])
+    s, a, plan, _ = _run(cfg, x, step)
+    assert plan.n_slopes == 9264
+    worst = _check(cfg, x, s, a, step)
+    print(f"config1 step {step}: worst slope error {worst:.3g} of tolerance")
+
+
+def test_config0_paper_sampling_counts():
+    torch, W = _gpu()
+    plan = W.Plan(synth.config0())
+    assert plan.n_valid == [52] and plan.n_slopes == 104
+    plan1 = W.Plan(synth.config1())
+    assert plan1.n_valid == [4632]
+    np.testing.assert_allclose(plan1.pix_scale[0], oracle.pixel_scale(synth.config1()["sensors"][0]))

@@ -1,0 +1,139 @@
+"""GPU parity of recon_apply and wfs_adjoint against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from wfs_cases import CASES, layers_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    import paper_1608_00386_amd as W
+    return torch, W
+
+
+def _recon_check(R, S, C0, alpha, beta, got, rows=None, rel=2e-5):
+    rows = np.arange(R.shape[0]) if rows is None else rows
+    R64 = R[rows].astype(np.float64)
+    S64 = S.astype(np.float64)
+    ref = alpha * (S64 @ R64.T) + beta * C0[:, rows].astype(np.float64)
+    scale = np.abs(alpha) * (np.abs(S64) @ np.abs(R64).T) + np.abs(beta * C0[:, rows]) + 1e-30
+    err = np.abs(got[:, rows] - ref) / scale
+    assert err.max() <= rel, f"recon error {err.max():.3g} of sum |R s|"
+
+
+@pytest.mark.parametrize("M,N,B", [(37, 101, 1), (37, 101, 3), (70, 256, 1), (70, 256, 2),
+                                   (70, 256, 8), (45, 1000, 17), (300, 4096, 8)])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.4, 1.0)])
+def test_recon_small(M, N, B, alpha, beta):
+    torch, W = _gpu()
+    rng = np.random.default_rng(M * 1000 + N + B)
+    R = rng.standard_normal((M, N)).astype(np.float32)
+    S = rng.standard_normal((B, N)).astype(np.float32)
+    ldc = M + 5
+    C0 = rng.standard_normal((B, ldc)).astype(np.float32)
+    Ct = torch.from_numpy(C0.copy()).cuda()
+    W.recon_apply(torch.from_numpy(R).cuda(), torch.from_numpy(S).cuda(), Ct, alpha=alpha,
+                  beta=beta, ldc=ldc)
+    got = Ct.cpu().numpy().astype(np.float64)
+    _recon_check(R, S, C0[:, :M], alpha, beta, got[:, :M])
+    np.testing.assert_array_equal(got[:, M:], C0[:, M:])  # padding untouched
+
+
+def test_recon_integer_exact():
+    torch, W = _gpu()
+    rng = np.random.default_rng(3)
+    R = rng.integers(-3, 4, size=(50, 400)).astype(np.float32)
+    S = rng.integers(-3, 4, size=(4, 400)).astype(np.float32)
+    C = W.recon_apply(torch.from_numpy(R).cuda(), torch.from_numpy(S).cuda())
+    np.testing.assert_array_equal(C.cpu().numpy(), (S.astype(np.int64) @ R.T.astype(np.int64)))
+
+
+@pytest.mark.parametrize("B", [1, 8])
+def test_recon_full_size_sampled_rows(B):
+    """5,400 x 55,608 reconstructor (entries N(0,1)/sqrt(N)), sampled rows against FP64."""
+    torch, W = _gpu()
+    M, N = 5400, 55608
+    R = synth.make_reconstructor(M, N)
+    S = synth.random_field((B, N), seed=11)
+    Rt = torch.from_numpy(R).cuda()
+    St = torch.from_numpy(S).cuda()
+    C = W.recon_apply(Rt, St)
+    C2 = W.recon_apply(Rt, St)
+    assert torch.equal(C, C2)  # deterministic
+    rows = np.random.default_rng(0).choice(M, 64, replace=False)
+    rows = np.concatenate([rows, [0, M - 1]])
+    got = C.cpu().numpy().astype(np.float64)
+    _recon_check(R, S, np.zeros((B, M), np.float32), 1.0, 0.0, got, rows=rows, rel=1e-4)
+
+
+def _adjoint_case(name, seed=1):
+    cfg = CASES[name]()
+    for s in cfg["sensors"]:
+        s["photons"] = 0.0
+        s["read_noise_e"] = 0.0
+    x = layers_for(cfg, scale=0.5)
+    g = synth.random_field((cfg["batch"], oracle.n_slopes(cfg)), seed=seed)
+    return cfg, x, g
+
+
+@pytest.mark.parametrize("name", ["lgs_n4_N8_b2", "lgs_n10_N32_b4_noise",
+                                  "lgs_n5_N10_b2_2sens_batch3", "dm_two_ngs_batch2", "cfg0",
+                                  "ngs_n6_N12_b4_oddpix"])
+@pytest.mark.parametrize("saved", [False, True])
+def test_adjoint_matches_oracle(name, saved):
+    torch, W = _gpu()
+    cfg, x, g = _adjoint_case(name)
+    step = 4
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    gt = torch.from_numpy(g).cuda()
+    if saved:
+        s, a = plan.forward(xt, step=step)
+        out = plan.adjoint(xt, gt, step=step, fwd_slopes=s, fwd_aux=a)
+    else:
+        out = plan.adjoint(xt, gt, step=step)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.adjoint(x.astype(np.float64), cfg, step, g.astype(np.float64))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-4, rel
+    assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max()
+
+
+def test_autograd_function_uses_the_adjoint():
+    torch, W = _gpu()
+    cfg, x, _ = _adjoint_case("lgs_n5_N10_b2_2sens_batch3")
+    plan = W.Plan(cfg)
+    target = torch.zeros(cfg["batch"], plan.n_slopes, device="cuda")
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    s = W.wfs_slopes(xt, plan, step=2)
+    loss = ((s - target) ** 2).sum()
+    loss.backward()
+    s_ref = oracle.forward(x.astype(np.float64), cfg, 2, noise=False)[0]
+    ref = oracle.adjoint(x.astype(np.float64), cfg, 2, 2.0 * s_ref)
+    got = xt.grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+def test_adjoint_dot_product_with_gpu_forward():
+    """<J v, g> from a central difference of the GPU forward equals <v, J^T g> from the GPU
+    adjoint (to the accuracy of an FP32 difference quotient)."""
+    torch, W = _gpu()
+    cfg, x, g = _adjoint_case("lgs_n10_N32_b4_noise")
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    gt = torch.from_numpy(g).cuda()
+    adj = plan.adjoint(xt, gt, step=1).double()
+    v = torch.from_numpy(synth.random_field(x.shape, seed=5)).cuda()
+    h = 1e-2
+    sp, _ = plan.forward(xt + h * v, step=1)
+    sp = sp.double().clone()
+    sm, _ = plan.forward(xt - h * v, step=1)
+    jv = (sp - sm.double()) / (2 * h)
+    lhs = float((jv * gt.double()).sum())
+    rhs = float((adj * v.double()).sum())
+    assert abs(lhs - rhs) <= 2e-3 * max(abs(lhs), abs(rhs)), (lhs, rhs)
