@@ -28,7 +28,14 @@ template <int NS>
 struct Otf {
   static constexpr int kJobs = NS * (NS + 1) / 2;  // row pairs (dy, r), dy >= 0
   static constexpr int kLags = 2 * NS - 1;         // dx = -(NS-1) .. NS-1
+  static constexpr int kRounds = (kJobs + kWave - 1) / kWave;
+  static constexpr int kJobsPerRound = (kJobs + kRounds - 1) / kRounds;
 };
+
+__host__ __device__ constexpr int otf_jobs_per_round(int ns) {
+  return (ns * (ns + 1) / 2 + ((ns * (ns + 1) / 2 + kWave - 1) / kWave) - 1) /
+         ((ns * (ns + 1) / 2 + kWave - 1) / kWave);
+}
 
 // Per-wave LDS layout (bytes), shared with the host sizing code.
 struct OtfLds {
@@ -37,7 +44,7 @@ struct OtfLds {
 
 __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix) {
   OtfLds o;
-  const int jobs = ns * (ns + 1) / 2, lags = 2 * ns - 1, np2 = n_pix * n_pix;
+  const int jobs = otf_jobs_per_round(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
   const int u0 = ((ns * ns * 8) + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
@@ -107,13 +114,14 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
   wave_sync();
 }
 
-// Autocorrelation row-pair jobs -> partial lag rows in LDS.
+// Autocorrelation row-pair jobs [j0, j0 + jobs per round) -> partial lag rows in LDS.
 template <int NS>
-__device__ __forceinline__ void otf_autocorr(char* wsm, const OtfLds& lo) {
+__device__ __forceinline__ void otf_autocorr(char* wsm, const OtfLds& lo, int j0) {
   const int lane = lane_id();
   const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
   float2* part = reinterpret_cast<float2*>(wsm + lo.part_off);
-  for (int j = lane; j < Otf<NS>::kJobs; j += kWave) {
+  const int j = j0 + lane;
+  if (lane < Otf<NS>::kJobsPerRound && j < Otf<NS>::kJobs) {
     int dy, r;
     job_of<NS>(j, dy, r);
     float2 e1[NS], e2[NS];
@@ -136,32 +144,37 @@ __device__ __forceinline__ void otf_autocorr(char* wsm, const OtfLds& lo) {
       }
     }
 #pragma unroll
-    for (int k = 0; k < Otf<NS>::kLags; ++k) part[j * Otf<NS>::kLags + k] = acc[k];
+    for (int k = 0; k < Otf<NS>::kLags; ++k) part[lane * Otf<NS>::kLags + k] = acc[k];
   }
   wave_sync();
 }
 
-// Lag sums, elongation, binning phases and the fold modulo n_pix: P[K], lane per K.
+// Lag sums of one round of jobs, elongation, binning phases and the fold modulo n_pix,
+// accumulated into P[K] (lane per K; the first round initialises P).
 template <int NS>
 __device__ __forceinline__ void otf_fold(const FwdParams& p, const DevSensor& S,
-                                         const DevSubap& sb, char* wsm, const OtfLds& lo) {
+                                         const DevSubap& sb, char* wsm, const OtfLds& lo,
+                                         int j0) {
   const int lane = lane_id();
   const int np = S.n_pix, np2 = np * np;
   const float2* part = reinterpret_cast<const float2*>(wsm + lo.part_off);
   float2* P = reinterpret_cast<float2*>(wsm + lo.p_off);
   const float2* stab = p.stab + S.stab_off;  // s(k), k = -(NS-1) .. NS-1
+  const int j1 = j0 + Otf<NS>::kJobsPerRound;
   for (int K = lane; K < np2; K += kWave) {
     const int Ky = K / np, Kx = K - Ky * np;
-    float2 acc = make_float2(0.0f, 0.0f);
+    float2 acc = j0 == 0 ? make_float2(0.0f, 0.0f) : P[K];
     for (int dy = Ky; dy < NS; dy += np) {
-      const float wgt = dy == 0 ? 1.0f : 2.0f;
       const int base = job_base<NS>(dy);
+      const int r0 = max(0, j0 - base), r1 = min(NS - dy, j1 - base);
+      if (r0 >= r1) continue;
+      const float wgt = dy == 0 ? 1.0f : 2.0f;
       const float2 sy = stab[dy + NS - 1];
       int dx = Kx - np * ((Kx + NS - 1) / np);
       for (; dx < NS; dx += np) {
         float2 a = make_float2(0.0f, 0.0f);
-        for (int r = 0; r < NS - dy; ++r) {
-          const float2 v = part[(base + r) * Otf<NS>::kLags + dx + NS - 1];
+        for (int r = r0; r < r1; ++r) {
+          const float2 v = part[(base + r - j0) * Otf<NS>::kLags + dx + NS - 1];
           a.x += v.x;
           a.y += v.y;
         }
@@ -275,8 +288,11 @@ __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
                                          const DevSubap& sb, int sid, int b, int64_t step,
                                          char* wsm, const OtfLds& lo) {
   otf_field<NS>(p, S, sb, sid, b, (double)step, wsm, lo);
-  otf_autocorr<NS>(wsm, lo);
-  otf_fold<NS>(p, S, sb, wsm, lo);
+#pragma unroll
+  for (int rd = 0; rd < Otf<NS>::kRounds; ++rd) {
+    otf_autocorr<NS>(wsm, lo, rd * Otf<NS>::kJobsPerRound);
+    otf_fold<NS>(p, S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
+  }
   otf_image(p, S, wsm, lo);
 }
 
