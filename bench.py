@@ -117,11 +117,11 @@ def eager_kernel_ms(torch, fn, n):
 # workloads
 # ------------------------------------------------------------------------------------------
 
-def bench_config1(torch, W, steps, warmup, k0=0):
+def bench_config1(torch, W, steps, warmup, k0=0, tune=True, flags=0):
     cfg = synth.config1()
     x = torch.from_numpy(synth.make_batch(cfg, [0])).cuda()
-    plan = W.Plan(cfg)
-    tuned_us = plan.tune(x, iters=10)
+    plan = W.Plan(cfg, flags=flags)
+    tuned_us = plan.tune(x, iters=10) if tune else None
     slopes, aux = plan.forward(x, step=0)
 
     def frame(i):
@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only (no extras, no CPU)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=8)
+    ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule")
+    ap.add_argument("--fused", action="store_true", help="projection fused into the spot kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the "
@@ -207,7 +209,8 @@ def main():
     torch.cuda.set_device(0)
 
     log("[bench] config1 forward ...")
-    r1 = bench_config1(torch, W, args.steps, args.warmup)
+    r1 = bench_config1(torch, W, args.steps, args.warmup, tune=not args.no_tune,
+                       flags=W.WFS_FLAG_FUSED if args.fused else 0)
     cfg1 = r1["cfg"]
     subaps = r1["plan"].n_valid[0]
     frames_per_s = args.steps / r1["wall"]

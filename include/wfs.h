@@ -49,6 +49,8 @@ enum {
 #define WFS_FLAG_FORCE_OTF (1u << 0)    /* every sensor on the lag-domain (autocorrelation) path */
 #define WFS_FLAG_FORCE_FFT (1u << 1)    /* every sensor on the FFT path (needs no elongation)     */
 #define WFS_FLAG_NO_XCD_REMAP (1u << 2) /* keep the hardware block order (no per-XCD grouping)    */
+#define WFS_FLAG_FUSED (1u << 3)        /* project inside the spot kernel (no projection pass and
+                                           no phase buffer); default: projection kernel first  */
 
 /* `step` value meaning "read the step from the plan's device-resident counter". */
 #define WFS_STEP_DEVICE (-1)

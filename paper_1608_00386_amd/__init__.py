@@ -3,6 +3,7 @@ centroids, reconstructor) as hand-written HIP kernels behind the C ABI of includ
 
 from ._lib import (  # noqa: F401
     WFS_FLAG_FORCE_FFT,
+    WFS_FLAG_FUSED,
     WFS_FLAG_FORCE_OTF,
     WFS_FLAG_NO_XCD_REMAP,
     WFS_STEP_DEVICE,

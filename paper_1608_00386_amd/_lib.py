@@ -17,6 +17,7 @@ WFS_EUNSUPPORTED = -4
 WFS_FLAG_FORCE_OTF = 1 << 0
 WFS_FLAG_FORCE_FFT = 1 << 1
 WFS_FLAG_NO_XCD_REMAP = 1 << 2
+WFS_FLAG_FUSED = 1 << 3
 WFS_STEP_DEVICE = -1
 
 

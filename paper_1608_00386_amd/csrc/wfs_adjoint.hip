@@ -39,9 +39,10 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   const FwdParams& p = ap.f;
   const int lane = lane_id();
   int b, sid, v;
+  t = __builtin_amdgcn_readfirstlane(t);
   task_of(p.otf, t, b, sid, v);
-  const DevSensor S = p.sen[sid];
-  const DevSubap sb = p.sub[S.valid_off + v];
+  const DevSensor S = cload(p.sen, sid);
+  const DevSubap sb = cload(p.sub, S.valid_off + v);
   const int np = S.n_pix, np2 = np * np;
   const OtfLds lo = otf_lds_layout(NS, p.n_layers, np);
   const AdjLds la = adj_lds_layout(NS, p.n_layers, np);
@@ -67,15 +68,15 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   const float inv = 1.0f / s0;
   float* gB = reinterpret_cast<float*>(wsm + la.gb_off);
   for (int q = lane; q < np2; q += kWave) {
-    const int qy = q / np, qx = q - qy * np;
+    const int qy = fdiv(q, np, S.inv_npix), qx = q - qy * np;
     gB[q] = (gx * ((float)qx - half - cx) + gy * ((float)qy - half - cy)) * inv;
   }
   wave_sync();
   // ghat[Ky][Kx] = sum_q gB[q] W^{Kx qx + Ky qy}, separable (W = e^{2 pi i / n_pix})
-  const float2* wt = p.wtab + S.wtab_off;
+  const float2* wt = reinterpret_cast<const float2*>(wsm + lo.wtab_off);
   float2* GZ = reinterpret_cast<float2*>(wsm + la.gz_off);  // [qy][Kx]
   for (int t2 = lane; t2 < np2; t2 += kWave) {
-    const int qy = t2 / np, Kx = t2 - qy * np;
+    const int qy = fdiv(t2, np, S.inv_npix), Kx = t2 - qy * np;
     float2 z = make_float2(0.0f, 0.0f);
     int idx = 0;
     for (int qx = 0; qx < np; ++qx) {
@@ -91,7 +92,7 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   wave_sync();
   float2* GH = reinterpret_cast<float2*>(wsm + la.gh_off);  // [Ky][Kx]
   for (int t2 = lane; t2 < np2; t2 += kWave) {
-    const int Ky = t2 / np, Kx = t2 - Ky * np;
+    const int Ky = fdiv(t2, np, S.inv_npix), Kx = t2 - Ky * np;
     float2 h = make_float2(0.0f, 0.0f);
     int idx = 0;
     for (int qy = 0; qy < np; ++qy) {
@@ -108,11 +109,14 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   // U[k] = c Kel(k) s(kx) s(ky) ghat[k mod n_pix] on all (2 NS - 1)^2 lags
   constexpr int NL = 2 * NS - 1;
   float2* U = reinterpret_cast<float2*>(wsm + la.u_off);
-  const float2* stab = p.stab + S.stab_off;
+  const float2* stab = reinterpret_cast<const float2*>(wsm + lo.stab_off);
   for (int t2 = lane; t2 < NL * NL; t2 += kWave) {
     const int iy = t2 / NL, ix = t2 - iy * NL;
     const int dy = iy - (NS - 1), dx = ix - (NS - 1);
-    const int Ky = ((dy % np) + np) % np, Kx = ((dx % np) + np) % np;
+    // lags -> bins modulo n_pix (|lag| < NS, so one shift by a multiple of n_pix is enough)
+    const int dyp = dy + np * NS, dxp = dx + np * NS;
+    const int Ky = dyp - np * fdiv(dyp, np, S.inv_npix);
+    const int Kx = dxp - np * fdiv(dxp, np, S.inv_npix);
     const float2 g = GH[Ky * np + Kx];
     const float2 sx = stab[ix], sy = stab[iy];
     const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);

@@ -23,6 +23,20 @@ __device__ __forceinline__ int xcd_logical_block(int i, int n) {
   return x * q + (x < r ? x : r) + (i >> 3);
 }
 
+// Read-only tables are read through the constant address space so that wave-uniform
+// indices become scalar (SMEM) loads.
+template <class T>
+__device__ __forceinline__ T cload(const T* p, int64_t i) {
+  static_assert(sizeof(T) % 4 == 0, "table rows are whole 32-bit words");
+  typedef const __attribute__((address_space(4))) uint32_t* wptr;
+  const wptr src = (wptr)(p + i);
+  T out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = src[k];
+  return out;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -38,11 +52,28 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;  // one 32x32->64 multiply each
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0);
   }
   return c;
+}
+
+// sin(2 pi x) and cos(2 pi x) for x in revolutions (|x| small): the hardware transcendental
+// unit (v_sin_f32 / v_cos_f32) takes its argument in revolutions.
+__device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(x);
+  *c = __builtin_amdgcn_cosf(x);
+}
+
+// floor(q / d) for 0 <= q < 2^22, d >= 1, given inv_d = 1/d rounded: the float quotient is off
+// by at most one, fixed by one compare.
+__device__ __forceinline__ int fdiv(int q, int d, float inv_d) {
+  int r = (int)((float)q * inv_d);
+  const int m = r * d;
+  r += (m > q) ? -1 : ((m + d <= q) ? 1 : 0);
+  return r;
 }
 
 // Uniform in (0,1) from the top 24 bits of a word: ((w >> 8) + 1/2) 2^-24 (exact in fp32).
@@ -53,11 +84,12 @@ __device__ __forceinline__ float u24(uint32_t w) {
 // Gaussian photon + read noise of two pixels from one Philox block (Box-Muller pairs
 // (u0,u1) and (u2,u3)): b' = b + sqrt(max(b,0)) z1 + ro z2.
 __device__ __forceinline__ void add_noise_pair(float& b0, float& b1, uint4 w, float ro) {
-  const float ra = sqrtf(-2.0f * logf(u24(w.x)));
-  const float rb = sqrtf(-2.0f * logf(u24(w.z)));
+  // -2 ln u = -2 ln2 log2 u ; angles 2 pi u in revolutions
+  const float ra = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u24(w.x)));
+  const float rb = sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u24(w.z)));
   float s0, c0, s1, c1;
-  sincospif(2.0f * u24(w.y), &s0, &c0);
-  sincospif(2.0f * u24(w.w), &s1, &c1);
+  sincos_rev(u24(w.y), &s0, &c0);
+  sincos_rev(u24(w.w), &s1, &c1);
   b0 += sqrtf(fmaxf(b0, 0.0f)) * (ra * c0) + ro * (ra * s0);
   b1 += sqrtf(fmaxf(b1, 0.0f)) * (rb * c1) + ro * (rb * s1);
 }
@@ -101,17 +133,23 @@ __device__ __forceinline__ Tap make_tap(double c, int32_t n, double inv_n, int32
 }
 
 __device__ __forceinline__ Tap col_tap(const FwdParams& p, int s, int l, int ic, double step) {
-  const DevLayer& L = p.lay[l];
-  const DevAffine& A = p.aff[s * p.n_layers + l];
+  const DevLayer L = p.lay[l];
+  const DevAffine A = p.aff[s * p.n_layers + l];
   const double u = fma(A.ax, (double)ic, A.bx0) + step * A.dbx;
   return make_tap(u, L.nx, L.inv_nx, L.boundary, 1);
 }
 
 __device__ __forceinline__ Tap row_tap(const FwdParams& p, int s, int l, int ir, double step) {
-  const DevLayer& L = p.lay[l];
-  const DevAffine& A = p.aff[s * p.n_layers + l];
+  const DevLayer L = p.lay[l];
+  const DevAffine A = p.aff[s * p.n_layers + l];
   const double v = fma(A.ay, (double)ir, A.by0) + step * A.dby;
   return make_tap(v, L.ny, L.inv_ny, L.boundary, L.nx);
+}
+
+// Load base[idx] with a wave-uniform base and a 32-bit element index: lets the compiler use
+// the scalar-base + 32-bit-offset addressing mode instead of per-lane 64-bit addresses.
+__device__ __forceinline__ float ld_idx(const float* base, uint32_t idx) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (idx << 2));
 }
 
 __device__ __forceinline__ float bilinear(const float* __restrict__ g, const Tap& cx,

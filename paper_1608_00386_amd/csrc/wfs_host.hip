@@ -17,7 +17,8 @@
 
 namespace wfs {
 hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st);
-hipError_t launch_project(const FwdParams& p, float* phase, int64_t per_real, hipStream_t st);
+hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
+int project_lds_bytes(int n_sub, int n_layers, int group, int rows);
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
@@ -75,6 +76,11 @@ struct wfs_plan_s {
   int otf_max_npix = 0;
   int64_t otf_tasks = 0, fft_tasks = 0;
   int adj_lds_per_wave = 0;
+  int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
+  int proj_lds_fft = 0;      // same, FFT-path sensors only
+  TaskTable proj_all{}, proj_fft{};
+  float* d_phase = nullptr;  // split-mode phase buffer [B][phase_per_real]
+  int split = 0;             // 1: projection kernel + spot kernel; 0: fused gather
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
@@ -283,6 +289,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     d.n_fft = S.n_fft;
     d.bin = S.bin;
     d.n_pix = S.n_fft / S.bin;
+    d.inv_npix = 1.0f / (float)d.n_pix;
     d.n_pup = g.n_pup;
     d.n_valid = (int32_t)g.subs.size();
     d.valid_off = (int32_t)subs.size();
@@ -297,6 +304,18 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     d.flux_c = (float)(fph / ((double)S.n_fft * S.n_fft * (double)S.n_sub * S.n_sub));
     d.read_noise = (float)S.read_noise_e;
     d.ramp = (float)(0.5 / S.n_fft);
+    {
+      // projection block: ~512 pixels (two per thread): whole subapertures in groups, or
+      // chunks of rows of one large subaperture; taps within ~32 KiB of LDS
+      const int n2 = S.n_sub * S.n_sub;
+      int G = std::max(1, 512 / n2);
+      const int per_sub = n_layers * 2 * S.n_sub * 16;
+      G = std::max(1, std::min(G, 32768 / per_sub));
+      int R = S.n_sub;
+      if (n2 > 512) R = std::max(1, 512 / S.n_sub);
+      d.proj_group = G;
+      d.proj_rows = R;
+    }
     if ((int64_t)masks.size() + (int64_t)g.mask.size() > (1LL << 31) - 1) {
       delete P;
       return fail(WFS_EINVAL, "wfs_plan: pupil masks too large");
@@ -416,6 +435,23 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.n_valid_total = P->n_valid_total;
   fill_tasks(b.otf, otf_ids, P->n_valid);
   fill_tasks(b.fft, fft_ids, P->n_valid);
+  {
+    std::vector<int> all_ids(n_sensors);
+    std::vector<int32_t> groups(n_sensors);
+    for (int s = 0; s < n_sensors; ++s) {
+      all_ids[s] = s;
+      const int chunks = (ds[s].n_sub + ds[s].proj_rows - 1) / ds[s].proj_rows;
+      groups[s] = (ds[s].n_valid + ds[s].proj_group - 1) / ds[s].proj_group * chunks;
+      const int lb = project_lds_bytes(ds[s].n_sub, n_layers, ds[s].proj_group, ds[s].proj_rows);
+      P->proj_lds = std::max(P->proj_lds, lb);
+      if (ds[s].path == kPathFft) P->proj_lds_fft = std::max(P->proj_lds_fft, lb);
+    }
+    fill_tasks(P->proj_all, all_ids, groups);
+    fill_tasks(P->proj_fft, fft_ids, groups);
+    b.proj = P->proj_all;
+  }
+  b.phase_per_real = P->phase_per_real;
+  b.phase_in = nullptr;
   P->otf_tasks = (int64_t)b.otf.per_real * batch;
   P->fft_tasks = (int64_t)b.fft.per_real * batch;
   if (P->otf_tasks > (1LL << 31) - 1 || P->fft_tasks > (1LL << 31) - 1) {
@@ -443,6 +479,22 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
   b.fft_blocks = (int32_t)((P->fft_tasks + 7) / 8 * 8);
   default_schedule(P);
+  if (P->phase_per_real > 0) {
+    e = hipMalloc((void**)&P->d_phase, sizeof(float) * (size_t)P->phase_per_real * batch);
+    if (e != hipSuccess) {
+      (void)hipFree(P->d_blob);
+      delete P;
+      return hip_fail(e, "wfs_plan: phase buffer");
+    }
+  }
+  P->split = (flags & WFS_FLAG_FUSED) ? 0 : 1;
+  if (P->proj_lds > 65536) P->split = 0;  // taps of one subaperture exceed the LDS budget
+  if (P->proj_lds_fft > 65536) {
+    (void)hipFree(P->d_blob);
+    if (P->d_phase) (void)hipFree(P->d_phase);
+    delete P;
+    return fail(WFS_EUNSUPPORTED, "wfs_plan: projection taps of an FFT-path sensor exceed 64 KiB");
+  }
   *out = P;
   return WFS_OK;
 }
@@ -469,6 +521,7 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_destroy: null plan");
   hipError_t e = hipDeviceSynchronize();
   if (P->d_blob) (void)hipFree(P->d_blob);
+  if (P->d_phase) (void)hipFree(P->d_phase);
   delete P;
   if (e != hipSuccess) return hip_fail(e, "wfs_plan_destroy");
   return WFS_OK;
@@ -504,6 +557,19 @@ static FwdParams call_params(wfs_plan_t P, const float* layers, int64_t step, ui
   return p;
 }
 
+// fused: one launch; split: projection into the plan's phase buffer, then the spot launch
+static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
+  const bool split = P->split && P->d_phase;
+  if (split || P->fft_tasks > 0) {  // FFT-path sensors always read the projected phase
+    p.proj = split ? P->proj_all : P->proj_fft;
+    hipError_t e = launch_project(p, P->d_phase, split ? P->proj_lds : P->proj_lds_fft, st);
+    if (e != hipSuccess) return e;
+    p.phase_in = P->d_phase;
+  }
+  p.otf_from_phase = split ? 1 : 0;
+  return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+}
+
 int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, float* slopes,
                 float* aux, void* stream) {
   if (!P) return fail(WFS_EINVAL, "wfs_forward: null plan");
@@ -513,7 +579,7 @@ int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, 
   rc = check_device(P, "wfs_forward");
   if (rc) return rc;
   FwdParams p = call_params(P, layers, step, seed, slopes, aux);
-  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  hipError_t e = launch_fwd_modes(P, p, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_forward: launch");
   return WFS_OK;
 }
@@ -525,8 +591,12 @@ int wfs_project(wfs_plan_t P, const float* layers, int64_t step, float* phase, v
   if (rc) return rc;
   rc = check_device(P, "wfs_project");
   if (rc) return rc;
+  if (P->proj_lds > 65536)
+    return fail(WFS_EUNSUPPORTED, "wfs_project: %d bytes of LDS per block exceed 64 KiB",
+                P->proj_lds);
   FwdParams p = call_params(P, layers, step, 0, nullptr, nullptr);
-  hipError_t e = launch_project(p, phase, P->phase_per_real, (hipStream_t)stream);
+  p.proj = P->proj_all;
+  hipError_t e = launch_project(p, phase, P->proj_lds, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_project: launch");
   return WFS_OK;
 }
@@ -601,7 +671,13 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   FwdParams best = keep;
   double best_t = 1e30;
   const int spws[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
-  for (int remap = 0; remap < 2; ++remap) {
+  const int keep_split = P->split;
+  int best_split = keep_split;
+  for (int mode = 0; mode < 4; ++mode) {
+    const int remap = mode & 1;
+    P->split = (mode >> 1) & 1;
+    if (P->split && (!P->d_phase || P->proj_lds > 65536)) continue;
+    if (P->flags & WFS_FLAG_FUSED) P->split = 0;
     for (int spw : spws) {
       const int64_t waves = (P->otf_tasks + spw - 1) / spw;
       if (spw > 1 && waves < 256) break;
@@ -611,10 +687,10 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
       c.xcd_remap = remap;
       P->base = c;
       FwdParams p = call_params(P, layers, 0, 1, slopes, aux);
-      e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);  // warm-up
+      e = launch_fwd_modes(P, p, st);  // warm-up
       if (e != hipSuccess) break;
       (void)hipEventRecord(e0, st);
-      for (int it = 0; it < iters; ++it) e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+      for (int it = 0; it < iters; ++it) e = launch_fwd_modes(P, p, st);
       (void)hipEventRecord(e1, st);
       (void)hipEventSynchronize(e1);
       float ms = 0;
@@ -623,18 +699,21 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
       if (e == hipSuccess && us < best_t) {
         best_t = us;
         best = c;
+        best_split = P->split;
       }
       if (P->otf_tasks == 0) break;
     }
     if (e != hipSuccess) break;
   }
   P->base = best;
+  P->split = best_split;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(slopes);
   (void)hipFree(aux);
   if (e != hipSuccess) {
     P->base = keep;
+    P->split = keep_split;
     return hip_fail(e, "wfs_plan_tune: launch");
   }
   if (best_us) *best_us = best_t;

@@ -36,14 +36,16 @@ struct DevSensor {
   int32_t n_sa, n_sub, n_fft, bin;
   int32_t n_pix, n_pup, n_valid, valid_off;  // valid_off: first row of the subap table
   int32_t slope_off, aux_off, mask_off, path;
-  int32_t noisy, elong, phase_off, pad0;     // phase_off: offset in wfs_project output
+  int32_t noisy, elong, phase_off, proj_group;  // phase_off: offset in the phase buffer;
+                                                // proj_group: subapertures per projection block
   float kappa;       // lambda_ref / lambda
   float flux_c;      // F_ph / (n_fft^2 n_sub^2)
   float read_noise;  // electrons rms
   float ramp;        // 1 / (2 n_fft): half-pixel centring ramp, turns per pixel index
   int32_t stab_off;  // first entry of this sensor's lag-phase table s(k), k = -(n_sub-1)..
   int32_t wtab_off;  // first entry of this sensor's n_pix-point twiddle table
-  int32_t pad1, pad2;
+  float inv_npix;    // 1 / n_pix
+  int32_t proj_rows; // subaperture rows per projection block (n_sub unless split in chunks)
 };
 
 struct DevSubap {
@@ -91,9 +93,12 @@ struct FwdParams {
   int32_t subaps_per_wave;  // lag-domain tasks per wave (contiguous)
   int32_t xcd_remap;
   int32_t lds_per_wave;     // bytes
-  int32_t pad;
+  int32_t otf_from_phase;   // lag-domain path reads phase_in (split mode) instead of gathering
   TaskTable otf;
   TaskTable fft;
+  TaskTable proj;            // projection blocks: groups of proj_group subapertures per sensor
+  const float* phase_in;     // split mode: phase of every valid pixel (kappa applied), or null
+  int64_t phase_per_real;    // floats per realisation in the phase buffer
 };
 
 struct AdjParams {

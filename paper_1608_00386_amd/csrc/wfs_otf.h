@@ -37,16 +37,22 @@ __host__ __device__ constexpr int otf_jobs_per_round(int ns) {
          ((ns * (ns + 1) / 2 + kWave - 1) / kWave);
 }
 
-// Per-wave LDS layout (bytes), shared with the host sizing code.
+// Per-wave LDS layout (bytes), shared with the host sizing code:
+//   E [n_sub^2] float2 | tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2 |
+//   AW [n_sub][2 n_sub - 1] float2 (weighted lag sums) |
+//   union( taps [n_layers][2 n_sub] Tap ,  partial lag rows (one round) + P + Z + B )
 struct OtfLds {
-  int e_off, taps_off, part_off, p_off, z_off, b_off, total;
+  int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off, total;
 };
 
 __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix) {
   OtfLds o;
   const int jobs = otf_jobs_per_round(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
-  const int u0 = ((ns * ns * 8) + 15) & ~15;
+  o.stab_off = ns * ns * 8;
+  o.wtab_off = o.stab_off + lags * 8;
+  o.aw_off = o.wtab_off + n_pix * 8;
+  const int u0 = (o.aw_off + ns * lags * 8 + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
   const int part = jobs * lags * 8;
   o.taps_off = u0;
@@ -76,40 +82,135 @@ __device__ __forceinline__ int job_base(int dy) {
   return dy * NS - (dy * (dy - 1)) / 2;
 }
 
-// Fills the wave's E region with the subaperture field E[r][c] = A exp(i(psi - pi (r+c)/N)).
-// Uses the taps region as scratch.  Returns after a wave_sync.
+// Tap of a given layer for the lanes of one half-wave: the layer parameters are wave-uniform
+// (scalar loads), two layers per pass (lanes 0-31 and 32-63).
+__device__ __forceinline__ Tap tap_of(const DevLayer& L, const DevAffine& A, bool row, int idx,
+                                      double stepd) {
+  if (!row) {
+    const double u = fma(A.ax, (double)idx, A.bx0) + stepd * A.dbx;
+    return make_tap(u, L.nx, L.inv_nx, L.boundary, 1);
+  }
+  const double v = fma(A.ay, (double)idx, A.by0) + stepd * A.dby;
+  return make_tap(v, L.ny, L.inv_ny, L.boundary, L.nx);
+}
+
+// Fills the wave's E region with the subaperture field E[r][c] = A exp(i(psi - pi (r+c)/N)),
+// and the wave's copies of the sensor's lag-phase and twiddle tables.  All per-subaperture
+// values (S, sb, sid, b) are wave-uniform.
 template <int NS>
 __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S,
                                           const DevSubap& sb, int sid, int b, double stepd,
                                           char* wsm, const OtfLds& lo) {
+  constexpr int NPIX = NS * NS;
+  constexpr int PPL = (NPIX + kWave - 1) / kWave;  // pixels per lane
   const int lane = lane_id();
   const int nl = p.n_layers;
-  Tap* taps = reinterpret_cast<Tap*>(wsm + lo.taps_off);  // [nl][2*NS]: cols then rows
-  for (int t = lane; t < 2 * NS * nl; t += kWave) {
-    const int l = t / (2 * NS), k = t - l * (2 * NS);
-    taps[t] = (k < NS) ? col_tap(p, sid, l, sb.b * NS + k, stepd)
-                       : row_tap(p, sid, l, sb.a * NS + (k - NS), stepd);
+  // small per-sensor tables -> LDS (consumed by the fold and the image stages)
+  {
+    float2* st = reinterpret_cast<float2*>(wsm + lo.stab_off);
+    float2* wt = reinterpret_cast<float2*>(wsm + lo.wtab_off);
+    for (int k = lane; k < 2 * NS - 1 + S.n_pix; k += kWave) {
+      if (k < 2 * NS - 1) st[k] = p.stab[S.stab_off + k];
+      else wt[k - (2 * NS - 1)] = p.wtab[S.wtab_off + k - (2 * NS - 1)];
+    }
+  }
+  if (p.otf_from_phase) {  // split mode: the projection kernel already wrote kappa * psi
+    const float* ph = p.phase_in + (int64_t)b * p.phase_per_real + S.phase_off +
+                      (int64_t)sb.v * NPIX;
+    float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const int q = lane + i * kWave;
+      if (q < NPIX) {
+        const int r = q / NS, c = q - r * NS;
+        const uint8_t amp = p.mask[S.mask_off + (sb.a * NS + r) * S.n_pup + sb.b * NS + c];
+        float turns = fmaf(ph[q], 0.15915494309189535f, -(float)(r + c) * S.ramp);
+        turns -= rintf(turns);
+        float sn, cs;
+        sincos_rev(turns, &sn, &cs);
+        E[q] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+      }
+    }
+    wave_sync();
+    return;
+  }
+  // amplitude of this lane's pixels (issued early)
+  uint8_t amp[PPL];
+  int pr[PPL], pc[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int q = lane + i * kWave;
+    const int qq = q < NPIX ? q : 0;
+    pr[i] = qq / NS;
+    pc[i] = qq - pr[i] * NS;
+    amp[i] = q < NPIX ? p.mask[S.mask_off + (sb.a * NS + pr[i]) * S.n_pup + sb.b * NS + pc[i]] : 0;
+  }
+  // taps: [l][0..NS) columns, [l][NS..2NS) rows
+  Tap* taps = reinterpret_cast<Tap*>(wsm + lo.taps_off);
+  {
+    const int g = lane >> 5, j = lane & 31;
+    const bool row = j >= NS;
+    const int idx = row ? sb.a * NS + (j - NS) : sb.b * NS + j;
+    for (int l0 = 0; l0 < nl; l0 += 2) {
+      const int l1 = l0 + 1 < nl ? l0 + 1 : l0;
+      const DevLayer L0 = cload(p.lay, l0), L1 = cload(p.lay, l1);
+      const DevAffine A0 = cload(p.aff, sid * nl + l0), A1 = cload(p.aff, sid * nl + l1);
+      const Tap t = tap_of(g ? L1 : L0, g ? A1 : A0, row, idx, stepd);
+      if (j < 2 * NS && (g == 0 || l0 + 1 < nl)) taps[(l0 + g) * 2 * NS + j] = t;
+    }
   }
   wave_sync();
+  // projection: every load of a 4-layer chunk for all of the lane's pixels in flight at once
   const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
-  float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
-  for (int q = lane; q < NS * NS; q += kWave) {
-    const int r = q / NS, c = q - r * NS;
-    const int ir = sb.a * NS + r, ic = sb.b * NS + c;
-    float psi = 0.0f;
-    for (int l = 0; l < nl; ++l) {
-      const DevLayer& L = p.lay[l];
-      const Tap cx = taps[l * 2 * NS + c];
-      const Tap ry = taps[l * 2 * NS + NS + r];
-      psi = fmaf(L.weight, bilinear(lay_b + L.offset, cx, ry), psi);
+  float psi[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) psi[i] = 0.0f;
+  constexpr int LC = 4;
+  for (int l0 = 0; l0 < nl; l0 += LC) {
+    float v[LC][PPL][4];
+    Tap cx[LC][PPL], ry[LC][PPL];
+#pragma unroll
+    for (int jj = 0; jj < LC; ++jj) {
+      const int l = l0 + jj;
+      if (l < nl) {
+        const float* g = lay_b + cload(p.lay, l).offset;
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+          cx[jj][i] = taps[l * 2 * NS + pc[i]];
+          ry[jj][i] = taps[l * 2 * NS + NS + pr[i]];
+          v[jj][i][0] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i0));
+          v[jj][i][1] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i1));
+          v[jj][i][2] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i0));
+          v[jj][i][3] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i1));
+        }
+      }
     }
-    const uint8_t amp = p.mask[S.mask_off + ir * S.n_pup + ic];
+#pragma unroll
+    for (int jj = 0; jj < LC; ++jj) {
+      const int l = l0 + jj;
+      if (l < nl) {
+        const float w = cload(p.lay, l).weight;
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+          const Tap& a = cx[jj][i];
+          const Tap& r = ry[jj][i];
+          const float val = r.w0 * fmaf(a.w0, v[jj][i][0], a.w1 * v[jj][i][1]) +
+                            r.w1 * fmaf(a.w0, v[jj][i][2], a.w1 * v[jj][i][3]);
+          psi[i] = fmaf(w, val, psi[i]);
+        }
+      }
+    }
+  }
+  float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int q = lane + i * kWave;
     // phase in turns, reduced to [-1/2, 1/2] before the sincos
-    float turns = fmaf(psi, S.kappa * 0.15915494309189535f, -(float)(r + c) * S.ramp);
+    float turns = fmaf(psi[i], S.kappa * 0.15915494309189535f, -(float)(pr[i] + pc[i]) * S.ramp);
     turns -= rintf(turns);
     float sn, cs;
-    sincospif(2.0f * turns, &sn, &cs);
-    E[q] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+    sincos_rev(turns, &sn, &cs);
+    if (q < NPIX) E[q] = amp[i] ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
   }
   wave_sync();
 }
@@ -149,43 +250,67 @@ __device__ __forceinline__ void otf_autocorr(char* wsm, const OtfLds& lo, int j0
   wave_sync();
 }
 
-// Lag sums of one round of jobs, elongation, binning phases and the fold modulo n_pix,
-// accumulated into P[K] (lane per K; the first round initialises P).
+// Row sums of one round of jobs times the elongation and binning factors,
+// AW[dy][dx] (+)= w_dy Kel(dx, dy) s(dx) s(dy) sum_r part, lane per lag (dy, dx).
 template <int NS>
-__device__ __forceinline__ void otf_fold(const FwdParams& p, const DevSensor& S,
-                                         const DevSubap& sb, char* wsm, const OtfLds& lo,
-                                         int j0) {
+__device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& sb, char* wsm,
+                                           const OtfLds& lo, int j0) {
+  constexpr int NL = Otf<NS>::kLags;
   const int lane = lane_id();
-  const int np = S.n_pix, np2 = np * np;
   const float2* part = reinterpret_cast<const float2*>(wsm + lo.part_off);
-  float2* P = reinterpret_cast<float2*>(wsm + lo.p_off);
-  const float2* stab = p.stab + S.stab_off;  // s(k), k = -(NS-1) .. NS-1
+  const float2* stab = reinterpret_cast<const float2*>(wsm + lo.stab_off);
+  float2* aw = reinterpret_cast<float2*>(wsm + lo.aw_off);
   const int j1 = j0 + Otf<NS>::kJobsPerRound;
-  for (int K = lane; K < np2; K += kWave) {
-    const int Ky = K / np, Kx = K - Ky * np;
-    float2 acc = j0 == 0 ? make_float2(0.0f, 0.0f) : P[K];
-    for (int dy = Ky; dy < NS; dy += np) {
+#pragma unroll
+  for (int o0 = 0; o0 < NS * NL; o0 += kWave) {
+    const int o = o0 + lane;
+    if (o < NS * NL) {
+      const int dy = o / NL, ix = o - dy * NL, dx = ix - (NS - 1);
       const int base = job_base<NS>(dy);
       const int r0 = max(0, j0 - base), r1 = min(NS - dy, j1 - base);
-      if (r0 >= r1) continue;
-      const float wgt = dy == 0 ? 1.0f : 2.0f;
-      const float2 sy = stab[dy + NS - 1];
-      int dx = Kx - np * ((Kx + NS - 1) / np);
-      for (; dx < NS; dx += np) {
-        float2 a = make_float2(0.0f, 0.0f);
-        for (int r = r0; r < r1; ++r) {
-          const float2 v = part[(base + r - j0) * Otf<NS>::kLags + dx + NS - 1];
+      float2 a = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        if (r >= r0 && r < r1) {
+          const float2 v = part[(base + r - j0) * NL + ix];
           a.x += v.x;
           a.y += v.y;
         }
-        const float2 sx = stab[dx + NS - 1];
-        // t = s(dx) s(dy) Kel(dx, dy) wgt
-        const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
-        const float kel = __expf(-sb.alpha * proj * proj) * wgt;
-        const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
-        const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
-        acc.x = fmaf(a.x, tr, fmaf(-a.y, ti, acc.x));
-        acc.y = fmaf(a.x, ti, fmaf(a.y, tr, acc.y));
+      }
+      const float2 sx = stab[ix], sy = stab[dy + NS - 1];
+      const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
+      const float kel = __expf(-sb.alpha * proj * proj) * (dy == 0 ? 1.0f : 2.0f);
+      const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
+      const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
+      float2 t = make_float2(a.x * tr - a.y * ti, a.x * ti + a.y * tr);
+      if (j0 > 0) {
+        const float2 prev = aw[o];
+        t.x += prev.x;
+        t.y += prev.y;
+      }
+      aw[o] = t;
+    }
+  }
+  wave_sync();
+}
+
+// Fold modulo n_pix: P[Ky][Kx] = sum over lags (dy, dx) = (Ky, Kx) mod n_pix of AW, lane per K.
+template <int NS>
+__device__ __forceinline__ void otf_fold(const DevSensor& S, char* wsm, const OtfLds& lo) {
+  constexpr int NL = Otf<NS>::kLags;
+  const int lane = lane_id();
+  const int np = S.n_pix, np2 = np * np;
+  const float2* aw = reinterpret_cast<const float2*>(wsm + lo.aw_off);
+  float2* P = reinterpret_cast<float2*>(wsm + lo.p_off);
+  for (int K = lane; K < np2; K += kWave) {
+    const int Ky = fdiv(K, np, S.inv_npix), Kx = K - Ky * np;
+    const int dx0 = Kx - np * fdiv(Kx + NS - 1, np, S.inv_npix);
+    float2 acc = make_float2(0.0f, 0.0f);
+    for (int dy = Ky; dy < NS; dy += np) {
+      for (int dx = dx0; dx < NS; dx += np) {
+        const float2 v = aw[dy * NL + dx + NS - 1];
+        acc.x += v.x;
+        acc.y += v.y;
       }
     }
     P[K] = acc;
@@ -201,11 +326,12 @@ __device__ __forceinline__ void otf_image(const FwdParams& p, const DevSensor& S
   const float2* P = reinterpret_cast<const float2*>(wsm + lo.p_off);
   float2* Z = reinterpret_cast<float2*>(wsm + lo.z_off);
   float* B = reinterpret_cast<float*>(wsm + lo.b_off);
-  const float2* wt = p.wtab + S.wtab_off;
+  const float2* wt = reinterpret_cast<const float2*>(wsm + lo.wtab_off);
   for (int t = lane; t < np2; t += kWave) {
-    const int Ky = t / np, qx = t - Ky * np;
+    const int Ky = fdiv(t, np, S.inv_npix), qx = t - Ky * np;
     float2 z = make_float2(0.0f, 0.0f);
     int idx = 0;
+#pragma unroll 8
     for (int Kx = 0; Kx < np; ++Kx) {
       const float2 a = P[Ky * np + Kx];
       const float2 w = wt[idx];
@@ -218,9 +344,10 @@ __device__ __forceinline__ void otf_image(const FwdParams& p, const DevSensor& S
   }
   wave_sync();
   for (int t = lane; t < np2; t += kWave) {
-    const int qy = t / np, qx = t - qy * np;
+    const int qy = fdiv(t, np, S.inv_npix), qx = t - qy * np;
     float v = 0.0f;
     int idx = 0;
+#pragma unroll 8
     for (int Ky = 0; Ky < np; ++Ky) {
       const float2 z = Z[Ky * np + qx];
       const float2 w = wt[idx];
@@ -257,8 +384,8 @@ __device__ __forceinline__ Cog cog_sums(const FwdParams& p, const DevSensor& S, 
       add_noise_pair(b0, b1, w, S.read_noise);
       if (q1 >= np2) b1 = 0.0f;
     }
-    const int y0 = q0 / np, x0 = q0 - y0 * np;
-    const int y1 = q1 / np, x1 = q1 - y1 * np;
+    const int y0 = fdiv(q0, np, S.inv_npix), x0 = q0 - y0 * np;
+    const int y1 = fdiv(q1, np, S.inv_npix), x1 = q1 - y1 * np;
     s0 += b0 + b1;
     sx = fmaf((float)x0 - half, b0, fmaf((float)x1 - half, b1, sx));
     sy = fmaf((float)y0 - half, b0, fmaf((float)y1 - half, b1, sy));
@@ -291,17 +418,19 @@ __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
 #pragma unroll
   for (int rd = 0; rd < Otf<NS>::kRounds; ++rd) {
     otf_autocorr<NS>(wsm, lo, rd * Otf<NS>::kJobsPerRound);
-    otf_fold<NS>(p, S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
+    otf_lagsum<NS>(S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
   }
+  otf_fold<NS>(S, wsm, lo);
   otf_image(p, S, wsm, lo);
 }
 
 template <int NS>
 __device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm) {
   int b, sid, v;
+  t = __builtin_amdgcn_readfirstlane(t);  // wave-uniform: per-subaperture data in SGPRs
   task_of(p.otf, t, b, sid, v);
-  const DevSensor S = p.sen[sid];
-  const DevSubap sb = p.sub[S.valid_off + v];
+  const DevSensor S = cload(p.sen, sid);
+  const DevSubap sb = cload(p.sub, S.valid_off + v);
   const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix);
   otf_spot<NS>(p, S, sb, sid, b, step, wsm, lo);
   const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));

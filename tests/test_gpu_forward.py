@@ -37,12 +37,38 @@ def _check(cfg, x, s_gpu, a_gpu, step, seed=42):
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("step", [0, 7])
-def test_forward_matches_oracle(name, step):
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_forward_matches_oracle(name, step, mode):
+    torch, W = _gpu()
     cfg = CASES[name]()
     x = layers_for(cfg)
-    s, a, plan, _ = _run(cfg, x, step)
+    s, a, plan, _ = _run(cfg, x, step, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
     assert s.shape == (cfg["batch"], oracle.n_slopes(cfg))
     _check(cfg, x, s, a, step)
+
+
+@pytest.mark.parametrize("name", ["cfg0", "fft_ngs_n14_N32_b4", "ngs_n2_N4_b2"])
+def test_forward_forced_fft_path(name):
+    """The FFT path on sensors the lag-domain path also serves (no elongation)."""
+    torch, W = _gpu()
+    cfg = CASES[name]()
+    x = layers_for(cfg)
+    try:
+        s, a, plan, _ = _run(cfg, x, 3, flags=W.WFS_FLAG_FORCE_FFT)
+    except W.WfsError as e:
+        assert e.code == -4 and name == "ngs_n2_N4_b2"  # N = 4 has no FFT kernel
+        return
+    assert all(p == 1 for p in plan.paths)
+    _check(cfg, x, s, a, 3)
+
+
+def test_paths_chosen_by_the_plan():
+    torch, W = _gpu()
+    plan = W.Plan(CASES["mixed_lgs_ngs_batch2"]())
+    assert plan.paths == [0, 1]
+    plan2 = W.Plan(synth.config2(batch=1))
+    assert plan2.paths == [0] * 6 + [1] * 3
+    assert plan2.n_slopes == 55608
 
 
 def test_forward_is_bitwise_deterministic():
@@ -67,6 +93,19 @@ def test_flat_screens_give_zero_slopes_on_gpu():
         x = np.zeros((cfg["batch"], cfg["layer_stride"]), np.float32)
         s, a, _, _ = _run(cfg, x, 0)
         assert np.abs(s).max() < 2e-6, name
+
+
+def test_tuned_schedule_matches_oracle():
+    """Whatever schedule the autotuner keeps (split/fused, tasks per wave, block order)
+    computes the same slopes."""
+    torch, W = _gpu()
+    cfg = CASES["lgs_n10_N32_b4_noise"]()
+    x = layers_for(cfg)
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    plan.tune(xt, iters=3)
+    s, a = plan.forward(xt, step=5)
+    _check(cfg, x, s.cpu().numpy().astype(np.float64), a.cpu().numpy().astype(np.float64), 5)
 
 
 def test_device_step_counter_matches_host_step():
@@ -103,12 +142,13 @@ def test_project_matches_oracle():
         o += len(geo["valid"]) * n * n
 
 
-@pytest.mark.parametrize("step", [0, 61])
-def test_config1_full_frame_matches_oracle(step):
+@pytest.mark.parametrize("step,mode", [(0, "split"), (61, "split"), (61, "fused")])
+def test_config1_full_frame_matches_oracle(step, mode):
     """E-ELT 80x80 LGS (config 1), every one of the 4,632 subapertures, noise on."""
+    torch, W = _gpu()
     cfg = synth.config1()
     x = synth.make_batch(cfg, [0])
-    s, a, plan, _ = _run(cfg, x, step)
+    s, a, plan, _ = _run(cfg, x, step, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
     assert plan.n_slopes == 9264
     worst = _check(cfg, x, s, a, step)
     print(f"config1 step {step}: worst slope error {worst:.3g} of tolerance")

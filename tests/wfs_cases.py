@@ -50,6 +50,17 @@ def dm_case():
     return _finish(cfg)
 
 
+def mixed_case(batch=2):
+    """A lag-domain LGS and an FFT-path NGS (n_sub > 12) in one plan, several realisations."""
+    cfg = lgs_case(6, 4, 8, 2, layers=2, n=128, pitch=0.25, noise=True, batch=batch)
+    ngs = synth.configs._ngs(theta_x=15 * ARCSEC, theta_y=-20 * ARCSEC, n_sa=2, n_sub=16,
+                             n_fft=32, bin_=4, lam=1.65e-6, photons=4000.0, read_noise=3.0,
+                             pupil_d=cfg["sensors"][0]["pupil_d_m"],
+                             obs_d=cfg["sensors"][0]["obs_d_m"])
+    cfg["sensors"].append(ngs)
+    return cfg
+
+
 CASES = {
     "cfg0": lambda: synth.config0(),
     "lgs_n4_N8_b2": lambda: lgs_case(6, 4, 8, 2),
@@ -60,6 +71,12 @@ CASES = {
     "ngs_n12_N24_b3": lambda: ngs_case(4, 12, 24, 3, D=8.0, obs=2.0, layers=3),
     "ngs_n2_N4_b2": lambda: ngs_case(6, 2, 4, 2, D=4.0, obs=0.5),
     "dm_two_ngs_batch2": dm_case,
+    "fft_ngs_n14_N32_b4": lambda: ngs_case(4, 14, 32, 4, D=8.0, obs=2.0, layers=2),
+    "fft_ngs_n20_N64_b2": lambda: ngs_case(3, 20, 64, 2, D=9.0, obs=2.0, layers=2, n=128),
+    "fft_ngs_n64_N128_b4": lambda: ngs_case(2, 64, 128, 4, D=39.0, obs=11.0, layers=3, n=256,
+                                            lam=1.65e-6, photons=5000.0, ro=3.0),
+    "fft_ngs_n40_N128_b4": lambda: ngs_case(2, 40, 128, 4, D=16.0, obs=3.0, layers=2, n=128),
+    "mixed_lgs_ngs_batch2": mixed_case,
 }
 
 
