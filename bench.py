@@ -137,6 +137,61 @@ def bench_config1(torch, W, steps, warmup, k0=0, tune=True, flags=0):
                 kernel_ms_eager=kernel_ms_eager, tuned_us=tuned_us, x=x)
 
 
+def bench_batched(torch, W, steps=20, batch=8):
+    """Config 2: 6 LGS + 3 NGS x 8 realisations, one wfs_forward per time step, the steps
+    captured in one HIP graph."""
+    cfg = synth.config2(batch=batch)
+    x = torch.from_numpy(synth.make_batch(cfg, range(batch))).cuda()
+    plan = W.Plan(cfg, batch=batch)
+    plan.tune(x, iters=3)
+    slopes, aux = plan.forward(x, step=0)
+
+    def step(i):
+        plan.forward(x, step=i, seed=42, slopes=slopes, aux=aux)
+
+    g = graph_of(torch, step, steps)
+    g.replay()
+    wall, gpu_ms = timed_replay(torch, g, steps)
+    n_lgs = sum(1 for s in cfg["sensors"] if np.isfinite(s["src_alt_m"]))
+    lgs_subaps = sum(nv for s, nv in zip(cfg["sensors"], plan.n_valid) if np.isfinite(s["src_alt_m"]))
+    flops = plan_flops(cfg, plan, batch)
+    return dict(workload="config2: 6 LGS 80x80 + 3 NGS 2x2 (64 px, N=128), 8 realisations, "
+                         "10 layers 1024^2, noise on, graph of %d steps" % steps,
+                ms_per_step=gpu_ms, steps=steps,
+                lgs_frames_per_s=n_lgs * batch / (gpu_ms * 1e-3),
+                subap_spots_per_s=(sum(plan.n_valid) * batch) / (gpu_ms * 1e-3),
+                lgs_subaps_per_step=lgs_subaps * batch,
+                achieved_tflops=flops / (gpu_ms * 1e-3) / 1e12,
+                frac_fp32_valu=flops / (gpu_ms * 1e-3) / PEAK_FP32_VALU,
+                paths=plan.paths)
+
+
+def bench_closed_loop(torch, W, steps=20, batch=8, gain=0.4):
+    """Config 4: config-2 sensors with three DM grids as weight -1 layers, reconstructor
+    5400 x 55608 applied as a GEMM over the 8 realisations straight into the DM actuators
+    (a += g R s), the loop steps captured in one HIP graph."""
+    cfg = synth.config4(batch=batch)
+    x = torch.from_numpy(synth.make_batch(cfg, range(batch))).cuda()
+    plan = W.Plan(cfg, batch=batch)
+    plan.tune(x, iters=3)
+    R = torch.from_numpy(synth.make_reconstructor(cfg["n_act_rows"], plan.n_slopes)).cuda()
+    slopes, aux = plan.forward(x, step=0)
+    dm = x.view(batch, -1)[:, cfg["dm_offset"]:]
+    ldc = cfg["layer_stride"]
+
+    def step(i):
+        plan.forward(x, step=i, seed=42, slopes=slopes, aux=aux)
+        W.recon_apply(R, slopes, dm, alpha=gain, beta=1.0, ldc=ldc)
+
+    step(0)
+    g = graph_of(torch, step, steps)
+    g.replay()
+    wall, gpu_ms = timed_replay(torch, g, steps)
+    return dict(workload="config4: config2 sensors + 3 DMs (40^2, 42^2, 45^2 @ 0/4/12.7 km), "
+                         "R 5400 x 55608 FP32, integrator g=0.4, graph of %d steps" % steps,
+                ms_per_step=gpu_ms, steps_per_s=1e3 / gpu_ms, n_slopes=plan.n_slopes)
+
+
 def bench_adjoint(torch, W, reps=20):
     cfg = synth.config3()
     x = torch.from_numpy(synth.make_batch(cfg, [cfg["guess_realisation"]])).cuda()
@@ -255,6 +310,18 @@ def main():
             out["recon"] = bench_recon(torch, W)
         except Exception as e:
             out["recon"] = {"error": repr(e)}
+        try:
+            log("[bench] config2 batched ...")
+            bt = bench_batched(torch, W)
+            bt["lgs_frames_vs_plain_forward"] = bt["lgs_frames_per_s"] / frames_per_s
+            out["batched"] = bt
+        except Exception as e:
+            out["batched"] = {"error": repr(e)}
+        try:
+            log("[bench] config4 closed loop ...")
+            out["closed_loop"] = bench_closed_loop(torch, W)
+        except Exception as e:
+            out["closed_loop"] = {"error": repr(e)}
         if not args.no_cpu:
             log("[bench] cpu baseline (oracle) ...")
             out["cpu_baseline"] = cpu_baseline(args.cpu_frames)

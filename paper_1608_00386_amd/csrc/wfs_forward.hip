@@ -40,94 +40,82 @@ __global__ __launch_bounds__(kBlock) void wfs_forward_kernel(FwdParams p) {
   }
 }
 
-// Projection (Sec. 2.2), also the first kernel of the split forward: block = (realisation,
-// sensor, group of proj_group consecutive valid subapertures or, for large subapertures, a
-// chunk of proj_rows of their rows; ~512 pixels).  The stencil taps of the block's pupil
-// columns and rows for every layer (FP64 coordinates) go to LDS once, then every thread
-// gathers its pixels with the loads of eight layers in flight.  Output: kappa * psi of every
-// pixel of every valid subaperture, subaperture-major (the spot kernels' input layout).
+// Projection (Sec. 2.2), also the first kernel of the split forward.  Coalesced column
+// strips: block = (realisation, sensor, subaperture row a, chunk of proj_rows pixel rows,
+// strip of kProjStrip pupil columns); thread = one pupil column and every kProjRowGroups-th
+// row.  The column taps of the strip and the row taps of the chunk (FP64 coordinates) go to
+// LDS once per block; then for each of its rows a thread issues the four stencil loads of
+// five layers at once — consecutive threads read consecutive layer pixels.  Output: kappa*psi
+// of every pixel of every valid subaperture, subaperture-major (the spot kernels' layout).
+constexpr int kProjStrip = 64;
+constexpr int kProjRowGroups = kBlock / kProjStrip;
+
 __global__ __launch_bounds__(kBlock) void wfs_project_kernel(FwdParams p, float* phase) {
   extern __shared__ __align__(16) char smem[];
-  const int i = p.xcd_remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int blk = p.xcd_remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
   int b, sid, task;
-  task_of(p.proj, i, b, sid, task);
+  task_of(p.proj, blk, b, sid, task);
   const DevSensor S = cload(p.sen, sid);
-  const int ns = S.n_sub, n2 = ns * ns, G = S.proj_group, R = S.proj_rows;
-  const int chunks = (ns + R - 1) / R;
-  const int g = task / chunks, rc = task - g * chunks;
-  const int r0 = rc * R, nr = min(R, ns - r0);  // rows [r0, r0 + nr) of each subaperture
-  const int v0 = g * G;
-  const int nv = min(G, S.n_valid - v0);
-  const int nl = p.n_layers, nt = ns + nr;      // taps per (subaperture, layer): cols + rows
-  DevLayer* lay = reinterpret_cast<DevLayer*>(smem);
-  DevAffine* aff = reinterpret_cast<DevAffine*>(smem + kMaxLayers * sizeof(DevLayer));
-  Tap* taps = reinterpret_cast<Tap*>(smem + kMaxLayers * (sizeof(DevLayer) + sizeof(DevAffine)));
-  for (int l = threadIdx.x; l < nl; l += kBlock) {
-    lay[l] = p.lay[l];
-    aff[l] = p.aff[sid * nl + l];
-  }
-  __syncthreads();
+  const int packed = cload(p.proj_tasks, (int64_t)S.ptask_off + task);  // a | rc<<12 | strip<<20
+  const int a = packed & 0xFFF, rc = (packed >> 12) & 0xFF, strip = packed >> 20;
+  const int ns = S.n_sub, n2 = ns * ns, R = S.proj_rows;
+  const int r0 = rc * R, nr = min(R, ns - r0);
+  const int c0 = strip * kProjStrip;
+  const int nl = p.n_layers;
+  Tap* ctap = reinterpret_cast<Tap*>(smem);   // [nl][kProjStrip]
+  Tap* rtap = ctap + nl * kProjStrip;         // [nl][R]
   const double stepd = (double)current_step(p);
-  const int nvt = nv * nt;
-  const float inv_nvt = 1.0f / (float)nvt, inv_nt = 1.0f / (float)nt;
-  for (int t = threadIdx.x; t < nl * nvt; t += kBlock) {
-    const int l = fdiv(t, nvt, inv_nvt);
-    const int rem = t - l * nvt;
-    const int gi = fdiv(rem, nt, inv_nt), k = rem - gi * nt;
-    const DevSubap sb = p.sub[S.valid_off + v0 + gi];
-    const DevLayer& L = lay[l];
-    const DevAffine& A = aff[l];
-    Tap tp;
-    if (k < ns) {
-      const double u = fma(A.ax, (double)(sb.b * ns + k), A.bx0) + stepd * A.dbx;
-      tp = make_tap(u, L.nx, L.inv_nx, L.boundary, 1);
-    } else {
-      const double v = fma(A.ay, (double)(sb.a * ns + r0 + k - ns), A.by0) + stepd * A.dby;
-      tp = make_tap(v, L.ny, L.inv_ny, L.boundary, L.nx);
-    }
-    taps[(gi * nl + l) * nt + k] = tp;
+  const int tx = threadIdx.x & (kProjStrip - 1), tg = threadIdx.x / kProjStrip;
+  for (int l = tg; l < nl; l += kProjRowGroups) {  // column taps: one per thread per layer
+    const DevLayer L = p.lay[l];
+    const DevAffine A = p.aff[sid * nl + l];
+    const double u = fma(A.ax, (double)(c0 + tx), A.bx0) + stepd * A.dbx;
+    ctap[l * kProjStrip + tx] = make_tap(u, L.nx, L.inv_nx, L.boundary, 1);
+  }
+  for (int t = threadIdx.x; t < nl * nr; t += kBlock) {  // row taps of the chunk
+    const int l = t / nr, r = t - l * nr;
+    const DevLayer L = p.lay[l];
+    const DevAffine A = p.aff[sid * nl + l];
+    const double v = fma(A.ay, (double)(a * ns + r0 + r), A.by0) + stepd * A.dby;
+    rtap[l * R + r] = make_tap(v, L.ny, L.inv_ny, L.boundary, L.nx);
   }
   __syncthreads();
+  const int ic = c0 + tx;
+  if (ic >= S.n_pup) return;
+  const int bs = ic / ns, cx_in = ic - bs * ns;
+  const int vsub = cload(p.subidx, (int64_t)S.subidx_off + a * S.n_sa + bs);
+  if (vsub < 0) return;  // column of an unused subaperture
   const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
-  float* out = phase + (int64_t)b * p.phase_per_real + S.phase_off + (int64_t)v0 * n2 + r0 * ns;
-  const int npx = nr * ns;  // pixels per subaperture in this block
-  const float inv_npx = 1.0f / (float)npx, inv_ns = 1.0f / (float)ns;
-  for (int px = threadIdx.x; px < nv * npx; px += kBlock) {
-    const int gi = fdiv(px, npx, inv_npx);
-    const int q = px - gi * npx;
-    const int r = fdiv(q, ns, inv_ns), c = q - r * ns;  // row r within the chunk
-    const Tap* tg = taps + gi * nl * nt;
+  float* out = phase + (int64_t)b * p.phase_per_real + S.phase_off + (int64_t)vsub * n2 + cx_in;
+  for (int r = tg; r < nr; r += kProjRowGroups) {
     float psi = 0.0f;
-    constexpr int LC = 8;
+    constexpr int LC = 5;  // layers past the end repeat the last one with weight 0
     for (int l0 = 0; l0 < nl; l0 += LC) {
       float v[LC][4], wx0[LC], wx1[LC], wy0[LC], wy1[LC];
 #pragma unroll
       for (int jj = 0; jj < LC; ++jj) {
-        const int l = l0 + jj;
-        if (l < nl) {
-          const DevLayer L = cload(p.lay, l);  // wave-uniform: scalar base address
-          const float* gl = lay_b + L.offset;
-          const Tap cx = tg[l * nt + c];
-          const Tap ry = tg[l * nt + ns + r];
-          v[jj][0] = ld_idx(gl, (uint32_t)(ry.i0 + cx.i0));
-          v[jj][1] = ld_idx(gl, (uint32_t)(ry.i0 + cx.i1));
-          v[jj][2] = ld_idx(gl, (uint32_t)(ry.i1 + cx.i0));
-          v[jj][3] = ld_idx(gl, (uint32_t)(ry.i1 + cx.i1));
-          wx0[jj] = cx.w0;
-          wx1[jj] = cx.w1;
-          wy0[jj] = ry.w0 * L.weight;
-          wy1[jj] = ry.w1 * L.weight;
-        }
+        const int l = min(l0 + jj, nl - 1);
+        const DevLayer L = cload(p.lay, l);  // wave-uniform: scalar base address
+        const float wl = l0 + jj < nl ? L.weight : 0.0f;
+        const float* gl = lay_b + L.offset;
+        const Tap cx = ctap[l * kProjStrip + tx];
+        const Tap ry = rtap[l * R + r];
+        v[jj][0] = ld_idx(gl, (uint32_t)(ry.i0 + cx.i0));
+        v[jj][1] = ld_idx(gl, (uint32_t)(ry.i0 + cx.i1));
+        v[jj][2] = ld_idx(gl, (uint32_t)(ry.i1 + cx.i0));
+        v[jj][3] = ld_idx(gl, (uint32_t)(ry.i1 + cx.i1));
+        wx0[jj] = cx.w0;
+        wx1[jj] = cx.w1;
+        wy0[jj] = ry.w0 * wl;
+        wy1[jj] = ry.w1 * wl;
       }
 #pragma unroll
       for (int jj = 0; jj < LC; ++jj) {
-        if (l0 + jj < nl) {
-          psi = fmaf(wy0[jj], fmaf(wx0[jj], v[jj][0], wx1[jj] * v[jj][1]), psi);
-          psi = fmaf(wy1[jj], fmaf(wx0[jj], v[jj][2], wx1[jj] * v[jj][3]), psi);
-        }
+        psi = fmaf(wy0[jj], fmaf(wx0[jj], v[jj][0], wx1[jj] * v[jj][1]), psi);
+        psi = fmaf(wy1[jj], fmaf(wx0[jj], v[jj][2], wx1[jj] * v[jj][3]), psi);
       }
     }
-    out[(int64_t)gi * n2 + q] = psi * S.kappa;
+    out[(r0 + r) * ns] = psi * S.kappa;
   }
 }
 
@@ -169,10 +157,11 @@ int otf_lds_bytes(int ns, int n_layers, int n_pix) {
   return otf_lds_layout(ns, n_layers, n_pix).total;
 }
 
-int project_lds_bytes(int n_sub, int n_layers, int group, int rows) {
-  return kMaxLayers * (int)(sizeof(DevLayer) + sizeof(DevAffine)) +
-         group * n_layers * (n_sub + rows) * (int)sizeof(Tap);
+int project_lds_bytes(int n_layers, int rows) {
+  return n_layers * (kProjStrip + rows) * (int)sizeof(Tap);
 }
+
+int project_strip() { return kProjStrip; }
 
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st) {
   const int64_t blocks = (int64_t)p.proj.per_real * p.batch;

@@ -18,7 +18,8 @@
 namespace wfs {
 hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st);
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
-int project_lds_bytes(int n_sub, int n_layers, int group, int rows);
+int project_lds_bytes(int n_layers, int rows);
+int project_strip();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
@@ -171,7 +172,8 @@ static int validate(const wfs_layer_desc* layers, int32_t n_layers, int64_t laye
   int64_t slopes = 0;
   for (int s = 0; s < n_sensors; ++s) {
     const wfs_sensor_desc& S = sensors[s];
-    if (S.n_sa < 1 || S.n_sub < 1 || S.n_fft < 2 || S.bin < 1 || S.n_sa > 4096 || S.n_sub > 4096)
+    if (S.n_sa < 1 || S.n_sub < 1 || S.n_fft < 2 || S.bin < 1 || S.n_sa > 4095 || S.n_sub > 4080 ||
+        (int64_t)S.n_sa * S.n_sub > 65536)
       return fail(WFS_EINVAL, "sensor %d: n_sa=%d n_sub=%d n_fft=%d bin=%d", s, S.n_sa, S.n_sub,
                   S.n_fft, S.bin);
     if (S.n_fft % 2) return fail(WFS_EINVAL, "sensor %d: n_fft=%d must be even", s, S.n_fft);
@@ -276,6 +278,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<uint8_t> masks;
   std::vector<float2> stab, wtab;
   std::vector<int> otf_ids, fft_ids;
+  std::vector<int32_t> subidx, proj_tasks, proj_task_off, proj_task_count;
   int32_t slope_off = 0, aux_off = 0;
   int64_t phase_off = 0;
   int otf_ns = 0;
@@ -304,17 +307,28 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     d.flux_c = (float)(fph / ((double)S.n_fft * S.n_fft * (double)S.n_sub * S.n_sub));
     d.read_noise = (float)S.read_noise_e;
     d.ramp = (float)(0.5 / S.n_fft);
+    // projection blocks: (subaperture row, chunk of <= 16 pixel rows, strip of columns) that
+    // hold at least one valid subaperture; packed a | chunk << 12 | strip << 20
+    d.proj_rows = std::min(S.n_sub, 16);
+    d.subidx_off = (int32_t)subidx.size();
     {
-      // projection block: ~512 pixels (two per thread): whole subapertures in groups, or
-      // chunks of rows of one large subaperture; taps within ~32 KiB of LDS
-      const int n2 = S.n_sub * S.n_sub;
-      int G = std::max(1, 512 / n2);
-      const int per_sub = n_layers * 2 * S.n_sub * 16;
-      G = std::max(1, std::min(G, 32768 / per_sub));
-      int R = S.n_sub;
-      if (n2 > 512) R = std::max(1, 512 / S.n_sub);
-      d.proj_group = G;
-      d.proj_rows = R;
+      std::vector<int32_t> idx((size_t)S.n_sa * S.n_sa, -1);
+      for (const DevSubap& q : g.subs) idx[(size_t)q.a * S.n_sa + q.b] = q.v;
+      subidx.insert(subidx.end(), idx.begin(), idx.end());
+      const int W = project_strip();
+      const int chunks = (S.n_sub + d.proj_rows - 1) / d.proj_rows;
+      const int strips = (g.n_pup + W - 1) / W;
+      proj_task_off.push_back((int32_t)proj_tasks.size());
+      d.ptask_off = proj_task_off.back();
+      for (int a = 0; a < S.n_sa; ++a)
+        for (int rc = 0; rc < chunks; ++rc)
+          for (int st = 0; st < strips; ++st) {
+            bool any = false;
+            for (int c = st * W; c < std::min(g.n_pup, (st + 1) * W) && !any; ++c)
+              any = idx[(size_t)a * S.n_sa + c / S.n_sub] >= 0;
+            if (any) proj_tasks.push_back(a | (rc << 12) | (st << 20));
+          }
+      proj_task_count.push_back((int32_t)proj_tasks.size() - proj_task_off.back());
     }
     if ((int64_t)masks.size() + (int64_t)g.mask.size() > (1LL << 31) - 1) {
       delete P;
@@ -403,6 +417,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   const size_t o_mask = push_table(blob, masks);
   const size_t o_stab = push_table(blob, stab);
   const size_t o_wtab = push_table(blob, wtab);
+  const size_t o_subidx = push_table(blob, subidx);
+  const size_t o_ptask = push_table(blob, proj_tasks);
   std::vector<int64_t> step0(1, 0);
   const size_t o_step = push_table(blob, step0);
   blob.resize((blob.size() + 255) & ~size_t(255));
@@ -425,6 +441,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.mask = reinterpret_cast<const uint8_t*>(P->d_blob + o_mask);
   b.stab = reinterpret_cast<const float2*>(P->d_blob + o_stab);
   b.wtab = reinterpret_cast<const float2*>(P->d_blob + o_wtab);
+  b.subidx = reinterpret_cast<const int32_t*>(P->d_blob + o_subidx);
+  b.proj_tasks = reinterpret_cast<const int32_t*>(P->d_blob + o_ptask);
   P->d_step = reinterpret_cast<int64_t*>(P->d_blob + o_step);
   b.step_dev = P->d_step;
   b.layer_stride = layer_stride;
@@ -440,9 +458,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     std::vector<int32_t> groups(n_sensors);
     for (int s = 0; s < n_sensors; ++s) {
       all_ids[s] = s;
-      const int chunks = (ds[s].n_sub + ds[s].proj_rows - 1) / ds[s].proj_rows;
-      groups[s] = (ds[s].n_valid + ds[s].proj_group - 1) / ds[s].proj_group * chunks;
-      const int lb = project_lds_bytes(ds[s].n_sub, n_layers, ds[s].proj_group, ds[s].proj_rows);
+      groups[s] = proj_task_count[s];
+      const int lb = project_lds_bytes(n_layers, ds[s].proj_rows);
       P->proj_lds = std::max(P->proj_lds, lb);
       if (ds[s].path == kPathFft) P->proj_lds_fft = std::max(P->proj_lds_fft, lb);
     }

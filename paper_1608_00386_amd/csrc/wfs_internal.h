@@ -36,8 +36,8 @@ struct DevSensor {
   int32_t n_sa, n_sub, n_fft, bin;
   int32_t n_pix, n_pup, n_valid, valid_off;  // valid_off: first row of the subap table
   int32_t slope_off, aux_off, mask_off, path;
-  int32_t noisy, elong, phase_off, proj_group;  // phase_off: offset in the phase buffer;
-                                                // proj_group: subapertures per projection block
+  int32_t noisy, elong, phase_off, proj_rows;  // phase_off: offset in the phase buffer;
+                                               // proj_rows: pixel rows per projection block
   float kappa;       // lambda_ref / lambda
   float flux_c;      // F_ph / (n_fft^2 n_sub^2)
   float read_noise;  // electrons rms
@@ -45,7 +45,9 @@ struct DevSensor {
   int32_t stab_off;  // first entry of this sensor's lag-phase table s(k), k = -(n_sub-1)..
   int32_t wtab_off;  // first entry of this sensor's n_pix-point twiddle table
   float inv_npix;    // 1 / n_pix
-  int32_t proj_rows; // subaperture rows per projection block (n_sub unless split in chunks)
+  int32_t subidx_off;  // first entry of this sensor's [n_sa][n_sa] valid-index table (-1 = unused)
+  int32_t ptask_off;   // first entry of this sensor's projection block list
+  int32_t pad3, pad4, pad5;
 };
 
 struct DevSubap {
@@ -96,7 +98,9 @@ struct FwdParams {
   int32_t otf_from_phase;   // lag-domain path reads phase_in (split mode) instead of gathering
   TaskTable otf;
   TaskTable fft;
-  TaskTable proj;            // projection blocks: groups of proj_group subapertures per sensor
+  TaskTable proj;            // projection blocks per sensor (strips of pupil columns x rows)
+  const int32_t* proj_tasks; // packed (subaperture row, row chunk, strip) of each block
+  const int32_t* subidx;     // valid-subaperture index of (sensor, a, b), -1 if not valid
   const float* phase_in;     // split mode: phase of every valid pixel (kappa applied), or null
   int64_t phase_per_real;    // floats per realisation in the phase buffer
 };

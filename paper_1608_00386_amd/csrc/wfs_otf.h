@@ -165,39 +165,38 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
   float psi[PPL];
 #pragma unroll
   for (int i = 0; i < PPL; ++i) psi[i] = 0.0f;
-  constexpr int LC = 4;
+  // chunks of LC layers with every load in flight; layers past the end repeat the last one
+  // with weight 0 (no predicated register arrays)
+  constexpr int LC = 5;
   for (int l0 = 0; l0 < nl; l0 += LC) {
     float v[LC][PPL][4];
     Tap cx[LC][PPL], ry[LC][PPL];
+    float wl[LC];
 #pragma unroll
     for (int jj = 0; jj < LC; ++jj) {
-      const int l = l0 + jj;
-      if (l < nl) {
-        const float* g = lay_b + cload(p.lay, l).offset;
+      const int l = min(l0 + jj, nl - 1);
+      const DevLayer L = cload(p.lay, l);
+      wl[jj] = l0 + jj < nl ? L.weight : 0.0f;
+      const float* g = lay_b + L.offset;
 #pragma unroll
-        for (int i = 0; i < PPL; ++i) {
-          cx[jj][i] = taps[l * 2 * NS + pc[i]];
-          ry[jj][i] = taps[l * 2 * NS + NS + pr[i]];
-          v[jj][i][0] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i0));
-          v[jj][i][1] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i1));
-          v[jj][i][2] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i0));
-          v[jj][i][3] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i1));
-        }
+      for (int i = 0; i < PPL; ++i) {
+        cx[jj][i] = taps[l * 2 * NS + pc[i]];
+        ry[jj][i] = taps[l * 2 * NS + NS + pr[i]];
+        v[jj][i][0] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i0));
+        v[jj][i][1] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i1));
+        v[jj][i][2] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i0));
+        v[jj][i][3] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i1));
       }
     }
 #pragma unroll
     for (int jj = 0; jj < LC; ++jj) {
-      const int l = l0 + jj;
-      if (l < nl) {
-        const float w = cload(p.lay, l).weight;
 #pragma unroll
-        for (int i = 0; i < PPL; ++i) {
-          const Tap& a = cx[jj][i];
-          const Tap& r = ry[jj][i];
-          const float val = r.w0 * fmaf(a.w0, v[jj][i][0], a.w1 * v[jj][i][1]) +
-                            r.w1 * fmaf(a.w0, v[jj][i][2], a.w1 * v[jj][i][3]);
-          psi[i] = fmaf(w, val, psi[i]);
-        }
+      for (int i = 0; i < PPL; ++i) {
+        const Tap& a = cx[jj][i];
+        const Tap& r = ry[jj][i];
+        const float val = r.w0 * fmaf(a.w0, v[jj][i][0], a.w1 * v[jj][i][1]) +
+                          r.w1 * fmaf(a.w0, v[jj][i][2], a.w1 * v[jj][i][3]);
+        psi[i] = fmaf(wl[jj], val, psi[i]);
       }
     }
   }

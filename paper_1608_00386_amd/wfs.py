@@ -159,11 +159,14 @@ def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None):
     if C is None:
         C = torch.zeros(B, M, device=R.device)
         ldc = M
-    _need(C, "C")
+    if not isinstance(C, torch.Tensor) or C.dtype != torch.float32 or not C.is_cuda:
+        raise TypeError("C must be a float32 GPU tensor")
+    if C.dim() != 2 or C.shape[0] != B or C.shape[1] < M or C.stride(1) != 1:
+        raise ValueError(f"C {tuple(C.shape)} must be [B][>= M] with unit column stride")
     if ldc is None:
-        ldc = C.shape[-1]
-    if C.numel() < (B - 1) * ldc + M:
-        raise ValueError("C is too small for B rows of stride ldc")
+        ldc = C.stride(0)
+    if C.stride(0) != ldc or ldc < M:
+        raise ValueError(f"C row stride {C.stride(0)} must equal ldc={ldc} >= M={M}")
     L.check(L.lib().recon_apply(_ptr(R), int(M), int(N), _ptr(S), int(B), _ptr(C), int(ldc),
                                 float(alpha), float(beta), _stream(stream)), "recon_apply")
     return C
