@@ -4,8 +4,9 @@
 Headline (`value`): E-ELT 80x80 LGS frames per second (config 1: 39 m pupil, 4,632 valid
 10x10-pixel subapertures, 32-point FFT-equivalent spots, 8x8 binned pixels, 10 frozen-flow
 layers of 1024^2, cone compression, 10 km sodium elongation, photon + read noise), one
-frame = one wfs_forward over the whole sensor at one time step, inputs resident in HBM,
-frames replayed from a captured HIP graph (time steps k0 .. k0+K-1 baked in).
+frame = the whole sensor at one time step, inputs resident in HBM; the K timed frames are one
+wfs_forward_steps call (the projection of step k+1 runs inside the spot launch of step k),
+captured in a HIP graph and replayed.  The one-wfs_forward-per-frame rate is reported too.
 
 Also reported (same JSON line): the batched multi-sensor step (config 2), the adjoint
 (config 3) and the reconstructor (config 4 shape), each against the plain forward, the
@@ -132,9 +133,41 @@ def bench_config1(torch, W, steps, warmup, k0=0, tune=True, flags=0):
     kernel_ms_eager = eager_kernel_ms(torch, frame, min(steps, 50))
     g = graph_of(torch, frame, steps)
     g.replay()  # warm replay
-    wall, gpu_ms = timed_replay(torch, g, steps)
-    return dict(cfg=cfg, plan=plan, wall=wall, gpu_ms_per_frame=gpu_ms,
-                kernel_ms_eager=kernel_ms_eager, tuned_us=tuned_us, x=x)
+    wall1, gpu_ms1 = timed_replay(torch, g, steps)
+    del g
+    # pipelined frames: one wfs_forward_steps call over the K steps (projection of step k+1
+    # inside the spot launch of step k), captured once and replayed
+    sK = torch.empty(steps, 1, plan.n_slopes, device="cuda")
+    aK = torch.empty(steps, 1, plan.n_valid_total, device="cuda")
+    plan.forward_steps(x, k0, min(steps, warmup + 2), slopes=sK[:min(steps, warmup + 2)],
+                       aux=aK[:min(steps, warmup + 2)])
+    gK = graph_of(torch, lambda i: plan.forward_steps(x, k0, steps, slopes=sK, aux=aK), 1)
+    gK.replay()
+    wallK, gpu_msK = timed_replay(torch, gK, steps)
+    del gK
+    out = dict(cfg=cfg, plan=plan, wall=wallK, gpu_ms_per_frame=gpu_msK,
+               single_wall=wall1, single_gpu_ms_per_frame=gpu_ms1,
+               kernel_ms_eager=kernel_ms_eager, tuned_us=tuned_us, x=x,
+               schedule=plan.schedule(), pipelined=plan.schedule()["split"] == 1)
+    out.update(kernel_split_ms(torch, plan, x, slopes, aux, k0, min(steps, 100)))
+    return out
+
+
+def kernel_split_ms(torch, plan, x, slopes, aux, k0, n):
+    """Per-launch duration of the projection kernel and of the spot kernel of a split frame,
+    each from a graph of n back-to-back launches of that kernel alone, HIP events around the
+    replay on the launch stream."""
+    phase = plan.project(x, step=k0)
+    gp = graph_of(torch, lambda i: plan.project(x, step=k0 + i, out=phase), n)
+    gp.replay()
+    _, proj_ms = timed_replay(torch, gp, n)
+    del gp
+    gs = graph_of(torch, lambda i: plan.spots(phase, step=k0 + i, seed=42, slopes=slopes,
+                                              aux=aux), n)
+    gs.replay()
+    _, spots_ms = timed_replay(torch, gs, n)
+    del gs
+    return dict(project_ms=proj_ms, spots_ms=spots_ms)
 
 
 def bench_batched(torch, W, steps=20, batch=8):
@@ -242,6 +275,25 @@ def cpu_baseline(frames=8):
                       f"1 thread, {dt:.1f} s"}
 
 
+def profile_run(torch, W, n, tune=True, flags=0):
+    cfg = synth.config1()
+    x = torch.from_numpy(synth.make_batch(cfg, [0])).cuda()
+    plan = W.Plan(cfg, flags=flags)
+    if tune:
+        plan.tune(x, iters=5)
+    slopes, aux = plan.forward(x, step=0)
+    src = torch.empty(64 << 20, device="cuda")  # 256 MiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for i in range(n):
+        plan.forward(x, step=i, slopes=slopes, aux=aux)
+    for i in range(n):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_frames": n, "schedule": plan.schedule(),
+                      "copy_bytes": 2 * src.numel() * 4}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +304,9 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=8)
     ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule")
     ap.add_argument("--fused", action="store_true", help="projection fused into the spot kernel")
+    ap.add_argument("--profile-frames", type=int, default=0,
+                    help="short run for a profiler: tune, N eager config-1 frames and N plain "
+                         "copies of 256 MiB (the HBM counter calibration), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the "
@@ -263,6 +318,11 @@ def main():
     W.lib()  # fails loudly when the HIP library is missing
     torch.cuda.set_device(0)
 
+    if args.profile_frames > 0:
+        profile_run(torch, W, args.profile_frames, tune=not args.no_tune,
+                    flags=W.WFS_FLAG_FUSED if args.fused else 0)
+        return
+
     log("[bench] config1 forward ...")
     r1 = bench_config1(torch, W, args.steps, args.warmup, tune=not args.no_tune,
                        flags=W.WFS_FLAG_FUSED if args.fused else 0)
@@ -270,8 +330,20 @@ def main():
     subaps = r1["plan"].n_valid[0]
     frames_per_s = args.steps / r1["wall"]
     flops = plan_flops(cfg1, r1["plan"])
-    kern_s = r1["gpu_ms_per_frame"] * 1e-3
-    achieved = flops / kern_s
+    split = r1["schedule"]["split"] == 1
+    # dominant kernel: the spot launch.  Pipelined (split schedule): one launch per frame that
+    # forms the spots of step k and projects step k+1; its mean duration is the replayed
+    # graph's time per frame less the one leading projection.  All of it is charged to the
+    # spot stage's FLOPs (the projection's bytes are reported separately).
+    if split:
+        kern_ms = (r1["gpu_ms_per_frame"] * args.steps - r1["project_ms"]) / args.steps
+        kern_name = "wfs_forward_kernel<10> (spots of step k + projection of step k+1)"
+    else:
+        kern_ms = r1["gpu_ms_per_frame"]
+        kern_name = "wfs_forward_kernel<10> (fused gather)"
+    achieved = flops / (kern_ms * 1e-3)
+    foot, n_phase = r1["plan"].footprint(0)
+    proj_bytes = 4.0 * (foot + n_phase)  # each layer pixel read once, each phase pixel written
     out = {
         "metric": METRIC,
         "value": frames_per_s,
@@ -288,14 +360,26 @@ def main():
         "config": {"workload": "config1: E-ELT 80x80 LGS, 39 m/11 m pupil, 4632 subaps of 10x10 "
                                "px, N=32, 8x8 px, 10 layers 1024^2 0-16 km, H=90 km, Na 10 km, "
                                "noise on", "frames_per_step": 1, "subaps": subaps,
-                   "graph_replay": True},
+                   "graph_replay": True, "pipelined_frames": r1["pipelined"]},
         "spots_per_s": frames_per_s * subaps,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-                     "kernel": "wfs_forward_kernel<10>",
-                     "kernel_ms": r1["gpu_ms_per_frame"],
-                     "kernel_ms_eager_events": r1["kernel_ms_eager"],
-                     "algorithmic_flop_per_launch": flops},
+                     "kernel": kern_name,
+                     "kernel_ms": kern_ms,
+                     "algorithmic_flop_per_launch": flops,
+                     "spots_only_kernel_ms": r1["spots_ms"],
+                     "spots_only_frac": flops / (r1["spots_ms"] * 1e-3) / PEAK_FP32_VALU,
+                     "schedule": r1["schedule"]},
+        "single_frame": {"frames_per_s": args.steps / r1["single_wall"],
+                         "gpu_ms_per_frame": r1["single_gpu_ms_per_frame"],
+                         "eager_ms_per_frame": r1["kernel_ms_eager"],
+                         "note": "one wfs_forward per frame (projection, then spots), graph "
+                                 "of K frames"},
+        "projection": {"bound": "hbm", "kernel": "wfs_project_kernel", "kernel_ms":
+                       r1["project_ms"], "algorithmic_bytes_per_launch": proj_bytes,
+                       "achieved": proj_bytes / (r1["project_ms"] * 1e-3) / 1e9,
+                       "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                       "frac": proj_bytes / (r1["project_ms"] * 1e-3) / PEAK_HBM},
     }
     if not args.quick:
         try:

@@ -132,6 +132,48 @@ int wfs_forward(wfs_plan_t plan, const float* layers, int64_t step, uint64_t see
                 float* slopes, float* aux, void* stream);
 
 /*
+ * wfs_forward_steps -- n_steps consecutive frames, steps step0 .. step0 + n_steps - 1 (or,
+ *   with step0 = WFS_STEP_DEVICE, the device counter + 0 .. n_steps - 1; the counter is not
+ *   advanced): the same results, bit for bit, as n_steps calls of wfs_forward.  slopes:
+ *   device [n_steps][B][n_slopes]; aux: device [n_steps][B][n_valid_total] or NULL.  With the
+ *   split schedule the frames are pipelined: each launch forms the spots of step k and
+ *   projects the layers for step k + 1 into the plan's second phase buffer, so the
+ *   memory-latency-bound projection overlaps the arithmetic-bound spot stage (frozen flow,
+ *   Sec. 2.1, makes every frame's input known in advance).  Layers must not change during
+ *   the call.
+ */
+int wfs_forward_steps(wfs_plan_t plan, const float* layers, int64_t step0, int32_t n_steps,
+                      uint64_t seed, float* slopes, float* aux, void* stream);
+
+/*
+ * wfs_spots -- the spot stage alone (Sec. 2.7): slopes from a given phase buffer laid out as
+ *   wfs_project writes it ([B][sum over sensors of n_valid*n_sub^2], phase in radians at
+ *   the sensor wavelength, device memory).  Same noise, outputs and determinism as wfs_forward, which is
+ *   wfs_project into a plan-owned buffer followed by this call (or the fused gather).
+ */
+int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, float* slopes,
+              float* aux, void* stream);
+
+/*
+ * wfs_plan_schedule -- the launch schedule the plan currently uses (set at creation, changed
+ *   by wfs_plan_tune): split = 1 when a frame is the projection kernel followed by the spot
+ *   kernel, 0 when the spot kernel gathers the layers itself; subaperture tasks per wave of the
+ *   lag-domain kernel; xcd_remap = 1 when blocks are renumbered so neighbouring tasks share an
+ *   XCD.  Any output pointer may be NULL.
+ */
+int wfs_plan_schedule(wfs_plan_t plan, int32_t* split, int32_t* subaps_per_wave,
+                      int32_t* xcd_remap);
+
+/*
+ * wfs_plan_footprint -- algorithmic read footprint of the projection at time step `step`:
+ *   the number of distinct layer pixels (per realisation, all layers and sensors) that the
+ *   bilinear stencils of the pixels of valid subapertures touch, and the number of projected
+ *   pixels.  Host computation; no device work.
+ */
+int wfs_plan_footprint(wfs_plan_t plan, int64_t step, int64_t* distinct_layer_pixels,
+                       int64_t* phase_pixels);
+
+/*
  * wfs_project -- the projection step alone (Sec. 2.2): phase at the sensor wavelength of
  *   every pixel of every valid subaperture, [B][sum over sensors of n_valid*n_sub^2], per
  *   sensor subaperture-major then row-major pixels; dark pixels hold their projected phase.

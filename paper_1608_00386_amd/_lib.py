@@ -76,6 +76,12 @@ _PROTOS = {
     "wfs_plan_destroy": (_c.c_int, [_P]),
     "wfs_forward": (_c.c_int, [_P, _P, _c.c_int64, _c.c_uint64, _P, _P, _P]),
     "wfs_project": (_c.c_int, [_P, _P, _c.c_int64, _P, _P]),
+    "wfs_forward_steps": (_c.c_int, [_P, _P, _c.c_int64, _c.c_int32, _c.c_uint64, _P, _P, _P]),
+    "wfs_spots": (_c.c_int, [_P, _P, _c.c_int64, _c.c_uint64, _P, _P, _P]),
+    "wfs_plan_schedule": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
+                                     _c.POINTER(_c.c_int32)]),
+    "wfs_plan_footprint": (_c.c_int, [_P, _c.c_int64, _c.POINTER(_c.c_int64),
+                                      _c.POINTER(_c.c_int64)]),
     "wfs_adjoint": (_c.c_int, [_P, _P, _P, _P, _P, _c.c_int64, _P, _P]),
     "wfs_set_step": (_c.c_int, [_P, _c.c_int64, _P]),
     "wfs_advance_step": (_c.c_int, [_P, _c.c_int64, _P]),

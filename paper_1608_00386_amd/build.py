@@ -3,11 +3,13 @@
     python -m paper_1608_00386_amd.build          # or __graft_entry__.build()
 """
 
+import concurrent.futures
 import glob
 import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -19,7 +21,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 (v_pk_*_f32) stays off: the compiler emits plain VALU FP32 instead
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # floating-point atomics as hardware atomics (the adjoint's layer scatter)
@@ -36,20 +37,36 @@ def hipcc():
     raise RuntimeError("hipcc not found (ROCm toolchain required to build libwfs.so)")
 
 
-def build(verbose=False, extra=()):
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + list(extra) + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = r.stdout + r.stderr
     # the host pass does not know the device target feature: drop that one harmless warning
     lines = [l for l in out.splitlines() if "packed-fp32-ops" not in l or "error" in l]
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(lines))
-    if verbose and lines:
-        print("\n".join(lines))
+    return r.returncode, lines
+
+
+def build(verbose=False, extra=()):
+    """Compile every csrc/*.hip unit to an object (in parallel), then link libwfs.so."""
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with tempfile.TemporaryDirectory(prefix="wfs_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(s)[:-4] + ".o") for s in srcs]
+        cmds = [[hipcc()] + FLAGS + list(extra) + ["-c", s, "-o", o] for s, o in zip(srcs, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(_run, cmds))
+        msgs = [l for _, lines in results for l in lines]
+        if any(rc != 0 for rc, _ in results):
+            raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
+        tmp = LIB + ".tmp"
+        link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
+        rc, lines = _run(link)
+        if rc != 0:
+            raise RuntimeError("link failed:\n" + "\n".join(lines))
+        if verbose and msgs + lines:
+            print("\n".join(msgs + lines))
     os.replace(tmp, LIB)
     return LIB
 

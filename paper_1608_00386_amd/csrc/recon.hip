@@ -48,8 +48,25 @@ __global__ __launch_bounds__(kRB) void recon_valu_kernel(const float* __restrict
 #pragma unroll
   for (int r = 0; r < RW; ++r) acc[r] = 0.0f;
   if (VEC) {
-    // k0 and N are multiples of 4; rows 16-byte aligned
-    for (int k = k0 + 4 * lane; k < k1; k += 4 * 64) {
+    // k0 and N are multiples of 4; rows 16-byte aligned; two steps of loads in flight
+    int k = k0 + 4 * lane;
+    for (; k + 4 * 64 < k1; k += 2 * 4 * 64) {
+      const float4 s0 = *reinterpret_cast<const float4*>(s + k);
+      const float4 s1 = *reinterpret_cast<const float4*>(s + k + 256);
+      float4 r0[RW], r1[RW];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const int row = min(row0 + r, M - 1);
+        r0[r] = ldnt4(R + (int64_t)row * N + k);
+        r1[r] = ldnt4(R + (int64_t)row * N + k + 256);
+      }
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        acc[r] = fmaf(r0[r].x, s0.x, fmaf(r0[r].y, s0.y, fmaf(r0[r].z, s0.z, fmaf(r0[r].w, s0.w, acc[r]))));
+        acc[r] = fmaf(r1[r].x, s1.x, fmaf(r1[r].y, s1.y, fmaf(r1[r].z, s1.z, fmaf(r1[r].w, s1.w, acc[r]))));
+      }
+    }
+    for (; k < k1; k += 4 * 64) {
       const float4 sv = *reinterpret_cast<const float4*>(s + k);
 #pragma unroll
       for (int r = 0; r < RW; ++r) {
@@ -114,19 +131,35 @@ __global__ __launch_bounds__(kRB) void recon_mfma_kernel(const float* __restrict
 #pragma unroll
   for (int t = 0; t < TR; ++t) acc[t] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
   int k = k0;
-  // main loop: 32 columns per iteration (two float4 per lane per operand row)
-  for (; k + 32 <= k1; k += 32) {
+  // main loop: 32 columns per iteration (two float4 per lane per operand row), the next
+  // iteration's loads issued before this iteration's MFMAs (double-buffered registers)
+  float4 ra[TR], rb[TR], sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa;
+  if (k + 32 <= k1) {
     const int ka = k + 4 * kq, kb = k + 16 + 4 * kq;
-    float4 sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa;
     if (bok) {
       sa = *reinterpret_cast<const float4*>(srow + ka);
       sb = *reinterpret_cast<const float4*>(srow + kb);
     }
-    float4 ra[TR], rb[TR];
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
       ra[t] = ldnt4(rrow[t] + ka);
       rb[t] = ldnt4(rrow[t] + kb);
+    }
+  }
+  for (; k + 32 <= k1; k += 32) {
+    float4 na[TR], nb[TR], nsa = make_float4(0.f, 0.f, 0.f, 0.f), nsb = nsa;
+    const bool more = k + 64 <= k1;
+    if (more) {
+      const int ka = k + 32 + 4 * kq, kb = k + 48 + 4 * kq;
+      if (bok) {
+        nsa = *reinterpret_cast<const float4*>(srow + ka);
+        nsb = *reinterpret_cast<const float4*>(srow + kb);
+      }
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        na[t] = ldnt4(rrow[t] + ka);
+        nb[t] = ldnt4(rrow[t] + kb);
+      }
     }
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
@@ -138,6 +171,15 @@ __global__ __launch_bounds__(kRB) void recon_mfma_kernel(const float* __restrict
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].y, sb.y, acc[t], 0, 0, 0);
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].z, sb.z, acc[t], 0, 0, 0);
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[t].w, sb.w, acc[t], 0, 0, 0);
+    }
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        ra[t] = na[t];
+        rb[t] = nb[t];
+      }
+      sa = nsa;
+      sb = nsb;
     }
   }
   // tail: 16 columns per step, float4 granularity, guarded
@@ -217,7 +259,7 @@ static hipError_t workspace(size_t bytes, float** out) {
 }
 
 static int choose_splits(int row_groups, int N, int align, int* chunk) {
-  const int target_waves = 256 * 16;  // ~4 waves per SIMD
+  const int target_waves = 256 * 32;  // ~8 waves per SIMD
   int splits = std::max(1, std::min((target_waves + row_groups - 1) / row_groups, N / 256));
   int c = (N + splits - 1) / splits;
   c = (c + align - 1) / align * align;

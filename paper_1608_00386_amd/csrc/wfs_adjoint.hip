@@ -34,7 +34,7 @@ __host__ __device__ inline AdjLds adj_lds_layout(int ns, int n_layers, int n_pix
   return a;
 }
 
-template <int NS>
+template <int NS, bool FUSED>
 __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char* wsm) {
   const FwdParams& p = ap.f;
   const int lane = lane_id();
@@ -50,12 +50,12 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   const float gy = ap.grad_slopes[(int64_t)b * p.n_slopes + S.slope_off + S.n_valid + v];
   float s0, cx, cy;
   if (ap.fwd_slopes) {
-    otf_field<NS>(p, S, sb, sid, b, (double)step, wsm, lo);
+    otf_field<NS, FUSED>(p, S, sb, sid, b, (double)step, wsm, lo);
     s0 = ap.fwd_aux[(int64_t)b * p.n_valid_total + S.aux_off + v];
     cx = ap.fwd_slopes[(int64_t)b * p.n_slopes + S.slope_off + v];
     cy = ap.fwd_slopes[(int64_t)b * p.n_slopes + S.slope_off + S.n_valid + v];
   } else {
-    otf_spot<NS>(p, S, sb, sid, b, step, wsm, lo);
+    otf_spot<NS, FUSED>(p, S, sb, sid, b, step, wsm, lo);
     const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));
     s0 = c.s0;
     cx = s0 > 0.0f ? c.sx / s0 : 0.0f;
@@ -172,7 +172,7 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   wave_sync();
 }
 
-template <int NS>
+template <int NS, bool FUSED>
 __global__ __launch_bounds__(kBlock) void wfs_adjoint_kernel(AdjParams ap) {
   extern __shared__ __align__(16) char smem[];
   const FwdParams& p = ap.f;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void wfs_adjoint_kernel(AdjParams ap) {
   for (int k = 0; k < p.subaps_per_wave; ++k) {
     const int t = t0 + k;
     if (t >= total) break;
-    otf_adjoint_subap<NS>(ap, t, step, wsm);
+    otf_adjoint_subap<NS, FUSED>(ap, t, step, wsm);
   }
 }
 
@@ -206,8 +206,12 @@ static hipError_t launch_adj(AdjParams a, hipStream_t st) {
   const int spw = a.f.subaps_per_wave;
   const int64_t waves = (tasks + spw - 1) / spw;
   const int grid = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  hipLaunchKernelGGL(wfs_adjoint_kernel<NS>, dim3(grid), dim3(kBlock),
-                     a.f.lds_per_wave * kWavesPerBlock, st, a);
+  if (a.f.otf_from_phase)
+    hipLaunchKernelGGL((wfs_adjoint_kernel<NS, false>), dim3(grid), dim3(kBlock),
+                       a.f.lds_per_wave * kWavesPerBlock, st, a);
+  else
+    hipLaunchKernelGGL((wfs_adjoint_kernel<NS, true>), dim3(grid), dim3(kBlock),
+                       a.f.lds_per_wave * kWavesPerBlock, st, a);
   return hipGetLastError();
 }
 

@@ -169,8 +169,9 @@ __device__ __forceinline__ void task_of(const TaskTable& tt, int t, int& b, int&
   v = r - tt.start[k];
 }
 
+// Time step of a launch: p.step, or the device counter plus p.step (graph replays).
 __device__ __forceinline__ int64_t current_step(const FwdParams& p) {
-  return p.use_dev_step ? *p.step_dev : p.step;
+  return p.use_dev_step ? *p.step_dev + p.step : p.step;
 }
 
 }  // namespace wfs

@@ -20,6 +20,7 @@ hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st);
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
 int project_lds_bytes(int n_layers, int rows);
 int project_strip();
+int project_rows();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
@@ -80,7 +81,8 @@ struct wfs_plan_s {
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
   TaskTable proj_all{}, proj_fft{};
-  float* d_phase = nullptr;  // split-mode phase buffer [B][phase_per_real]
+  float* d_phase = nullptr;   // split-mode phase buffer [B][phase_per_real]
+  float* d_phase2 = nullptr;  // second buffer (pipelined frames), same allocation
   int split = 0;             // 1: projection kernel + spot kernel; 0: fused gather
 };
 
@@ -307,27 +309,26 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     d.flux_c = (float)(fph / ((double)S.n_fft * S.n_fft * (double)S.n_sub * S.n_sub));
     d.read_noise = (float)S.read_noise_e;
     d.ramp = (float)(0.5 / S.n_fft);
-    // projection blocks: (subaperture row, chunk of <= 16 pixel rows, strip of columns) that
-    // hold at least one valid subaperture; packed a | chunk << 12 | strip << 20
-    d.proj_rows = std::min(S.n_sub, 16);
+    // projection blocks: (group of project_rows() pupil rows, strip of project_strip()
+    // columns) holding at least one pixel of a valid subaperture; packed row0 | strip << 16
+    d.proj_rows = project_rows();
     d.subidx_off = (int32_t)subidx.size();
     {
       std::vector<int32_t> idx((size_t)S.n_sa * S.n_sa, -1);
       for (const DevSubap& q : g.subs) idx[(size_t)q.a * S.n_sa + q.b] = q.v;
       subidx.insert(subidx.end(), idx.begin(), idx.end());
-      const int W = project_strip();
-      const int chunks = (S.n_sub + d.proj_rows - 1) / d.proj_rows;
+      const int W = project_strip(), RG = d.proj_rows;
       const int strips = (g.n_pup + W - 1) / W;
       proj_task_off.push_back((int32_t)proj_tasks.size());
       d.ptask_off = proj_task_off.back();
-      for (int a = 0; a < S.n_sa; ++a)
-        for (int rc = 0; rc < chunks; ++rc)
-          for (int st = 0; st < strips; ++st) {
-            bool any = false;
+      for (int r0 = 0; r0 < g.n_pup; r0 += RG)
+        for (int st = 0; st < strips; ++st) {
+          bool any = false;
+          for (int r = r0; r < std::min(g.n_pup, r0 + RG) && !any; ++r)
             for (int c = st * W; c < std::min(g.n_pup, (st + 1) * W) && !any; ++c)
-              any = idx[(size_t)a * S.n_sa + c / S.n_sub] >= 0;
-            if (any) proj_tasks.push_back(a | (rc << 12) | (st << 20));
-          }
+              any = idx[(size_t)(r / S.n_sub) * S.n_sa + c / S.n_sub] >= 0;
+          if (any) proj_tasks.push_back(r0 | (st << 16));
+        }
       proj_task_count.push_back((int32_t)proj_tasks.size() - proj_task_off.back());
     }
     if ((int64_t)masks.size() + (int64_t)g.mask.size() > (1LL << 31) - 1) {
@@ -497,13 +498,16 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.fft_blocks = (int32_t)((P->fft_tasks + 7) / 8 * 8);
   default_schedule(P);
   if (P->phase_per_real > 0) {
-    e = hipMalloc((void**)&P->d_phase, sizeof(float) * (size_t)P->phase_per_real * batch);
+    const size_t n = (size_t)P->phase_per_real * batch;
+    e = hipMalloc((void**)&P->d_phase, sizeof(float) * 2 * n);
     if (e != hipSuccess) {
       (void)hipFree(P->d_blob);
       delete P;
-      return hip_fail(e, "wfs_plan: phase buffer");
+      return hip_fail(e, "wfs_plan: phase buffers");
     }
+    P->d_phase2 = P->d_phase + n;
   }
+  P->base.proj_lds = P->proj_lds;
   P->split = (flags & WFS_FLAG_FUSED) ? 0 : 1;
   if (P->proj_lds > 65536) P->split = 0;  // taps of one subaperture exceed the LDS budget
   if (P->proj_lds_fft > 65536) {
@@ -601,6 +605,132 @@ int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, 
   return WFS_OK;
 }
 
+int wfs_forward_steps(wfs_plan_t P, const float* layers, int64_t step0, int32_t n_steps,
+                      uint64_t seed, float* slopes, float* aux, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_forward_steps: null plan");
+  if (!layers || !slopes) return fail(WFS_EINVAL, "wfs_forward_steps: null layers or slopes");
+  if (n_steps < 1) return fail(WFS_EINVAL, "wfs_forward_steps: n_steps=%d < 1", n_steps);
+  int rc = check_step(step0, "wfs_forward_steps");
+  if (rc) return rc;
+  if (step0 >= 0 && step0 > INT64_MAX - n_steps)
+    return fail(WFS_EINVAL, "wfs_forward_steps: step overflow");
+  rc = check_device(P, "wfs_forward_steps");
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t ns_per = (int64_t)P->n_slopes * P->batch;
+  const int64_t na_per = (int64_t)P->n_valid_total * P->batch;
+  // frame k at step0 + k (or the device counter + k)
+  auto frame = [&](int k) {
+    const int64_t s = step0 == WFS_STEP_DEVICE ? WFS_STEP_DEVICE : step0 + k;
+    FwdParams p = call_params(P, layers, s, seed, slopes + k * ns_per, aux ? aux + k * na_per : nullptr);
+    if (s == WFS_STEP_DEVICE) p.step = k;
+    return p;
+  };
+  hipError_t e = hipSuccess;
+  if (!(P->split && P->d_phase)) {  // fused schedule: frames one after the other
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = launch_fwd_modes(P, frame(k), st);
+    if (e != hipSuccess) return hip_fail(e, "wfs_forward_steps: launch");
+    return WFS_OK;
+  }
+  // split schedule, pipelined: project step0; then launch k computes the spots of step k from
+  // buffer k % 2 and projects step k + 1 into the other buffer
+  float* buf[2] = {P->d_phase, P->d_phase2};
+  {
+    FwdParams p = frame(0);
+    p.proj = P->proj_all;
+    e = launch_project(p, buf[0], P->proj_lds, st);
+  }
+  for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+    FwdParams p = frame(k);
+    p.phase_in = buf[k & 1];
+    p.otf_from_phase = 1;
+    if (k + 1 < n_steps) {
+      p.proj = P->proj_all;
+      p.proj_blocks = P->proj_all.per_real * P->batch;
+      p.phase_out = buf[(k + 1) & 1];
+    }
+    e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "wfs_forward_steps: launch");
+  return WFS_OK;
+}
+
+int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, float* slopes,
+              float* aux, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_spots: null plan");
+  if (!phase || !slopes) return fail(WFS_EINVAL, "wfs_spots: null phase or slopes");
+  int rc = check_step(step, "wfs_spots");
+  if (rc) return rc;
+  rc = check_device(P, "wfs_spots");
+  if (rc) return rc;
+  FwdParams p = call_params(P, nullptr, step, seed, slopes, aux);
+  p.phase_in = phase;
+  p.otf_from_phase = 1;
+  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "wfs_spots: launch");
+  return WFS_OK;
+}
+
+int wfs_plan_schedule(wfs_plan_t P, int32_t* split, int32_t* subaps_per_wave,
+                      int32_t* xcd_remap) {
+  if (!P) return fail(WFS_EINVAL, "wfs_plan_schedule: null plan");
+  if (split) *split = P->split;
+  if (subaps_per_wave) *subaps_per_wave = P->base.subaps_per_wave;
+  if (xcd_remap) *xcd_remap = P->base.xcd_remap;
+  return WFS_OK;
+}
+
+int wfs_plan_footprint(wfs_plan_t P, int64_t step, int64_t* distinct_layer_pixels,
+                       int64_t* phase_pixels) {
+  if (!P) return fail(WFS_EINVAL, "wfs_plan_footprint: null plan");
+  if (step < 0) return fail(WFS_EINVAL, "wfs_plan_footprint: step < 0");
+  int64_t total = 0;
+  for (int l = 0; l < P->n_layers; ++l) {
+    const wfs_layer_desc& L = P->layers[l];
+    std::vector<uint8_t> hit((size_t)L.nx * L.ny, 0);
+    for (int s = 0; s < P->n_sensors; ++s) {
+      const wfs_sensor_desc& S = P->sensors[s];
+      SensorGeom g = sensor_geometry(S);
+      const double H = S.src_alt_m;
+      const double sc = finite_d(H) ? 1.0 - L.alt_m / H : 1.0;
+      const double t = (double)step * P->dt;
+      auto idx = [&](double c, int n, std::vector<int>& out) {
+        out.clear();
+        const double f = std::floor(c);
+        for (int k = 0; k < 2; ++k) {
+          long long i = (long long)f + k;
+          if (L.boundary == 0) {
+            i %= n;
+            if (i < 0) i += n;
+          } else if (i < 0 || i >= n) {
+            continue;
+          }
+          out.push_back((int)i);
+        }
+      };
+      std::vector<int> us, vs;
+      const int ns = S.n_sub;
+      for (const DevSubap& q : g.subs)
+        for (int r = 0; r < ns; ++r) {
+          const double y = ((q.a * ns + r) + 0.5 - g.n_pup / 2.0) * g.dx;
+          const double Y = sc * y + S.theta_y_rad * L.alt_m - L.vy_mps * t;
+          idx(Y / L.pitch_m + L.ny / 2.0 - 0.5, L.ny, vs);
+          for (int c = 0; c < ns; ++c) {
+            const double x = ((q.b * ns + c) + 0.5 - g.n_pup / 2.0) * g.dx;
+            const double X = sc * x + S.theta_x_rad * L.alt_m - L.vx_mps * t;
+            idx(X / L.pitch_m + L.nx / 2.0 - 0.5, L.nx, us);
+            for (int vv : vs)
+              for (int uu : us) hit[(size_t)vv * L.nx + uu] = 1;
+          }
+        }
+    }
+    for (uint8_t v : hit) total += v;
+  }
+  if (distinct_layer_pixels) *distinct_layer_pixels = total;
+  if (phase_pixels) *phase_pixels = P->phase_per_real;
+  return WFS_OK;
+}
+
 int wfs_project(wfs_plan_t P, const float* layers, int64_t step, float* phase, void* stream) {
   if (!P) return fail(WFS_EINVAL, "wfs_project: null plan");
   if (!layers || !phase) return fail(WFS_EINVAL, "wfs_project: null layers or phase");
@@ -661,7 +791,15 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   a.fwd_aux = fwd_aux;
   a.grad_layers = grad_layers;
   a.f.lds_per_wave = P->adj_lds_per_wave;
-  hipError_t e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  hipError_t e = hipSuccess;
+  if (P->split && P->d_phase) {  // subaperture fields from the projection kernel's phase
+    a.f.proj = P->proj_all;
+    e = launch_project(a.f, P->d_phase, P->proj_lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: projection launch");
+    a.f.phase_in = P->d_phase;
+    a.f.otf_from_phase = 1;
+  }
+  e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: launch");
   return WFS_OK;
 }

@@ -99,10 +99,14 @@ struct FwdParams {
   TaskTable otf;
   TaskTable fft;
   TaskTable proj;            // projection blocks per sensor (strips of pupil columns x rows)
-  const int32_t* proj_tasks; // packed (subaperture row, row chunk, strip) of each block
+  const int32_t* proj_tasks; // packed (first pupil row, column strip) of each block
   const int32_t* subidx;     // valid-subaperture index of (sensor, a, b), -1 if not valid
   const float* phase_in;     // split mode: phase of every valid pixel (kappa applied), or null
   int64_t phase_per_real;    // floats per realisation in the phase buffer
+  // pipelined frames: the spot launch of step k also projects step k + 1 into phase_out
+  int32_t proj_blocks;       // projection blocks interleaved with the spot blocks (0: none)
+  int32_t proj_lds;          // bytes of LDS a projection block needs
+  float* phase_out;
 };
 
 struct AdjParams {

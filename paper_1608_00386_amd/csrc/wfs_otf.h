@@ -40,7 +40,8 @@ __host__ __device__ constexpr int otf_jobs_per_round(int ns) {
 // Per-wave LDS layout (bytes), shared with the host sizing code:
 //   E [n_sub^2] float2 | tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2 |
 //   AW [n_sub][2 n_sub - 1] float2 (weighted lag sums) |
-//   union( taps [n_layers][2 n_sub] Tap ,  partial lag rows (one round) + P + Z + B )
+//   union( taps [n_layers][2 n_sub] Tap ,  partial lag rows (one round, half of the lags at
+//   a time: [jobs][n_sub] float2) + P (later B) + Z )
 struct OtfLds {
   int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off, total;
 };
@@ -54,13 +55,13 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   o.aw_off = o.wtab_off + n_pix * 8;
   const int u0 = (o.aw_off + ns * lags * 8 + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
-  const int part = jobs * lags * 8;
+  const int part = jobs * ns * 8;
   o.taps_off = u0;
   o.part_off = u0;
   o.p_off = u0 + part;
   o.z_off = o.p_off + np2 * 8;
-  o.b_off = o.z_off + np2 * 8;
-  int end = o.b_off + np2 * 4;
+  o.b_off = o.p_off;  // B overwrites P: the image's second pass reads only Z
+  int end = o.z_off + np2 * 8;
   if (u0 + taps > end) end = u0 + taps;
   o.total = (end + 15) & ~15;
   return o;
@@ -96,8 +97,10 @@ __device__ __forceinline__ Tap tap_of(const DevLayer& L, const DevAffine& A, boo
 
 // Fills the wave's E region with the subaperture field E[r][c] = A exp(i(psi - pi (r+c)/N)),
 // and the wave's copies of the sensor's lag-phase and twiddle tables.  All per-subaperture
-// values (S, sb, sid, b) are wave-uniform.
-template <int NS>
+// values (S, sb, sid, b) are wave-uniform.  FUSED: the phase is gathered from the layers here;
+// otherwise it is read from the projection kernel's buffer p.phase_in (a compile-time choice,
+// so that each kernel only holds the registers of its own path).
+template <int NS, bool FUSED>
 __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S,
                                           const DevSubap& sb, int sid, int b, double stepd,
                                           char* wsm, const OtfLds& lo) {
@@ -114,7 +117,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       else wt[k - (2 * NS - 1)] = p.wtab[S.wtab_off + k - (2 * NS - 1)];
     }
   }
-  if (p.otf_from_phase) {  // split mode: the projection kernel already wrote kappa * psi
+  if constexpr (!FUSED) {  // split mode: the projection kernel already wrote kappa * psi
     const float* ph = p.phase_in + (int64_t)b * p.phase_per_real + S.phase_off +
                       (int64_t)sb.v * NPIX;
     float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
@@ -132,126 +135,94 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       }
     }
     wave_sync();
-    return;
-  }
-  // amplitude of this lane's pixels (issued early)
-  uint8_t amp[PPL];
-  int pr[PPL], pc[PPL];
+  } else {
+    // amplitude of this lane's pixels (issued early)
+    uint8_t amp[PPL];
+    int pr[PPL], pc[PPL];
 #pragma unroll
-  for (int i = 0; i < PPL; ++i) {
-    const int q = lane + i * kWave;
-    const int qq = q < NPIX ? q : 0;
-    pr[i] = qq / NS;
-    pc[i] = qq - pr[i] * NS;
-    amp[i] = q < NPIX ? p.mask[S.mask_off + (sb.a * NS + pr[i]) * S.n_pup + sb.b * NS + pc[i]] : 0;
-  }
-  // taps: [l][0..NS) columns, [l][NS..2NS) rows
-  Tap* taps = reinterpret_cast<Tap*>(wsm + lo.taps_off);
-  {
-    const int g = lane >> 5, j = lane & 31;
-    const bool row = j >= NS;
-    const int idx = row ? sb.a * NS + (j - NS) : sb.b * NS + j;
-    for (int l0 = 0; l0 < nl; l0 += 2) {
-      const int l1 = l0 + 1 < nl ? l0 + 1 : l0;
-      const DevLayer L0 = cload(p.lay, l0), L1 = cload(p.lay, l1);
-      const DevAffine A0 = cload(p.aff, sid * nl + l0), A1 = cload(p.aff, sid * nl + l1);
-      const Tap t = tap_of(g ? L1 : L0, g ? A1 : A0, row, idx, stepd);
-      if (j < 2 * NS && (g == 0 || l0 + 1 < nl)) taps[(l0 + g) * 2 * NS + j] = t;
+    for (int i = 0; i < PPL; ++i) {
+      const int q = lane + i * kWave;
+      const int qq = q < NPIX ? q : 0;
+      pr[i] = qq / NS;
+      pc[i] = qq - pr[i] * NS;
+      amp[i] = q < NPIX ? p.mask[S.mask_off + (sb.a * NS + pr[i]) * S.n_pup + sb.b * NS + pc[i]]
+                        : 0;
     }
-  }
-  wave_sync();
-  // projection: every load of a 4-layer chunk for all of the lane's pixels in flight at once
-  const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
-  float psi[PPL];
-#pragma unroll
-  for (int i = 0; i < PPL; ++i) psi[i] = 0.0f;
-  // chunks of LC layers with every load in flight; layers past the end repeat the last one
-  // with weight 0 (no predicated register arrays)
-  constexpr int LC = 5;
-  for (int l0 = 0; l0 < nl; l0 += LC) {
-    float v[LC][PPL][4];
-    Tap cx[LC][PPL], ry[LC][PPL];
-    float wl[LC];
-#pragma unroll
-    for (int jj = 0; jj < LC; ++jj) {
-      const int l = min(l0 + jj, nl - 1);
-      const DevLayer L = cload(p.lay, l);
-      wl[jj] = l0 + jj < nl ? L.weight : 0.0f;
-      const float* g = lay_b + L.offset;
-#pragma unroll
-      for (int i = 0; i < PPL; ++i) {
-        cx[jj][i] = taps[l * 2 * NS + pc[i]];
-        ry[jj][i] = taps[l * 2 * NS + NS + pr[i]];
-        v[jj][i][0] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i0));
-        v[jj][i][1] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i1));
-        v[jj][i][2] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i0));
-        v[jj][i][3] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i1));
+    // taps: [l][0..NS) columns, [l][NS..2NS) rows
+    Tap* taps = reinterpret_cast<Tap*>(wsm + lo.taps_off);
+    {
+      const int g = lane >> 5, j = lane & 31;
+      const bool row = j >= NS;
+      const int idx = row ? sb.a * NS + (j - NS) : sb.b * NS + j;
+      for (int l0 = 0; l0 < nl; l0 += 2) {
+        const int l1 = l0 + 1 < nl ? l0 + 1 : l0;
+        const DevLayer L0 = cload(p.lay, l0), L1 = cload(p.lay, l1);
+        const DevAffine A0 = cload(p.aff, sid * nl + l0), A1 = cload(p.aff, sid * nl + l1);
+        const Tap t = tap_of(g ? L1 : L0, g ? A1 : A0, row, idx, stepd);
+        if (j < 2 * NS && (g == 0 || l0 + 1 < nl)) taps[(l0 + g) * 2 * NS + j] = t;
       }
     }
+    wave_sync();
+    // projection: every load of a 4-layer chunk for all of the lane's pixels in flight at once
+    const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
+    float psi[PPL];
 #pragma unroll
-    for (int jj = 0; jj < LC; ++jj) {
+    for (int i = 0; i < PPL; ++i) psi[i] = 0.0f;
+    // chunks of LC layers with every load in flight; layers past the end repeat the last one
+    // with weight 0 (no predicated register arrays)
+    constexpr int LC = 5;
+    for (int l0 = 0; l0 < nl; l0 += LC) {
+      float v[LC][PPL][4];
+      Tap cx[LC][PPL], ry[LC][PPL];
+      float wl[LC];
 #pragma unroll
-      for (int i = 0; i < PPL; ++i) {
-        const Tap& a = cx[jj][i];
-        const Tap& r = ry[jj][i];
-        const float val = r.w0 * fmaf(a.w0, v[jj][i][0], a.w1 * v[jj][i][1]) +
-                          r.w1 * fmaf(a.w0, v[jj][i][2], a.w1 * v[jj][i][3]);
-        psi[i] = fmaf(wl[jj], val, psi[i]);
+      for (int jj = 0; jj < LC; ++jj) {
+        const int l = min(l0 + jj, nl - 1);
+        const DevLayer L = cload(p.lay, l);
+        wl[jj] = l0 + jj < nl ? L.weight : 0.0f;
+        const float* g = lay_b + L.offset;
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+          cx[jj][i] = taps[l * 2 * NS + pc[i]];
+          ry[jj][i] = taps[l * 2 * NS + NS + pr[i]];
+          v[jj][i][0] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i0));
+          v[jj][i][1] = ld_idx(g, (uint32_t)(ry[jj][i].i0 + cx[jj][i].i1));
+          v[jj][i][2] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i0));
+          v[jj][i][3] = ld_idx(g, (uint32_t)(ry[jj][i].i1 + cx[jj][i].i1));
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < LC; ++jj) {
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+          const Tap& a = cx[jj][i];
+          const Tap& r = ry[jj][i];
+          const float val = r.w0 * fmaf(a.w0, v[jj][i][0], a.w1 * v[jj][i][1]) +
+                            r.w1 * fmaf(a.w0, v[jj][i][2], a.w1 * v[jj][i][3]);
+          psi[i] = fmaf(wl[jj], val, psi[i]);
+        }
       }
     }
-  }
-  float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
+    float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
 #pragma unroll
-  for (int i = 0; i < PPL; ++i) {
-    const int q = lane + i * kWave;
-    // phase in turns, reduced to [-1/2, 1/2] before the sincos
-    float turns = fmaf(psi[i], S.kappa * 0.15915494309189535f, -(float)(pr[i] + pc[i]) * S.ramp);
-    turns -= rintf(turns);
-    float sn, cs;
-    sincos_rev(turns, &sn, &cs);
-    if (q < NPIX) E[q] = amp[i] ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+    for (int i = 0; i < PPL; ++i) {
+      const int q = lane + i * kWave;
+      // phase in turns, reduced to [-1/2, 1/2] before the sincos
+      float turns =
+          fmaf(psi[i], S.kappa * 0.15915494309189535f, -(float)(pr[i] + pc[i]) * S.ramp);
+      turns -= rintf(turns);
+      float sn, cs;
+      sincos_rev(turns, &sn, &cs);
+      if (q < NPIX) E[q] = amp[i] ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+    }
+    wave_sync();
   }
-  wave_sync();
 }
 
-// Autocorrelation row-pair jobs [j0, j0 + jobs per round) -> partial lag rows in LDS.
-template <int NS>
-__device__ __forceinline__ void otf_autocorr(char* wsm, const OtfLds& lo, int j0) {
-  const int lane = lane_id();
-  const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
-  float2* part = reinterpret_cast<float2*>(wsm + lo.part_off);
-  const int j = j0 + lane;
-  if (lane < Otf<NS>::kJobsPerRound && j < Otf<NS>::kJobs) {
-    int dy, r;
-    job_of<NS>(j, dy, r);
-    float2 e1[NS], e2[NS];
-#pragma unroll
-    for (int c = 0; c < NS; ++c) {
-      e1[c] = E[r * NS + c];
-      e2[c] = E[(r + dy) * NS + c];
-    }
-    float2 acc[Otf<NS>::kLags];
-#pragma unroll
-    for (int k = 0; k < Otf<NS>::kLags; ++k) acc[k] = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int c1 = 0; c1 < NS; ++c1) {
-#pragma unroll
-      for (int c2 = 0; c2 < NS; ++c2) {
-        // E[r][c1] conj(E[r+dy][c2]) -> lag dx = c2 - c1
-        float2& a = acc[c2 - c1 + NS - 1];
-        a.x = fmaf(e1[c1].x, e2[c2].x, fmaf(e1[c1].y, e2[c2].y, a.x));
-        a.y = fmaf(e1[c1].y, e2[c2].x, fmaf(-e1[c1].x, e2[c2].y, a.y));
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < Otf<NS>::kLags; ++k) part[lane * Otf<NS>::kLags + k] = acc[k];
-  }
-  wave_sync();
-}
-
-// Row sums of one round of jobs times the elongation and binning factors,
+// Lag sums of one round of row-pair jobs for the lag columns [IX0, IX0 + W) (held in the
+// partial-row region, W columns per job), times the elongation and binning factors:
 // AW[dy][dx] (+)= w_dy Kel(dx, dy) s(dx) s(dy) sum_r part, lane per lag (dy, dx).
-template <int NS>
+template <int NS, int IX0, int W>
 __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& sb, char* wsm,
                                            const OtfLds& lo, int j0) {
   constexpr int NL = Otf<NS>::kLags;
@@ -261,17 +232,17 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
   float2* aw = reinterpret_cast<float2*>(wsm + lo.aw_off);
   const int j1 = j0 + Otf<NS>::kJobsPerRound;
 #pragma unroll
-  for (int o0 = 0; o0 < NS * NL; o0 += kWave) {
+  for (int o0 = 0; o0 < NS * W; o0 += kWave) {
     const int o = o0 + lane;
-    if (o < NS * NL) {
-      const int dy = o / NL, ix = o - dy * NL, dx = ix - (NS - 1);
+    if (o < NS * W) {
+      const int dy = o / W, k = o - dy * W, ix = IX0 + k, dx = ix - (NS - 1);
       const int base = job_base<NS>(dy);
       const int r0 = max(0, j0 - base), r1 = min(NS - dy, j1 - base);
       float2 a = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
         if (r >= r0 && r < r1) {
-          const float2 v = part[(base + r - j0) * NL + ix];
+          const float2 v = part[(base + r - j0) * NS + k];
           a.x += v.x;
           a.y += v.y;
         }
@@ -282,15 +253,66 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
       const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
       const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
       float2 t = make_float2(a.x * tr - a.y * ti, a.x * ti + a.y * tr);
+      const int oa = dy * NL + ix;
       if (j0 > 0) {
-        const float2 prev = aw[o];
+        const float2 prev = aw[oa];
         t.x += prev.x;
         t.y += prev.y;
       }
-      aw[o] = t;
+      aw[oa] = t;
     }
   }
   wave_sync();
+}
+
+// One round of autocorrelation row-pair jobs [j0, j0 + jobs per round), lag columns
+// [IX0, IX0 + W): lane per (dy, r) forms sum_c E[r][c] conj(E[r+dy][c+dx]) for those dx in
+// registers and leaves them in the partial-row region, then the lag sums over r.  Splitting
+// the lag columns in two halves keeps both the registers and the LDS region at half a lag row
+// per job, at the same number of multiply-adds.
+template <int NS, int IX0, int W>
+__device__ __forceinline__ void otf_corr_half(const DevSensor& S, const DevSubap& sb,
+                                              char* wsm, const OtfLds& lo, int j0) {
+  const int lane = lane_id();
+  const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
+  float2* part = reinterpret_cast<float2*>(wsm + lo.part_off);
+  const int j = j0 + lane;
+  if (lane < Otf<NS>::kJobsPerRound && j < Otf<NS>::kJobs) {
+    int dy, r;
+    job_of<NS>(j, dy, r);
+    // the second row stays in registers; the first streams from LDS one pixel at a time
+    float2 e2[NS];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) e2[c] = E[(r + dy) * NS + c];
+    float2 acc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[k] = make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int c1 = 0; c1 < NS; ++c1) {
+      const float2 e1 = E[r * NS + c1];
+#pragma unroll
+      for (int c2 = 0; c2 < NS; ++c2) {
+        // E[r][c1] conj(E[r+dy][c2]) -> lag dx = c2 - c1, column c2 - c1 + NS - 1
+        const int k = c2 - c1 + NS - 1 - IX0;
+        if (k >= 0 && k < W) {
+          float2& a = acc[k];
+          a.x = fmaf(e1.x, e2[c2].x, fmaf(e1.y, e2[c2].y, a.x));
+          a.y = fmaf(e1.y, e2[c2].x, fmaf(-e1.x, e2[c2].y, a.y));
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) part[lane * NS + k] = acc[k];
+  }
+  wave_sync();
+  otf_lagsum<NS, IX0, W>(S, sb, wsm, lo, j0);
+}
+
+template <int NS>
+__device__ __forceinline__ void otf_corr_round(const DevSensor& S, const DevSubap& sb,
+                                               char* wsm, const OtfLds& lo, int j0) {
+  otf_corr_half<NS, 0, NS>(S, sb, wsm, lo, j0);
+  otf_corr_half<NS, NS, NS - 1>(S, sb, wsm, lo, j0);
 }
 
 // Fold modulo n_pix: P[Ky][Kx] = sum over lags (dy, dx) = (Ky, Kx) mod n_pix of AW, lane per K.
@@ -409,21 +431,19 @@ __device__ __forceinline__ void write_slopes(const FwdParams& p, const DevSensor
 }
 
 // Binned noise-free (or noisy) image of one subaperture into the wave's B region.
-template <int NS>
+template <int NS, bool FUSED>
 __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
                                          const DevSubap& sb, int sid, int b, int64_t step,
                                          char* wsm, const OtfLds& lo) {
-  otf_field<NS>(p, S, sb, sid, b, (double)step, wsm, lo);
+  otf_field<NS, FUSED>(p, S, sb, sid, b, (double)step, wsm, lo);
 #pragma unroll
-  for (int rd = 0; rd < Otf<NS>::kRounds; ++rd) {
-    otf_autocorr<NS>(wsm, lo, rd * Otf<NS>::kJobsPerRound);
-    otf_lagsum<NS>(S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
-  }
+  for (int rd = 0; rd < Otf<NS>::kRounds; ++rd)
+    otf_corr_round<NS>(S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
   otf_fold<NS>(S, wsm, lo);
   otf_image(p, S, wsm, lo);
 }
 
-template <int NS>
+template <int NS, bool FUSED>
 __device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm) {
   int b, sid, v;
   t = __builtin_amdgcn_readfirstlane(t);  // wave-uniform: per-subaperture data in SGPRs
@@ -431,7 +451,7 @@ __device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm) {
   const DevSensor S = cload(p.sen, sid);
   const DevSubap sb = cload(p.sub, S.valid_off + v);
   const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix);
-  otf_spot<NS>(p, S, sb, sid, b, step, wsm, lo);
+  otf_spot<NS, FUSED>(p, S, sb, sid, b, step, wsm, lo);
   const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));
   write_slopes(p, S, b, v, c);
   wave_sync();

@@ -105,9 +105,56 @@ class Plan:
                                       _ptr(aux), _stream(stream)), "wfs_forward")
         return slopes, aux
 
+    def forward_steps(self, layers, step0, n_steps, seed=42, slopes=None, aux=None,
+                      stream=None):
+        """Slopes [n_steps][B][n_slopes] of steps step0 .. step0+n_steps-1 (pipelined)."""
+        self._layers(layers)
+        n = int(n_steps)
+        if slopes is None:
+            slopes = torch.empty(n, self.batch, self.n_slopes, device=layers.device)
+        if aux is None:
+            aux = torch.empty(n, self.batch, self.n_valid_total, device=layers.device)
+        _need(slopes, "slopes", numel=n * self.batch * self.n_slopes)
+        _need(aux, "aux", numel=n * self.batch * self.n_valid_total)
+        L.check(self._lib.wfs_forward_steps(self._h, _ptr(layers), int(step0), n, int(seed),
+                                            _ptr(slopes), _ptr(aux), _stream(stream)),
+                "wfs_forward_steps")
+        return slopes, aux
+
+    @property
+    def phase_numel(self):
+        return sum(nv * s["n_sub"] ** 2 for nv, s in zip(self.n_valid, self.cfg["sensors"]))
+
+    def spots(self, phase, step=0, seed=42, slopes=None, aux=None, stream=None):
+        """Slopes from a phase buffer laid out as ``project`` returns it (``wfs_spots``)."""
+        _need(phase, "phase", numel=self.batch * self.phase_numel)
+        if slopes is None:
+            slopes = torch.empty(self.batch, self.n_slopes, device=phase.device)
+        if aux is None:
+            aux = torch.empty(self.batch, self.n_valid_total, device=phase.device)
+        _need(slopes, "slopes", numel=self.batch * self.n_slopes)
+        _need(aux, "aux", numel=self.batch * self.n_valid_total)
+        L.check(self._lib.wfs_spots(self._h, _ptr(phase), int(step), int(seed), _ptr(slopes),
+                                    _ptr(aux), _stream(stream)), "wfs_spots")
+        return slopes, aux
+
+    def schedule(self):
+        """dict(split, subaps_per_wave, xcd_remap) of the current launch schedule."""
+        v = [ctypes.c_int32() for _ in range(3)]
+        L.check(self._lib.wfs_plan_schedule(self._h, *[ctypes.byref(x) for x in v]),
+                "wfs_plan_schedule")
+        return dict(split=v[0].value, subaps_per_wave=v[1].value, xcd_remap=v[2].value)
+
+    def footprint(self, step=0):
+        """(distinct layer pixels read, projected pixels) per realisation at ``step``."""
+        d, n = ctypes.c_int64(), ctypes.c_int64()
+        L.check(self._lib.wfs_plan_footprint(self._h, int(step), ctypes.byref(d),
+                                             ctypes.byref(n)), "wfs_plan_footprint")
+        return d.value, n.value
+
     def project(self, layers, step=0, out=None, stream=None):
         self._layers(layers)
-        n = sum(nv * s["n_sub"] ** 2 for nv, s in zip(self.n_valid, self.cfg["sensors"]))
+        n = self.phase_numel
         if out is None:
             out = torch.empty(self.batch, n, device=layers.device)
         _need(out, "phase", numel=self.batch * n)

@@ -24,7 +24,7 @@ def _declared_functions():
 def test_header_declares_the_path_entry_points():
     names = _declared_functions()
     for n in ("wfs_plan", "wfs_forward", "wfs_adjoint", "recon_apply", "wfs_plan_destroy",
-              "wfs_plan_info", "wfs_last_error", "wfs_project"):
+              "wfs_plan_info", "wfs_last_error", "wfs_project", "wfs_spots"):
         assert n in names
 
 
@@ -103,6 +103,9 @@ def test_calls_reject_null_handles_without_a_device():
     assert L.wfs_forward(None, None, 0, 0, None, None, None) == -1
     assert L.wfs_adjoint(None, None, None, None, None, 0, None, None) == -1
     assert L.wfs_plan_destroy(None) == -1
+    assert L.wfs_spots(None, None, 0, 0, None, None, None) == -1
+    assert L.wfs_plan_schedule(None, None, None, None) == -1
+    assert L.wfs_plan_footprint(None, 0, None, None) == -1
     assert L.recon_apply(None, 1, 1, None, 1, None, 1, 1.0, 0.0, None) == -1
     assert "null" in L.wfs_last_error().decode()
 

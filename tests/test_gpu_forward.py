@@ -142,6 +142,84 @@ def test_project_matches_oracle():
         o += len(geo["valid"]) * n * n
 
 
+@pytest.mark.parametrize("name", ["lgs_n10_N32_b4_noise", "mixed_lgs_ngs_batch2", "cfg0"])
+def test_spots_of_projection_is_the_forward(name):
+    """wfs_spots(wfs_project(x)) is the split forward, bit for bit (noise included)."""
+    torch, W = _gpu()
+    cfg = CASES[name]()
+    x = layers_for(cfg)
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    s1, a1 = plan.forward(xt, step=5, seed=3)
+    s2, a2 = plan.spots(plan.project(xt, step=5), step=5, seed=3)
+    assert torch.equal(s1, s2) and torch.equal(a1, a2)
+
+
+@pytest.mark.parametrize("name", ["lgs_n10_N32_b4_noise", "mixed_lgs_ngs_batch2",
+                                  "dm_two_ngs_batch2", "fft_ngs_n64_N128_b4"])
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_forward_steps_equals_single_frames(name, mode):
+    """Pipelined frames (projection of step k+1 inside the spot launch of step k) give the
+    single-frame results bit for bit, also from the device step counter."""
+    torch, W = _gpu()
+    cfg = CASES[name]()
+    x = layers_for(cfg)
+    plan = W.Plan(cfg, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
+    xt = torch.from_numpy(x).cuda()
+    n, k0 = 5, 3
+    s, a = plan.forward_steps(xt, k0, n, seed=7)
+    for k in range(n):
+        s1, a1 = plan.forward(xt, step=k0 + k, seed=7)
+        assert torch.equal(s[k], s1) and torch.equal(a[k], a1), k
+    plan.set_step(k0)
+    sd, ad = plan.forward_steps(xt, W.WFS_STEP_DEVICE, n, seed=7)
+    assert torch.equal(sd, s) and torch.equal(ad, a)
+    s_ref, _ = oracle.forward(x.astype(np.float64), cfg, k0 + n - 1, 7, noise=True)
+    err = np.abs(s[n - 1].cpu().numpy().astype(np.float64) - s_ref)
+    assert (err / slope_tolerance(cfg)[None, :]).max() <= 1.0
+
+
+def test_forward_steps_config1_equals_single_frames():
+    """Config 1, 6 pipelined frames: every frame's slopes equal the single-frame call."""
+    torch, W = _gpu()
+    cfg = synth.config1()
+    x = synth.make_batch(cfg, [0])
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    s, _ = plan.forward_steps(xt, 40, 6)
+    for k in (0, 5):
+        s1, _ = plan.forward(xt, step=40 + k)
+        assert torch.equal(s[k], s1)
+
+
+def test_footprint_matches_oracle_coordinates():
+    """Distinct layer pixels under the bilinear stencils of the valid subapertures' pixels."""
+    torch, W = _gpu()
+    cfg = CASES["dm_two_ngs_batch2"]()
+    plan = W.Plan(cfg)
+    step = 9
+    want = 0
+    for L in cfg["layers"]:
+        hit = np.zeros((L["ny"], L["nx"]), bool)
+        for sensor in cfg["sensors"]:
+            geo = oracle.pupil_geometry(sensor)
+            n = sensor["n_sub"]
+            u, v = oracle.wfs_oracle._layer_coords(L, sensor, geo, step, cfg["dt_s"])
+            iu0, iu1, _, _, ou0, ou1 = oracle.wfs_oracle._bilinear_taps(u, L["nx"], L["boundary"])
+            iv0, iv1, _, _, ov0, ov1 = oracle.wfs_oracle._bilinear_taps(v, L["ny"], L["boundary"])
+            for a, b in geo["valid"]:
+                rs, cs = slice(a * n, (a + 1) * n), slice(b * n, (b + 1) * n)
+                for iv, ov in ((iv0, ov0), (iv1, ov1)):
+                    for iu, ou in ((iu0, ou0), (iu1, ou1)):
+                        m = ov[rs][:, None] & ou[cs][None, :]
+                        hit[np.broadcast_to(iv[rs][:, None], m.shape)[m],
+                            np.broadcast_to(iu[cs][None, :], m.shape)[m]] = True
+        want += int(hit.sum())
+    got, n_phase = plan.footprint(step)
+    assert n_phase == plan.phase_numel
+    assert abs(got - want) <= 0.002 * want, (got, want)
+
+
 @pytest.mark.parametrize("step,mode", [(0, "split"), (61, "split"), (61, "fused")])
 def test_config1_full_frame_matches_oracle(step, mode):
     """E-ELT 80x80 LGS (config 1), every one of the 4,632 subapertures, noise on."""

@@ -85,11 +85,12 @@ def _adjoint_case(name, seed=1):
                                   "lgs_n5_N10_b2_2sens_batch3", "dm_two_ngs_batch2", "cfg0",
                                   "ngs_n6_N12_b4_oddpix"])
 @pytest.mark.parametrize("saved", [False, True])
-def test_adjoint_matches_oracle(name, saved):
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_adjoint_matches_oracle(name, saved, mode):
     torch, W = _gpu()
     cfg, x, g = _adjoint_case(name)
     step = 4
-    plan = W.Plan(cfg)
+    plan = W.Plan(cfg, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
     xt = torch.from_numpy(x).cuda()
     gt = torch.from_numpy(g).cuda()
     if saved:
