@@ -16,6 +16,7 @@ roofline fraction of the dominant kernel and the FP64 oracle's rate on the host 
 """
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -275,23 +276,57 @@ def cpu_baseline(frames=8):
                       f"1 thread, {dt:.1f} s"}
 
 
-def profile_run(torch, W, n, tune=True, flags=0):
+def profile_run(torch, W, n, flags=0):
+    """Short run for a profiler: the headline's pipelined frames (one projection, then n spot
+    launches that also project the next step) and n plain copies of 256 MiB, the HBM counter
+    calibration.  The plan keeps its default schedule (split, one subaperture per wave, XCD
+    block order), the one the autotuner picks for config 1 in unprofiled runs: timings taken
+    under counter collection would mislead the tuner."""
     cfg = synth.config1()
     x = torch.from_numpy(synth.make_batch(cfg, [0])).cuda()
     plan = W.Plan(cfg, flags=flags)
-    if tune:
-        plan.tune(x, iters=5)
-    slopes, aux = plan.forward(x, step=0)
+    sK = torch.empty(n, 1, plan.n_slopes, device="cuda")
+    aK = torch.empty(n, 1, plan.n_valid_total, device="cuda")
     src = torch.empty(64 << 20, device="cuda")  # 256 MiB
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    for i in range(n):
-        plan.forward(x, step=i, slopes=slopes, aux=aux)
+    plan.forward_steps(x, 0, n, slopes=sK, aux=aK)
     for i in range(n):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"profile_frames": n, "schedule": plan.schedule(),
                       "copy_bytes": 2 * src.numel() * 4}), flush=True)
+
+
+def kernel_source_digest():
+    """SHA-256 of the kernel and ABI sources (the counters in profiles/ name the digest they
+    were taken with; a different digest means they no longer describe these kernels)."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(root, "paper_1608_00386_amd", "csrc", "*")))
+    files.append(os.path.join(root, "include", "wfs.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "hbm_traffic_config1.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != kernel_source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
 def main():
@@ -305,8 +340,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule")
     ap.add_argument("--fused", action="store_true", help="projection fused into the spot kernel")
     ap.add_argument("--profile-frames", type=int, default=0,
-                    help="short run for a profiler: tune, N eager config-1 frames and N plain "
-                         "copies of 256 MiB (the HBM counter calibration), then exit")
+                    help="short run for a profiler: N pipelined config-1 frames (default "
+                         "schedule) and N plain copies of 256 MiB (the HBM counter "
+                         "calibration), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the "
@@ -319,8 +355,7 @@ def main():
     torch.cuda.set_device(0)
 
     if args.profile_frames > 0:
-        profile_run(torch, W, args.profile_frames, tune=not args.no_tune,
-                    flags=W.WFS_FLAG_FUSED if args.fused else 0)
+        profile_run(torch, W, args.profile_frames, flags=W.WFS_FLAG_FUSED if args.fused else 0)
         return
 
     log("[bench] config1 forward ...")
@@ -338,9 +373,11 @@ def main():
     if split:
         kern_ms = (r1["gpu_ms_per_frame"] * args.steps - r1["project_ms"]) / args.steps
         kern_name = "wfs_forward_kernel<10> (spots of step k + projection of step k+1)"
+        traffic_key = "wfs_forward_kernel<10, false, false, true>"
     else:
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = "wfs_forward_kernel<10> (fused gather)"
+        traffic_key = "wfs_forward_kernel<10, true, false, false>"
     achieved = flops / (kern_ms * 1e-3)
     foot, n_phase = r1["plan"].footprint(0)
     proj_bytes = 4.0 * (foot + n_phase)  # each layer pixel read once, each phase pixel written
@@ -363,7 +400,8 @@ def main():
                    "graph_replay": True, "pipelined_frames": r1["pipelined"]},
         "spots_per_s": frames_per_s * subaps,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": recorded_traffic(traffic_key),
                      "kernel": kern_name,
                      "kernel_ms": kern_ms,
                      "algorithmic_flop_per_launch": flops,
@@ -379,7 +417,8 @@ def main():
                        r1["project_ms"], "algorithmic_bytes_per_launch": proj_bytes,
                        "achieved": proj_bytes / (r1["project_ms"] * 1e-3) / 1e9,
                        "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                       "frac": proj_bytes / (r1["project_ms"] * 1e-3) / PEAK_HBM},
+                       "frac": proj_bytes / (r1["project_ms"] * 1e-3) / PEAK_HBM,
+                       "traffic": recorded_traffic("wfs_project_kernel")},
     }
     if not args.quick:
         try:

@@ -51,15 +51,15 @@ int otf_lds_bytes(int ns, int n_layers, int n_pix) {
   return otf_lds_layout(ns, n_layers, n_pix).total;
 }
 
-int project_lds_bytes(int n_layers, int rows) {
-  return n_layers * (kProjStrip + rows) * (int)sizeof(Tap);
+int project_lds_bytes(int n_layers) {
+  return n_layers * (kProjStrip + kProjRows) * (int)sizeof(Tap);
 }
 
 int project_strip() { return kProjStrip; }
 int project_rows() { return kProjRows; }
 
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st) {
-  const int64_t blocks = (int64_t)p.proj.per_real * p.batch;
+  const int64_t blocks = (int64_t)p.proj_per_real * p.batch;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(wfs_project_kernel, dim3((unsigned)blocks), dim3(kBlock), lds, st, p, phase);
   return hipGetLastError();

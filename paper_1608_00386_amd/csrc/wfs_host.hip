@@ -18,7 +18,7 @@
 namespace wfs {
 hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st);
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
-int project_lds_bytes(int n_layers, int rows);
+int project_lds_bytes(int n_layers);
 int project_strip();
 int project_rows();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
@@ -57,6 +57,17 @@ static int hip_fail(hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(_e, what); \
   } while (0)
 
+// projection blocks of one realisation (device descriptors)
+struct ProjTable {
+  const int2* desc = nullptr;
+  int32_t per_real = 0;
+};
+
+static void set_proj(FwdParams& p, const ProjTable& t) {
+  p.proj_desc = t.desc;
+  p.proj_per_real = t.per_real;
+}
+
 struct wfs_plan_s {
   int device = 0;
   int32_t n_layers = 0, n_sensors = 0, batch = 0;
@@ -80,7 +91,7 @@ struct wfs_plan_s {
   int adj_lds_per_wave = 0;
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
-  TaskTable proj_all{}, proj_fft{};
+  ProjTable proj_all{}, proj_fft{};
   float* d_phase = nullptr;   // split-mode phase buffer [B][phase_per_real]
   float* d_phase2 = nullptr;  // second buffer (pipelined frames), same allocation
   int split = 0;             // 1: projection kernel + spot kernel; 0: fused gather
@@ -160,8 +171,9 @@ static int validate(const wfs_layer_desc* layers, int32_t n_layers, int64_t laye
   if (!(dt_s >= 0) || !finite_d(dt_s)) return fail(WFS_EINVAL, "wfs_plan: dt_s must be >= 0");
   for (int l = 0; l < n_layers; ++l) {
     const wfs_layer_desc& L = layers[l];
-    if (L.nx < 2 || L.ny < 2 || L.nx > (1 << 20) || L.ny > (1 << 20))
-      return fail(WFS_EINVAL, "layer %d: grid %dx%d", l, L.nx, L.ny);
+    if (L.nx < 2 || L.ny < 2 || L.nx > (1 << 20) || L.ny > (1 << 20) ||
+        (int64_t)L.nx * L.ny > (1LL << 29))  // byte offsets within a layer fit 31 bits
+      return fail(WFS_EINVAL, "layer %d: grid %dx%d (at most 2^29 pixels)", l, L.nx, L.ny);
     if (L.offset < 0 || L.offset + (int64_t)L.nx * L.ny > layer_stride)
       return fail(WFS_EINVAL, "layer %d: grid [%lld, +%lld) outside the stride %lld", l,
                   (long long)L.offset, (long long)L.nx * L.ny, (long long)layer_stride);
@@ -280,7 +292,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<uint8_t> masks;
   std::vector<float2> stab, wtab;
   std::vector<int> otf_ids, fft_ids;
-  std::vector<int32_t> subidx, proj_tasks, proj_task_off, proj_task_count;
+  std::vector<int32_t> subidx;
+  std::vector<std::vector<int2>> proj_desc_s(n_sensors);  // projection blocks per sensor
   int32_t slope_off = 0, aux_off = 0;
   int64_t phase_off = 0;
   int otf_ns = 0;
@@ -312,6 +325,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     // projection blocks: (group of project_rows() pupil rows, strip of project_strip()
     // columns) holding at least one pixel of a valid subaperture; packed row0 | strip << 16
     d.proj_rows = project_rows();
+    d.inv_nsub = 1.0f / (float)S.n_sub;
     d.subidx_off = (int32_t)subidx.size();
     {
       std::vector<int32_t> idx((size_t)S.n_sa * S.n_sa, -1);
@@ -319,17 +333,14 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       subidx.insert(subidx.end(), idx.begin(), idx.end());
       const int W = project_strip(), RG = d.proj_rows;
       const int strips = (g.n_pup + W - 1) / W;
-      proj_task_off.push_back((int32_t)proj_tasks.size());
-      d.ptask_off = proj_task_off.back();
       for (int r0 = 0; r0 < g.n_pup; r0 += RG)
         for (int st = 0; st < strips; ++st) {
           bool any = false;
           for (int r = r0; r < std::min(g.n_pup, r0 + RG) && !any; ++r)
             for (int c = st * W; c < std::min(g.n_pup, (st + 1) * W) && !any; ++c)
               any = idx[(size_t)(r / S.n_sub) * S.n_sa + c / S.n_sub] >= 0;
-          if (any) proj_tasks.push_back(r0 | (st << 16));
+          if (any) proj_desc_s[s].push_back(make_int2(r0 | (st << 16), s));
         }
-      proj_task_count.push_back((int32_t)proj_tasks.size() - proj_task_off.back());
     }
     if ((int64_t)masks.size() + (int64_t)g.mask.size() > (1LL << 31) - 1) {
       delete P;
@@ -419,7 +430,14 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   const size_t o_stab = push_table(blob, stab);
   const size_t o_wtab = push_table(blob, wtab);
   const size_t o_subidx = push_table(blob, subidx);
-  const size_t o_ptask = push_table(blob, proj_tasks);
+  std::vector<int2> desc_all, desc_fft;
+  for (int s = 0; s < n_sensors; ++s) {
+    desc_all.insert(desc_all.end(), proj_desc_s[s].begin(), proj_desc_s[s].end());
+    if (ds[s].path == kPathFft)
+      desc_fft.insert(desc_fft.end(), proj_desc_s[s].begin(), proj_desc_s[s].end());
+  }
+  const size_t o_pall = push_table(blob, desc_all);
+  const size_t o_pfft = push_table(blob, desc_fft);
   std::vector<int64_t> step0(1, 0);
   const size_t o_step = push_table(blob, step0);
   blob.resize((blob.size() + 255) & ~size_t(255));
@@ -443,7 +461,10 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.stab = reinterpret_cast<const float2*>(P->d_blob + o_stab);
   b.wtab = reinterpret_cast<const float2*>(P->d_blob + o_wtab);
   b.subidx = reinterpret_cast<const int32_t*>(P->d_blob + o_subidx);
-  b.proj_tasks = reinterpret_cast<const int32_t*>(P->d_blob + o_ptask);
+  P->proj_all.desc = reinterpret_cast<const int2*>(P->d_blob + o_pall);
+  P->proj_all.per_real = (int32_t)desc_all.size();
+  P->proj_fft.desc = reinterpret_cast<const int2*>(P->d_blob + o_pfft);
+  P->proj_fft.per_real = (int32_t)desc_fft.size();
   P->d_step = reinterpret_cast<int64_t*>(P->d_blob + o_step);
   b.step_dev = P->d_step;
   b.layer_stride = layer_stride;
@@ -454,20 +475,12 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.n_valid_total = P->n_valid_total;
   fill_tasks(b.otf, otf_ids, P->n_valid);
   fill_tasks(b.fft, fft_ids, P->n_valid);
-  {
-    std::vector<int> all_ids(n_sensors);
-    std::vector<int32_t> groups(n_sensors);
-    for (int s = 0; s < n_sensors; ++s) {
-      all_ids[s] = s;
-      groups[s] = proj_task_count[s];
-      const int lb = project_lds_bytes(n_layers, ds[s].proj_rows);
-      P->proj_lds = std::max(P->proj_lds, lb);
-      if (ds[s].path == kPathFft) P->proj_lds_fft = std::max(P->proj_lds_fft, lb);
-    }
-    fill_tasks(P->proj_all, all_ids, groups);
-    fill_tasks(P->proj_fft, fft_ids, groups);
-    b.proj = P->proj_all;
+  for (int s = 0; s < n_sensors; ++s) {
+    const int lb = project_lds_bytes(n_layers);
+    P->proj_lds = std::max(P->proj_lds, lb);
+    if (ds[s].path == kPathFft) P->proj_lds_fft = std::max(P->proj_lds_fft, lb);
   }
+  set_proj(b, P->proj_all);
   b.phase_per_real = P->phase_per_real;
   b.phase_in = nullptr;
   P->otf_tasks = (int64_t)b.otf.per_real * batch;
@@ -582,7 +595,7 @@ static FwdParams call_params(wfs_plan_t P, const float* layers, int64_t step, ui
 static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
   const bool split = P->split && P->d_phase;
   if (split || P->fft_tasks > 0) {  // FFT-path sensors always read the projected phase
-    p.proj = split ? P->proj_all : P->proj_fft;
+    set_proj(p, split ? P->proj_all : P->proj_fft);
     hipError_t e = launch_project(p, P->d_phase, split ? P->proj_lds : P->proj_lds_fft, st);
     if (e != hipSuccess) return e;
     p.phase_in = P->d_phase;
@@ -637,7 +650,7 @@ int wfs_forward_steps(wfs_plan_t P, const float* layers, int64_t step0, int32_t 
   float* buf[2] = {P->d_phase, P->d_phase2};
   {
     FwdParams p = frame(0);
-    p.proj = P->proj_all;
+    set_proj(p, P->proj_all);
     e = launch_project(p, buf[0], P->proj_lds, st);
   }
   for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
@@ -645,7 +658,7 @@ int wfs_forward_steps(wfs_plan_t P, const float* layers, int64_t step0, int32_t 
     p.phase_in = buf[k & 1];
     p.otf_from_phase = 1;
     if (k + 1 < n_steps) {
-      p.proj = P->proj_all;
+      set_proj(p, P->proj_all);
       p.proj_blocks = P->proj_all.per_real * P->batch;
       p.phase_out = buf[(k + 1) & 1];
     }
@@ -742,7 +755,7 @@ int wfs_project(wfs_plan_t P, const float* layers, int64_t step, float* phase, v
     return fail(WFS_EUNSUPPORTED, "wfs_project: %d bytes of LDS per block exceed 64 KiB",
                 P->proj_lds);
   FwdParams p = call_params(P, layers, step, 0, nullptr, nullptr);
-  p.proj = P->proj_all;
+  set_proj(p, P->proj_all);
   hipError_t e = launch_project(p, phase, P->proj_lds, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_project: launch");
   return WFS_OK;
@@ -793,7 +806,7 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   a.f.lds_per_wave = P->adj_lds_per_wave;
   hipError_t e = hipSuccess;
   if (P->split && P->d_phase) {  // subaperture fields from the projection kernel's phase
-    a.f.proj = P->proj_all;
+    set_proj(a.f, P->proj_all);
     e = launch_project(a.f, P->d_phase, P->proj_lds, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: projection launch");
     a.f.phase_in = P->d_phase;

@@ -46,8 +46,9 @@ struct DevSensor {
   int32_t wtab_off;  // first entry of this sensor's n_pix-point twiddle table
   float inv_npix;    // 1 / n_pix
   int32_t subidx_off;  // first entry of this sensor's [n_sa][n_sa] valid-index table (-1 = unused)
-  int32_t ptask_off;   // first entry of this sensor's projection block list
-  int32_t pad3, pad4, pad5;
+  int32_t pad2;
+  float inv_nsub;    // 1 / n_sub
+  int32_t pad4, pad5;
 };
 
 struct DevSubap {
@@ -98,8 +99,9 @@ struct FwdParams {
   int32_t otf_from_phase;   // lag-domain path reads phase_in (split mode) instead of gathering
   TaskTable otf;
   TaskTable fft;
-  TaskTable proj;            // projection blocks per sensor (strips of pupil columns x rows)
-  const int32_t* proj_tasks; // packed (first pupil row, column strip) of each block
+  // projection blocks of one realisation: (first pupil row | column strip << 16, sensor)
+  const int2* proj_desc;
+  int32_t proj_per_real;
   const int32_t* subidx;     // valid-subaperture index of (sensor, a, b), -1 if not valid
   const float* phase_in;     // split mode: phase of every valid pixel (kappa applied), or null
   int64_t phase_per_real;    // floats per realisation in the phase buffer

@@ -80,6 +80,7 @@ def _set(which, key, value):
     (_set("layer", "boundary", 3), "boundary"),
     (_set("layer", "pitch_m", 0.0), "geometry"),
     (_set("layer", "nx", 1), "grid"),
+    (lambda l, s, st, lam: (l[0].update(nx=1 << 15, ny=1 << 15) or 1 << 31, lam), "2^29"),
     (lambda l, s, st, lam: (100, lam), "outside the stride"),
     (lambda l, s, st, lam: (st, -1.0), "lambda_ref"),
 ])
