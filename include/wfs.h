@@ -158,8 +158,8 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
  * wfs_plan_schedule -- the launch schedule the plan currently uses (set at creation, changed
  *   by wfs_plan_tune): split = 1 when a frame is the projection kernel followed by the spot
  *   kernel, 0 when the spot kernel gathers the layers itself; subaperture tasks per wave of the
- *   lag-domain kernel; xcd_remap = 1 when blocks are renumbered so neighbouring tasks share an
- *   XCD.  Any output pointer may be NULL.
+ *   lag-domain kernel (1 in this version); xcd_remap = 1 when blocks are renumbered so
+ *   neighbouring tasks share an XCD.  Any output pointer may be NULL.
  */
 int wfs_plan_schedule(wfs_plan_t plan, int32_t* split, int32_t* subaps_per_wave,
                       int32_t* xcd_remap);
@@ -199,7 +199,7 @@ int wfs_set_step(wfs_plan_t plan, int64_t step, void* stream);
 int wfs_advance_step(wfs_plan_t plan, int64_t delta, void* stream);
 
 /*
- * wfs_plan_tune -- time the launch schedules (subapertures per wave, block order, path where
+ * wfs_plan_tune -- time the launch schedules (block order, split or fused projection where
  *   both apply) on `layers` and keep the fastest in the plan.  Synchronises; writes scratch
  *   slopes internally.  iters: timed launches per candidate.  On return *best_us holds the
  *   best time per forward call (may be NULL).

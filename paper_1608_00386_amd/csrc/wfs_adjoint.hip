@@ -181,12 +181,8 @@ __global__ __launch_bounds__(kBlock) void wfs_adjoint_kernel(AdjParams ap) {
   char* wsm = smem + wave * p.lds_per_wave;
   const int total = p.otf.per_real * p.batch;
   const int L = p.xcd_remap ? xcd_logical_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int t0 = (L * kWavesPerBlock + wave) * p.subaps_per_wave;
-  for (int k = 0; k < p.subaps_per_wave; ++k) {
-    const int t = t0 + k;
-    if (t >= total) break;
-    otf_adjoint_subap<NS, FUSED>(ap, t, step, wsm);
-  }
+  const int t = L * kWavesPerBlock + wave;  // one subaperture per wave
+  if (t < total) otf_adjoint_subap<NS, FUSED>(ap, t, step, wsm);
 }
 
 __global__ __launch_bounds__(kBlock) void zero_kernel(float* x, int64_t n) {
@@ -203,8 +199,7 @@ static hipError_t launch_adj(AdjParams a, hipStream_t st) {
   if (e != hipSuccess) return e;
   const int64_t tasks = (int64_t)a.f.otf.per_real * a.f.batch;
   if (tasks == 0) return hipSuccess;
-  const int spw = a.f.subaps_per_wave;
-  const int64_t waves = (tasks + spw - 1) / spw;
+  const int64_t waves = tasks;
   const int grid = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   if (a.f.otf_from_phase)
     hipLaunchKernelGGL((wfs_adjoint_kernel<NS, false>), dim3(grid), dim3(kBlock),

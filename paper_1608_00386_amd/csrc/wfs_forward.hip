@@ -47,8 +47,8 @@ hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st) {
   }
 }
 
-int otf_lds_bytes(int ns, int n_layers, int n_pix) {
-  return otf_lds_layout(ns, n_layers, n_pix).total;
+int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps) {
+  return otf_lds_layout(ns, n_layers, n_pix, with_taps).total;
 }
 
 int project_lds_bytes(int n_layers) {

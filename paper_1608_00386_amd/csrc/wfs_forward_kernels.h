@@ -16,14 +16,17 @@
 namespace wfs {
 
 // Split-schedule lag-domain kernels are held to 5 waves per SIMD for n_sub <= 10 (<= 96
-// VGPRs; their LDS, < 8 KB per wave, allows 5 four-wave blocks per CU), fewer above: the spot
-// stage is VALU-bound with short dependent LDS phases, and the extra waves hide them.
-template <int NS>
-constexpr int otf_waves_per_simd() { return NS <= 10 ? 5 : (NS == 11 ? 4 : 3); }
+// VGPRs; their LDS, < 7 KB per wave, lets 5 four-wave blocks share a CU), fewer above.
+// Measured on config 1: splitting the lag row in 3 or 4 passes to fit 7 or 8 waves per SIMD
+// made the kernel slower (the spot stage is bound by VALU issue, not by latency).
+template <int NS, bool PROJ>
+constexpr int otf_waves_per_simd() {
+  return NS <= 10 ? 5 : (NS == 11 ? 4 : 3);
+}
 
 template <int NS, bool FUSED, bool FFT, bool PROJ>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((FUSED || FFT) ? 1 : otf_waves_per_simd<NS>())))
+__attribute__((amdgpu_waves_per_eu((FUSED || FFT) ? 1 : otf_waves_per_simd<NS, PROJ>())))
 void wfs_forward_kernel(
     FwdParams p) {
   extern __shared__ __align__(16) char smem[];
@@ -53,12 +56,10 @@ void wfs_forward_kernel(
   const int wave = threadIdx.x >> 6;
   char* wsm = smem + wave * p.lds_per_wave;
   const int total = p.otf.per_real * p.batch;
-  const int t0 = (L * kWavesPerBlock + wave) * p.subaps_per_wave;
-  for (int k = 0; k < p.subaps_per_wave; ++k) {
-    const int t = t0 + k;
-    if (t >= total) break;
-    otf_subap<NS, FUSED>(p, t, step, wsm);
-  }
+  // one subaperture per wave and no task loop: a loop would let the compiler hoist per-lane
+  // index arithmetic out of it and hold those registers across every stage
+  const int t = L * kWavesPerBlock + wave;
+  if (t < total) otf_subap<NS, FUSED>(p, t, step, wsm);
 }
 
 template <int NS, bool FUSED, bool FFT, bool PROJ>

@@ -26,7 +26,7 @@ hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
                         int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma);
-int otf_lds_bytes(int ns, int n_layers, int n_pix);
+int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps);
 int fft_lds_bytes(int n_sub, int n_fft, int n_pix);
 bool fft_supported(int n_sub, int n_fft, int bin);
 }  // namespace wfs
@@ -89,6 +89,7 @@ struct wfs_plan_s {
   int otf_max_npix = 0;
   int64_t otf_tasks = 0, fft_tasks = 0;
   int adj_lds_per_wave = 0;
+  int lds_split = 0, lds_fused = 0;  // LDS bytes per lag-domain wave, per schedule
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
   ProjTable proj_all{}, proj_fft{};
@@ -239,11 +240,8 @@ static void fill_tasks(TaskTable& tt, const std::vector<int>& ids, const std::ve
 
 static void default_schedule(wfs_plan_s* P) {
   const int64_t tasks = P->otf_tasks;
-  int spw = 1;
-  // enough waves to cover ~8 wavefronts per SIMD on 256 CUs before batching tasks per wave
-  while (tasks / spw > 256LL * 4 * 8 * 2 && spw < 64) spw *= 2;
-  P->base.subaps_per_wave = spw;
-  const int64_t waves = (tasks + spw - 1) / spw;
+  P->base.subaps_per_wave = 1;  // one subaperture per wavefront
+  const int64_t waves = tasks;
   P->base.otf_blocks = (int32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   P->base.xcd_remap = (P->flags & WFS_FLAG_NO_XCD_REMAP) ? 0 : 1;
 }
@@ -291,6 +289,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<DevSubap> subs;
   std::vector<uint8_t> masks;
   std::vector<float2> stab, wtab;
+  std::vector<float> mtab;
   std::vector<int> otf_ids, fft_ids;
   std::vector<int32_t> subidx;
   std::vector<std::vector<int2>> proj_desc_s(n_sensors);  // projection blocks per sensor
@@ -394,6 +393,32 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       const double sg = (std::abs(k) % 2) ? -1.0 : 1.0;
       stab.push_back(make_float2((float)(sg * re), (float)(sg * im)));
     }
+    // image operands for the matrix cores (n_pix <= 8): with C = cos, S = sin of
+    // 2 pi (k n mod n_pix) / n_pix, F1 = [[C, S], [-S, C]] (Z = [Pr|Pi] F1 gives [Zr|Zi]) and
+    // F2 = [C | -S] (B = F2 [Zr; Zi]), each 16 x 16 row-major, zero outside n_pix
+    d.mtab_off = -1;
+    if (d.n_pix <= 8) {
+      d.mtab_off = (int32_t)mtab.size();
+      const int np = d.n_pix;
+      auto cs = [&](int a, int b2, bool sine) {
+        if (a >= np || b2 >= np) return 0.0f;
+        const double t = 2.0 * M_PI * ((a * b2) % np) / np;
+        return (float)(sine ? std::sin(t) : std::cos(t));
+      };
+      for (int k = 0; k < 16; ++k)
+        for (int n = 0; n < 16; ++n) {
+          const int kk = k & 7, nn = n & 7;
+          float v;
+          if (k < 8) v = n < 8 ? cs(kk, nn, false) : cs(kk, nn, true);
+          else v = n < 8 ? -cs(kk, nn, true) : cs(kk, nn, false);
+          mtab.push_back(v);
+        }
+      for (int m = 0; m < 16; ++m)
+        for (int k = 0; k < 16; ++k) {
+          const int mm = m & 7, kk = k & 7;
+          mtab.push_back(m >= 8 ? 0.0f : (k < 8 ? cs(mm, kk, false) : -cs(mm, kk, true)));
+        }
+    }
     d.wtab_off = (int32_t)wtab.size();
     for (int t = 0; t < d.n_pix; ++t) {
       const double a = 2.0 * M_PI * t / d.n_pix;
@@ -429,6 +454,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   const size_t o_mask = push_table(blob, masks);
   const size_t o_stab = push_table(blob, stab);
   const size_t o_wtab = push_table(blob, wtab);
+  const size_t o_mtab = push_table(blob, mtab);
   const size_t o_subidx = push_table(blob, subidx);
   std::vector<int2> desc_all, desc_fft;
   for (int s = 0; s < n_sensors; ++s) {
@@ -460,6 +486,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.mask = reinterpret_cast<const uint8_t*>(P->d_blob + o_mask);
   b.stab = reinterpret_cast<const float2*>(P->d_blob + o_stab);
   b.wtab = reinterpret_cast<const float2*>(P->d_blob + o_wtab);
+  b.mtab = reinterpret_cast<const float*>(P->d_blob + o_mtab);
   b.subidx = reinterpret_cast<const int32_t*>(P->d_blob + o_subidx);
   P->proj_all.desc = reinterpret_cast<const int2*>(P->d_blob + o_pall);
   P->proj_all.per_real = (int32_t)desc_all.size();
@@ -490,21 +517,27 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     delete P;
     return fail(WFS_EINVAL, "wfs_plan: too many subaperture tasks");
   }
-  // LDS: lag-domain waves and FFT workgroups share one dynamic allocation
-  int lds_wave = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix) : 0;
+  // LDS: lag-domain waves and FFT workgroups share one dynamic allocation; the split
+  // schedule's waves need no tap region (the fused gather does)
   int lds_fft = 0;
   for (int s : fft_ids)
     lds_fft = std::max(lds_fft, fft_lds_bytes(sensors[s].n_sub, sensors[s].n_fft,
                                               sensors[s].n_fft / sensors[s].bin));
-  lds_wave = std::max(lds_wave, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
-  lds_wave = (lds_wave + 15) & ~15;
+  auto wave_lds = [&](bool taps) {
+    int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps) : 0;
+    w = std::max(w, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
+    return (w + 15) & ~15;
+  };
+  const int lds_wave = wave_lds(true);
   if (lds_wave * kWavesPerBlock > 65536) {
     (void)hipFree(P->d_blob);
     delete P;
     return fail(WFS_EUNSUPPORTED, "wfs_plan: %d bytes of LDS per workgroup exceed 64 KiB",
                 lds_wave * kWavesPerBlock);
   }
-  b.lds_per_wave = lds_wave;
+  P->lds_fused = lds_wave;
+  P->lds_split = wave_lds(false);
+  b.lds_per_wave = P->lds_split;
   P->adj_lds_per_wave = otf_ns ? ((adj_lds_bytes(otf_ns, n_layers, P->otf_max_npix) + 15) & ~15) : 16;
   if (P->adj_lds_per_wave * kWavesPerBlock > 65536) P->adj_lds_per_wave = 0;  // adjoint unsupported
   // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
@@ -601,6 +634,7 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
     p.phase_in = P->d_phase;
   }
   p.otf_from_phase = split ? 1 : 0;
+  p.lds_per_wave = split ? P->lds_split : P->lds_fused;
   return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
 }
 
@@ -838,7 +872,6 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   const FwdParams keep = P->base;
   FwdParams best = keep;
   double best_t = 1e30;
-  const int spws[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
   const int keep_split = P->split;
   int best_split = keep_split;
   for (int mode = 0; mode < 4; ++mode) {
@@ -846,12 +879,8 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
     P->split = (mode >> 1) & 1;
     if (P->split && (!P->d_phase || P->proj_lds > 65536)) continue;
     if (P->flags & WFS_FLAG_FUSED) P->split = 0;
-    for (int spw : spws) {
-      const int64_t waves = (P->otf_tasks + spw - 1) / spw;
-      if (spw > 1 && waves < 256) break;
+    {
       FwdParams c = keep;
-      c.subaps_per_wave = spw;
-      c.otf_blocks = (int32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
       c.xcd_remap = remap;
       P->base = c;
       FwdParams p = call_params(P, layers, 0, 1, slopes, aux);
@@ -869,7 +898,6 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
         best = c;
         best_split = P->split;
       }
-      if (P->otf_tasks == 0) break;
     }
     if (e != hipSuccess) break;
   }

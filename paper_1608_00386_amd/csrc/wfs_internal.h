@@ -14,6 +14,7 @@ constexpr int kMaxSensors = 64;
 constexpr int kOtfMaxNsub = 12;    // lag-domain path: subapertures up to 12 x 12 pixels
 constexpr int kFftMaxNsub = 64;    // FFT path: fields up to 64 x 64 pixels
 constexpr int kFftMaxN = 128;      // FFT path: transforms up to 128 points per axis
+constexpr int kOtfLagParts = 2;    // lag-domain path: passes over each lag row
 
 enum Path : int32_t { kPathOtf = 0, kPathFft = 1 };
 
@@ -48,7 +49,8 @@ struct DevSensor {
   int32_t subidx_off;  // first entry of this sensor's [n_sa][n_sa] valid-index table (-1 = unused)
   int32_t pad2;
   float inv_nsub;    // 1 / n_sub
-  int32_t pad4, pad5;
+  int32_t mtab_off;  // matrix-core image operands (n_pix <= 8), -1: vector path
+  int32_t pad5;
 };
 
 struct DevSubap {
@@ -78,6 +80,7 @@ struct FwdParams {
   const uint8_t* mask;
   const float2* stab;
   const float2* wtab;
+  const float* mtab;        // per sensor: the 16x16 operands of the two image products
   const int64_t* step_dev;  // read when use_dev_step
   int64_t step;
   int32_t use_dev_step;
@@ -93,7 +96,7 @@ struct FwdParams {
   // schedule
   int32_t otf_blocks;       // blocks serving the lag-domain tasks
   int32_t fft_blocks;       // blocks serving FFT tasks (one subaperture each), launched first
-  int32_t subaps_per_wave;  // lag-domain tasks per wave (contiguous)
+  int32_t subaps_per_wave;  // lag-domain tasks per wave (always 1)
   int32_t xcd_remap;
   int32_t lds_per_wave;     // bytes
   int32_t otf_from_phase;   // lag-domain path reads phase_in (split mode) instead of gathering

@@ -28,6 +28,8 @@ template <int NS>
 struct Otf {
   static constexpr int kJobs = NS * (NS + 1) / 2;  // row pairs (dy, r), dy >= 0
   static constexpr int kLags = 2 * NS - 1;         // dx = -(NS-1) .. NS-1
+  static constexpr int kParts = kOtfLagParts;        // passes over the lag row
+  static constexpr int kChunk = (kLags + kParts - 1) / kParts;  // lag columns per pass
   static constexpr int kRounds = (kJobs + kWave - 1) / kWave;
   static constexpr int kJobsPerRound = (kJobs + kRounds - 1) / kRounds;
 };
@@ -40,13 +42,16 @@ __host__ __device__ constexpr int otf_jobs_per_round(int ns) {
 // Per-wave LDS layout (bytes), shared with the host sizing code:
 //   E [n_sub^2] float2 | tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2 |
 //   AW [n_sub][2 n_sub - 1] float2 (weighted lag sums) |
-//   union( taps [n_layers][2 n_sub] Tap ,  partial lag rows (one round, half of the lags at
-//   a time: [jobs][n_sub] float2) + P (later B) + Z )
+//   union( taps [n_layers][2 n_sub] Tap (fused gather and adjoint only),
+//          partial lag rows (one round, one pass over the lag row at a time:
+//          [jobs][ceil((2 n_sub - 1) / kOtfLagParts)] float2),
+//          P (later B) + Z (after the last round) )
 struct OtfLds {
   int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off, total;
 };
 
-__host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix) {
+__host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix,
+                                                 bool with_taps = true) {
   OtfLds o;
   const int jobs = otf_jobs_per_round(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
@@ -55,14 +60,16 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   o.aw_off = o.wtab_off + n_pix * 8;
   const int u0 = (o.aw_off + ns * lags * 8 + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
-  const int part = jobs * ns * 8;
+  const int part = jobs * ((lags + kOtfLagParts - 1) / kOtfLagParts) * 8;
   o.taps_off = u0;
   o.part_off = u0;
-  o.p_off = u0 + part;
+  o.p_off = u0;  // the fold writes P after the last round has read its partial rows
   o.z_off = o.p_off + np2 * 8;
   o.b_off = o.p_off;  // B overwrites P: the image's second pass reads only Z
   int end = o.z_off + np2 * 8;
-  if (u0 + taps > end) end = u0 + taps;
+  if (o.p_off + 1024 > end) end = o.p_off + 1024;  // matrix-core image: 16 x 16 floats
+  if (u0 + part > end) end = u0 + part;
+  if (with_taps && u0 + taps > end) end = u0 + taps;
   o.total = (end + 15) & ~15;
   return o;
 }
@@ -220,7 +227,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
 }
 
 // Lag sums of one round of row-pair jobs for the lag columns [IX0, IX0 + W) (held in the
-// partial-row region, W columns per job), times the elongation and binning factors:
+// partial-row region, kChunk columns per job), times the elongation and binning factors:
 // AW[dy][dx] (+)= w_dy Kel(dx, dy) s(dx) s(dy) sum_r part, lane per lag (dy, dx).
 template <int NS, int IX0, int W>
 __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& sb, char* wsm,
@@ -230,29 +237,62 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
   const float2* part = reinterpret_cast<const float2*>(wsm + lo.part_off);
   const float2* stab = reinterpret_cast<const float2*>(wsm + lo.stab_off);
   float2* aw = reinterpret_cast<float2*>(wsm + lo.aw_off);
+  // weighted lag value at (dy, column ix) from the row sum a
+  auto weigh = [&](int dy, int ix, float2 a) {
+    const int dx = ix - (NS - 1);
+    const float2 sx = stab[ix], sy = stab[dy + NS - 1];
+    const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
+    const float kel = __expf(-sb.alpha * proj * proj) * (dy == 0 ? 1.0f : 2.0f);
+    const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
+    const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
+    return make_float2(a.x * tr - a.y * ti, a.x * ti + a.y * tr);
+  };
+  if constexpr (Otf<NS>::kRounds == 1) {
+    // every job in one round: lane per (pair of lag rows dy and NS-1-dy, column).  The two
+    // rows hold NS - dy and dy + 1 jobs, so each lane sums exactly NS + 1 partial rows.
+    constexpr int NQ = (NS + 1) / 2;
+    static_assert(NQ * W <= kWave, "one pass");
+    const int q = lane / W, k = lane - q * W;
+    if (q < NQ) {
+      const int dyA = q, dyB = NS - 1 - q, nA = NS - q;
+      const int baseA = job_base<NS>(dyA), baseB = job_base<NS>(dyB) - nA;
+      float2 a = make_float2(0.0f, 0.0f), bsum = make_float2(0.0f, 0.0f);
+#pragma unroll
+      for (int t = 0; t <= NS; ++t) {
+        const bool inA = t < nA;
+        const float2 v = part[((inA ? baseA : baseB) + t) * Otf<NS>::kChunk + k];
+        if (inA) {
+          a.x += v.x;
+          a.y += v.y;
+        } else {
+          bsum.x += v.x;
+          bsum.y += v.y;
+        }
+      }
+      aw[dyA * NL + IX0 + k] = weigh(dyA, IX0 + k, a);
+      if (dyB != dyA) aw[dyB * NL + IX0 + k] = weigh(dyB, IX0 + k, bsum);
+    }
+    wave_sync();
+    return;
+  }
   const int j1 = j0 + Otf<NS>::kJobsPerRound;
 #pragma unroll
   for (int o0 = 0; o0 < NS * W; o0 += kWave) {
     const int o = o0 + lane;
     if (o < NS * W) {
-      const int dy = o / W, k = o - dy * W, ix = IX0 + k, dx = ix - (NS - 1);
+      const int dy = o / W, k = o - dy * W, ix = IX0 + k;
       const int base = job_base<NS>(dy);
       const int r0 = max(0, j0 - base), r1 = min(NS - dy, j1 - base);
       float2 a = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
         if (r >= r0 && r < r1) {
-          const float2 v = part[(base + r - j0) * NS + k];
+          const float2 v = part[(base + r - j0) * Otf<NS>::kChunk + k];
           a.x += v.x;
           a.y += v.y;
         }
       }
-      const float2 sx = stab[ix], sy = stab[dy + NS - 1];
-      const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
-      const float kel = __expf(-sb.alpha * proj * proj) * (dy == 0 ? 1.0f : 2.0f);
-      const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
-      const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
-      float2 t = make_float2(a.x * tr - a.y * ti, a.x * ti + a.y * tr);
+      float2 t = weigh(dy, ix, a);
       const int oa = dy * NL + ix;
       if (j0 > 0) {
         const float2 prev = aw[oa];
@@ -267,11 +307,11 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
 
 // One round of autocorrelation row-pair jobs [j0, j0 + jobs per round), lag columns
 // [IX0, IX0 + W): lane per (dy, r) forms sum_c E[r][c] conj(E[r+dy][c+dx]) for those dx in
-// registers and leaves them in the partial-row region, then the lag sums over r.  Splitting
-// the lag columns in two halves keeps both the registers and the LDS region at half a lag row
-// per job, at the same number of multiply-adds.
+// registers and leaves them in the partial-row region, then the lag sums over r.  Taking the
+// lag row in kOtfLagParts passes keeps the registers and the LDS region at that fraction of a
+// row per job, at the same number of multiply-adds.
 template <int NS, int IX0, int W>
-__device__ __forceinline__ void otf_corr_half(const DevSensor& S, const DevSubap& sb,
+__device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap& sb,
                                               char* wsm, const OtfLds& lo, int j0) {
   const int lane = lane_id();
   const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
@@ -302,17 +342,19 @@ __device__ __forceinline__ void otf_corr_half(const DevSensor& S, const DevSubap
       }
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) part[lane * NS + k] = acc[k];
+    for (int k = 0; k < W; ++k) part[lane * Otf<NS>::kChunk + k] = acc[k];
   }
   wave_sync();
   otf_lagsum<NS, IX0, W>(S, sb, wsm, lo, j0);
 }
 
-template <int NS>
+template <int NS, int IX0 = 0>
 __device__ __forceinline__ void otf_corr_round(const DevSensor& S, const DevSubap& sb,
                                                char* wsm, const OtfLds& lo, int j0) {
-  otf_corr_half<NS, 0, NS>(S, sb, wsm, lo, j0);
-  otf_corr_half<NS, NS, NS - 1>(S, sb, wsm, lo, j0);
+  constexpr int NL = Otf<NS>::kLags, CW = Otf<NS>::kChunk;
+  constexpr int W = IX0 + CW <= NL ? CW : NL - IX0;
+  otf_corr_part<NS, IX0, W>(S, sb, wsm, lo, j0);
+  if constexpr (IX0 + W < NL) otf_corr_round<NS, IX0 + W>(S, sb, wsm, lo, j0);
 }
 
 // Fold modulo n_pix: P[Ky][Kx] = sum over lags (dy, dx) = (Ky, Kx) mod n_pix of AW, lane per K.
@@ -339,9 +381,64 @@ __device__ __forceinline__ void otf_fold(const DevSensor& S, char* wsm, const Ot
   wave_sync();
 }
 
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// B[q] = c Re sum_K P[K] W^{K.q} on the matrix cores (n_pix <= 8), as two real 16 x 16 x 16
+// products of four v_mfma_f32_16x16x4f32 each:  [Zr | Zi] = [Pr | Pi] F1 with
+// F1 = [[C, S], [-S, C]], then B = c F2 [Zr ; Zi] with F2 = [C | -S] (C, S: cosine and sine of
+// 2 pi (k n mod n_pix) / n_pix, per-sensor tables).  Operand layout: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; accumulator i of lane l holds D[4 (l/16) + i][l%16].
+// The intermediate [Zr | Zi] goes through LDS over the P and Z regions.
+__device__ __forceinline__ void otf_image_mfma(const FwdParams& p, const DevSensor& S,
+                                               char* wsm, const OtfLds& lo) {
+  const int lane = lane_id();
+  const int np = S.n_pix;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const float* F1 = p.mtab + S.mtab_off;
+  const float* F2 = F1 + 256;
+  const float2* P = reinterpret_cast<const float2*>(wsm + lo.p_off);
+  float* D = reinterpret_cast<float*>(wsm + lo.p_off);  // [16][16]
+  float* B = reinterpret_cast<float*>(wsm + lo.b_off);
+  float a[4], f[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = kq + 4 * s, kk = k & 7;
+    const float2 v = (r16 < np && kk < np) ? P[r16 * np + kk] : make_float2(0.0f, 0.0f);
+    a[s] = k < 8 ? v.x : v.y;
+    f[s] = F1[k * 16 + r16];
+  }
+  v4f_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], f[s], acc, 0, 0, 0);
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) D[(4 * kq + i) * 16 + r16] = acc[i];
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = kq + 4 * s;
+    f[s] = F2[r16 * 16 + k];
+    a[s] = k < 8 ? D[k * 16 + (r16 & 7)] : D[(k - 8) * 16 + 8 + (r16 & 7)];
+  }
+  acc = (v4f_t){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(f[s], a[s], acc, 0, 0, 0);
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int qy = 4 * kq + i;
+    if (qy < np && r16 < np) B[qy * np + r16] = S.flux_c * acc[i];
+  }
+  wave_sync();
+}
+
 // B[q] = c Re sum_K P[K] W^{K.q}, separable through Z[Ky][qx] (W = e^{2 pi i / n_pix}).
 __device__ __forceinline__ void otf_image(const FwdParams& p, const DevSensor& S, char* wsm,
                                           const OtfLds& lo) {
+  if (S.mtab_off >= 0) {
+    otf_image_mfma(p, S, wsm, lo);
+    return;
+  }
   const int lane = lane_id();
   const int np = S.n_pix, np2 = np * np;
   const float2* P = reinterpret_cast<const float2*>(wsm + lo.p_off);
