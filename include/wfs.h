@@ -51,6 +51,8 @@ enum {
 #define WFS_FLAG_NO_XCD_REMAP (1u << 2) /* keep the hardware block order (no per-XCD grouping)    */
 #define WFS_FLAG_FUSED (1u << 3)        /* project inside the spot kernel (no projection pass and
                                            no phase buffer); default: projection kernel first  */
+#define WFS_FLAG_ADJOINT_ATOMIC (1u << 4) /* wfs_adjoint scatters with FP32 atomics instead of
+                                           the deterministic gather                        */
 
 /* `step` value meaning "read the step from the plan's device-resident counter". */
 #define WFS_STEP_DEVICE (-1)
@@ -187,7 +189,10 @@ int wfs_project(wfs_plan_t plan, const float* layers, int64_t step, float* phase
  *   off).  Subaperture fields are recomputed from the layers.  fwd_slopes/fwd_aux: the
  *   noise-free forward outputs for the same layers and step (both given, or both NULL: then
  *   they are recomputed).  grad_layers: device [B][layer_stride], overwritten (zero outside
- *   the grids).  Uses floating-point atomics: reproducible to rounding, not bitwise.
+ *   the grids).  By default the phase gradients go through the plan's second phase buffer and
+ *   each layer pixel gathers its contributions in a fixed order: bitwise deterministic.  With
+ *   WFS_FLAG_ADJOINT_ATOMIC the taps are scattered with FP32 atomics (reproducible to
+ *   rounding, not bitwise).  Lag-domain sensors only (WFS_EUNSUPPORTED otherwise).
  */
 int wfs_adjoint(wfs_plan_t plan, const float* layers, const float* grad_slopes,
                 const float* fwd_slopes, const float* fwd_aux, int64_t step,

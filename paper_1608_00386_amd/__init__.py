@@ -2,6 +2,7 @@
 centroids, reconstructor) as hand-written HIP kernels behind the C ABI of include/wfs.h."""
 
 from ._lib import (  # noqa: F401
+    WFS_FLAG_ADJOINT_ATOMIC,
     WFS_FLAG_FORCE_FFT,
     WFS_FLAG_FUSED,
     WFS_FLAG_FORCE_OTF,

@@ -8,7 +8,11 @@
 //   dL     = Re sum_k U[k] dA[k],  dE[m] = i E[m] dpsi[m]
 //   =>  g_psi[p] = -2 Im(E[p] V[p]),   V[p] = sum_{m'} U[m' - p] conj(E[m'])
 // and the layer gradient is the transpose of the bilinear projection, kappa w_l times the
-// stencil weights, accumulated with floating-point atomics (subaperture fields recomputed).
+// stencil weights (subaperture fields recomputed).  Two ways to form it:
+//   gather (default): g_psi (kappa applied) goes to a phase-layout buffer, then one thread per
+//     layer pixel sums, sensor by sensor, the stencil weights of the pupil pixels whose
+//     forward taps touch it (the same FP64 taps as the forward) -- bitwise deterministic;
+//   atomic scatter: each pupil pixel adds its four weighted taps with FP32 atomics.
 #include "wfs_otf.h"
 
 namespace wfs {
@@ -62,7 +66,13 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
     cy = s0 > 0.0f ? c.sy / s0 : 0.0f;
   }
   wave_sync();
-  if (!(s0 > 0.0f) || (gx == 0.0f && gy == 0.0f)) return;  // wave-uniform
+  // gather mode: this subaperture's block of the sensor's pupil-frame gradient image
+  float* gout = ap.gpsi ? ap.gpsi + (int64_t)b * p.pupil_per_real + S.pupil_off +
+                              (int64_t)sb.a * NS * S.n_pup + sb.b * NS
+                        : nullptr;
+  if (!(s0 > 0.0f) || (gx == 0.0f && gy == 0.0f)) {  // wave-uniform: no gradient (the image
+    return;                                            // was cleared before the launch)
+  }
 
   const float half = 0.5f * (float)(np - 1);
   const float inv = 1.0f / s0;
@@ -125,14 +135,16 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
     const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
     U[t2] = make_float2(tr * g.x - ti * g.y, tr * g.y + ti * g.x);
   }
-  // taps again (the forward scratch region is free now)
+  // taps again (the forward scratch region is free now); the gather mode needs none
   const int nlay = p.n_layers;
   Tap* taps = reinterpret_cast<Tap*>(wsm + lo.taps_off);
   const double stepd = (double)step;
-  for (int t2 = lane; t2 < 2 * NS * nlay; t2 += kWave) {
-    const int l = t2 / (2 * NS), k = t2 - l * (2 * NS);
-    taps[t2] = (k < NS) ? col_tap(p, sid, l, sb.b * NS + k, stepd)
-                        : row_tap(p, sid, l, sb.a * NS + (k - NS), stepd);
+  if (!gout) {
+    for (int t2 = lane; t2 < 2 * NS * nlay; t2 += kWave) {
+      const int l = t2 / (2 * NS), k = t2 - l * (2 * NS);
+      taps[t2] = (k < NS) ? col_tap(p, sid, l, sb.b * NS + k, stepd)
+                          : row_tap(p, sid, l, sb.a * NS + (k - NS), stepd);
+    }
   }
   wave_sync();
   const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
@@ -155,6 +167,10 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
       }
     }
     const float gpsi = -2.0f * (e.x * V.y + e.y * V.x) * S.kappa;
+    if (gout) {
+      gout[r * S.n_pup + c] = gpsi;
+      continue;
+    }
     for (int l = 0; l < nlay; ++l) {
       const DevLayer& L = p.lay[l];
       const Tap cxt = taps[l * 2 * NS + c];
@@ -185,6 +201,219 @@ __global__ __launch_bounds__(kBlock) void wfs_adjoint_kernel(AdjParams ap) {
   if (t < total) otf_adjoint_subap<NS, FUSED>(ap, t, step, wsm);
 }
 
+// Gather tiles: kGTW layer columns x kGTH layer rows per block; wave w takes the rows
+// w, w + 4, ... (kGPix rows per thread).
+constexpr int kGTW = 64;
+constexpr int kGPix = 4;
+constexpr int kGTH = kGPix * kBlock / kGTW;
+constexpr int kGCols = 128;  // candidate pupil columns per pass
+constexpr int kGRows = 32;   // candidate pupil rows per pass
+
+// Candidate taps of a tile: pupil index k, the tap's lower index relative to the tile start
+// (floor(w) - m n - tile start, w the layer coordinate, m the periodic image) and the weight
+// of the upper neighbour.  The lower weight is 1 - w1, as in the forward's make_tap.
+struct GTap {
+  int32_t k, rel;
+  float w1;
+  int32_t pad;
+};
+
+// Exact forward tap of pupil index k against layer image m (see make_tap: for a periodic
+// grid the fractional part of the unwrapped coordinate equals that of the wrapped one; for a
+// zero boundary, candidates lie within a few pixels of the grid, where no clamping happens).
+__device__ __forceinline__ GTap gather_tap(double a, double b0, double db, double stepd,
+                                           int k, int64_t shift) {
+  const double w = fma(a, (double)k, b0) + stepd * db;
+  const double f0 = floor(w);
+  GTap t;
+  t.k = k;
+  t.rel = (int32_t)((int64_t)f0 - shift);
+  t.w1 = (float)(w - f0);
+  t.pad = 0;
+  return t;
+}
+
+// Pupil index range [lo, hi] whose coordinate w = a k + b (a > 0) falls in [t0 - 1, t1 + 1),
+// with one index of slack on each side, clamped to [0, npup).
+__device__ __forceinline__ void cand_range(double inv_a, double b, double t0, double t1,
+                                           int npup, int& lo, int& hi) {
+  // one index of slack on each side also covers the rounding of the reciprocal
+  const double lo_d = floor((t0 - 1.0 - b) * inv_a) - 1.0;
+  const double hi_d = ceil((t1 + 1.0 - b) * inv_a) + 1.0;
+  lo = lo_d < 0.0 ? 0 : (lo_d > (double)npup ? npup : (int)lo_d);
+  hi = hi_d < -1.0 ? -1 : (hi_d > (double)(npup - 1) ? npup - 1 : (int)hi_d);
+}
+
+// Periodic images m whose layer window [t0 - 1 + m n, t1 + 1 + m n) can meet the pupil's
+// coordinate range [w(0), w(npup - 1)]; a single image for a zero boundary.
+__device__ __forceinline__ void image_range(double a, double b, int n, double inv_n, int npup,
+                                            int t0, int t1, int boundary, int& m_lo,
+                                            int& m_hi) {
+  if (boundary != 0) {
+    m_lo = m_hi = 0;
+    return;
+  }
+  const double w0 = b, w1 = fma(a, (double)(npup - 1), b);
+  // floor / ceil of the bounds already include every image the rounding could move in
+  m_lo = (int)floor((w0 - t1 - 1.0) * inv_n);
+  m_hi = (int)ceil((w1 - t0 + 1.0) * inv_n);
+}
+
+// Layer gradient, gather form: block = (realisation, layer, kGTH x kGTW tile); thread =
+// layer pixel.  For every sensor, pass by pass over the tile's candidate pupil rows and
+// columns (every periodic image, kGRows x kGCols at a time): their exact forward taps and the
+// rectangle of the sensor's phase-gradient image they span go to LDS (one batch of coalesced
+// loads); then each wave (one layer row) walks the candidate rows, and each lane the few
+// candidate columns whose taps reach its pixel, summing weight x gradient in a fixed order.
+__global__ __launch_bounds__(kBlock) void wfs_adjoint_gather_kernel(GatherParams g) {
+  __shared__ GTap ct[kGCols];
+  __shared__ GTap rt[kGRows];
+  __shared__ float gt[kGRows][kGCols];
+  __shared__ float tt[kGRows][kGTW];  // column-transposed rows: sum over c of w_c g[r][c]
+  __shared__ int rfirst[kGTH];        // first candidate row reaching each tile row
+  const FwdParams& p = g.f;
+  const int nl = p.n_layers;
+  const int per_real = g.blk_start[nl];
+  const int b = blockIdx.x / per_real;
+  const int rb = blockIdx.x - b * per_real;
+  int l = 0;
+  while (l + 1 < nl && rb >= g.blk_start[l + 1]) ++l;  // block-uniform
+  const DevLayer L = cload(p.lay, l);
+  const int tiles_x = (L.nx + kGTW - 1) / kGTW;
+  const int tile = rb - g.blk_start[l];
+  const int ty0 = (tile / tiles_x) * kGTH, tx0 = (tile - (tile / tiles_x) * tiles_x) * kGTW;
+  const int tid = threadIdx.x;
+  const int wy = __builtin_amdgcn_readfirstlane(tid / kGTW);  // wave: tile rows wy + 4 k
+  const int lx = tid - wy * kGTW;
+  const int i = tx0 + lx;
+  constexpr int kWavesG = kBlock / kGTW;
+  const double stepd = (double)current_step(p);
+  const float* gb = g.gpsi + (int64_t)b * p.pupil_per_real;
+  float acc[kGPix];
+#pragma unroll
+  for (int k = 0; k < kGPix; ++k) acc[k] = 0.0f;
+  for (int s = 0; s < p.n_sensors; ++s) {
+    const DevSensor S = cload(p.sen, s);
+    const DevAffine A = cload(p.aff, (int64_t)s * nl + l);
+    const double bx = A.bx0 + stepd * A.dbx, by = A.by0 + stepd * A.dby;
+    const int npup = S.n_pup;
+    const float* gs = gb + S.pupil_off;
+    int my_lo, my_hi, mx_lo, mx_hi;
+    image_range(A.ay, by, L.ny, L.inv_ny, npup, ty0, ty0 + kGTH - 1, L.boundary, my_lo, my_hi);
+    image_range(A.ax, bx, L.nx, L.inv_nx, npup, tx0, tx0 + kGTW - 1, L.boundary, mx_lo, mx_hi);
+    for (int my = my_lo; my <= my_hi; ++my) {
+      const int64_t yshift = (int64_t)my * L.ny + ty0;
+      int r_lo, r_hi;
+      cand_range(A.inv_ay, by, (double)yshift, (double)(yshift + kGTH - 1), npup, r_lo, r_hi);
+      for (int r0 = r_lo; r0 <= r_hi; r0 += kGRows) {
+        const int nr = min(kGRows, r_hi - r0 + 1);
+        for (int mx = mx_lo; mx <= mx_hi; ++mx) {
+          const int64_t xshift = (int64_t)mx * L.nx + tx0;
+          int c_lo, c_hi;
+          cand_range(A.inv_ax, bx, (double)xshift, (double)(xshift + kGTW - 1), npup, c_lo,
+                     c_hi);
+          for (int c0 = c_lo; c0 <= c_hi; c0 += kGCols) {
+            const int nc = min(kGCols, c_hi - c0 + 1);
+            __syncthreads();  // previous pass done with the tables
+            if (tid < nr) rt[tid] = gather_tap(A.ay, A.by0, A.dby, stepd, r0 + tid, yshift);
+            if (tid < nc) ct[tid] = gather_tap(A.ax, A.bx0, A.dbx, stepd, c0 + tid, xshift);
+            {  // gradient rectangle rows r0.., columns c0.. (kGCols-pitched), loads issued first
+              constexpr int kPer = kGRows * kGCols / kBlock, kStep = kBlock / kGCols;
+              const int qc = tid & (kGCols - 1), qb = tid / kGCols;
+              const uint32_t o0 = (uint32_t)(r0 * npup + c0 + qc);  // < pupil_per_real < 2^31
+              float v[kPer];
+#pragma unroll
+              for (int k = 0; k < kPer; ++k) {
+                const int q = qb + k * kStep;
+                v[k] = (q < nr && qc < nc) ? ld_idx(gs, o0 + (uint32_t)(q * npup)) : 0.0f;
+              }
+#pragma unroll
+              for (int k = 0; k < kPer; ++k) {
+                const int q = qb + k * kStep;
+                if (q < nr) gt[q][qc] = v[k];
+              }
+            }
+            __syncthreads();
+            // separable transpose, first along columns: T[r][lx] = sum over the candidate
+            // columns whose taps reach lx (rel in {lx - 1, lx}, a contiguous run: rel is
+            // non-decreasing) of w_c g[r][c]; up to kGC4 of them kept in registers
+            int q0 = 0, q1 = nc;
+            while (q0 < q1) {
+              const int mid = (q0 + q1) >> 1;
+              if (ct[mid].rel + 1 < lx) q0 = mid + 1;
+              else q1 = mid;
+            }
+            constexpr int kGC4 = 4;
+            int qk[kGC4];
+            float wk[kGC4];
+            int nk = 0;
+            bool more = false;
+#pragma unroll
+            for (int k = 0; k < kGC4; ++k) {
+              qk[k] = 0;
+              wk[k] = 0.0f;
+              const int qc = q0 + k;
+              if (qc < nc && ct[qc].rel <= lx) {
+                const GTap tc = ct[qc];
+                qk[k] = qc;
+                wk[k] = (tc.rel == lx ? 1.0f - tc.w1 : 0.0f) + (tc.rel + 1 == lx ? tc.w1 : 0.0f);
+                nk = k + 1;
+              }
+            }
+            if (nk == kGC4 && q0 + kGC4 < nc && ct[q0 + kGC4].rel <= lx) more = true;
+            for (int r = wy; r < nr; r += kWavesG) {
+              float t = 0.0f;
+#pragma unroll
+              for (int k = 0; k < kGC4; ++k) t = fmaf(wk[k], gt[r][qk[k]], t);
+              if (more) {  // coarse layer: more than kGC4 pupil columns per layer column
+                for (int qc = q0 + kGC4; qc < nc; ++qc) {
+                  const GTap tc = ct[qc];
+                  if (tc.rel > lx) break;
+                  const float wc =
+                      (tc.rel == lx ? 1.0f - tc.w1 : 0.0f) + (tc.rel + 1 == lx ? tc.w1 : 0.0f);
+                  t = fmaf(wc, gt[r][qc], t);
+                }
+              }
+              tt[r][lx] = t;
+            }
+            if (tid < kGTH) {  // first candidate row whose taps reach tile row tid
+              int r = 0, r1 = nr;
+              while (r < r1) {
+                const int mid = (r + r1) >> 1;
+                if (rt[mid].rel + 1 < tid) r = mid + 1;
+                else r1 = mid;
+              }
+              rfirst[tid] = r;
+            }
+            __syncthreads();
+            // then along rows: G[ry][lx] += sum over the candidate rows reaching ry of w_r T
+#pragma unroll
+            for (int k = 0; k < kGPix; ++k) {
+              const int ry = wy + k * kWavesG;  // wave-uniform
+              for (int rr = rfirst[ry]; rr < nr; ++rr) {
+                const GTap tr = rt[rr];
+                if (tr.rel > ry) break;
+                const float wr =
+                    (tr.rel == ry ? 1.0f - tr.w1 : 0.0f) + (tr.rel + 1 == ry ? tr.w1 : 0.0f);
+                acc[k] = fmaf(wr, tt[rr][lx], acc[k]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  if (i < L.nx) {
+#pragma unroll
+    for (int k = 0; k < kGPix; ++k) {
+      const int j = ty0 + wy + k * kWavesG;
+      if (j < L.ny)
+        g.grad[(int64_t)b * p.layer_stride + L.offset + (int64_t)j * L.nx + i] =
+            acc[k] * L.weight;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void zero_kernel(float* x, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0f;
@@ -192,11 +421,21 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(float* x, int64_t n) {
 
 template <int NS>
 static hipError_t launch_adj(AdjParams a, hipStream_t st) {
-  const int64_t n = a.f.layer_stride * a.f.batch;
+  // atomic mode accumulates into the gradient; gather mode into the phase-gradient images
+  float* z = a.gpsi ? a.gpsi : a.grad_layers;
+  const int64_t n = a.gpsi ? a.f.pupil_per_real * a.f.batch : a.f.layer_stride * a.f.batch;
   const int zb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
-  hipLaunchKernelGGL(zero_kernel, dim3(zb > 0 ? zb : 1), dim3(kBlock), 0, st, a.grad_layers, n);
+  hipLaunchKernelGGL(zero_kernel, dim3(zb > 0 ? zb : 1), dim3(kBlock), 0, st, z, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (a.gpsi) {  // the gather writes every grid pixel; clear the rest of the gradient buffer
+    const int64_t ng = a.f.layer_stride * a.f.batch;
+    const int zg = (int)std::min<int64_t>((ng + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(zero_kernel, dim3(zg > 0 ? zg : 1), dim3(kBlock), 0, st, a.grad_layers,
+                       ng);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const int64_t tasks = (int64_t)a.f.otf.per_real * a.f.batch;
   if (tasks == 0) return hipSuccess;
   const int64_t waves = tasks;
@@ -212,6 +451,20 @@ static hipError_t launch_adj(AdjParams a, hipStream_t st) {
 
 int adj_lds_bytes(int ns, int n_layers, int n_pix) {
   return adj_lds_layout(ns, n_layers, n_pix).total;
+}
+
+hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* grad,
+                                 const int32_t* blk_start, hipStream_t st) {
+  GatherParams g;
+  g.f = f;
+  g.gpsi = gpsi;
+  g.grad = grad;
+  for (int l = 0; l <= f.n_layers; ++l) g.blk_start[l] = blk_start[l];
+  const int64_t blocks = (int64_t)blk_start[f.n_layers] * f.batch;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wfs_adjoint_gather_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, g);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st) {

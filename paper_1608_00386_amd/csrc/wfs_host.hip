@@ -23,6 +23,8 @@ int project_strip();
 int project_rows();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
 hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
+hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* grad,
+                                 const int32_t* blk_start, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
                         int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma);
@@ -81,6 +83,8 @@ struct wfs_plan_s {
   std::vector<double> pix_scale;
   int32_t n_slopes = 0, n_valid_total = 0;
   int64_t phase_per_real = 0;
+  int64_t pupil_per_real = 0;       // sum over sensors of n_pup^2
+  float* d_gimg = nullptr;          // adjoint gather: [B][pupil_per_real], allocated on first use
   // device blob holding every table
   char* d_blob = nullptr;
   int64_t* d_step = nullptr;
@@ -89,6 +93,7 @@ struct wfs_plan_s {
   int otf_max_npix = 0;
   int64_t otf_tasks = 0, fft_tasks = 0;
   int adj_lds_per_wave = 0;
+  std::vector<int32_t> gather_blk;  // adjoint gather: first tile of each layer (+ total)
   int lds_split = 0, lds_fused = 0;  // LDS bytes per lag-domain wave, per schedule
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
@@ -294,7 +299,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<int32_t> subidx;
   std::vector<std::vector<int2>> proj_desc_s(n_sensors);  // projection blocks per sensor
   int32_t slope_off = 0, aux_off = 0;
-  int64_t phase_off = 0;
+  int64_t phase_off = 0, pupil_off = 0;
   int otf_ns = 0;
   for (int s = 0; s < n_sensors; ++s) {
     const wfs_sensor_desc& S = sensors[s];
@@ -314,6 +319,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     d.aux_off = aux_off;
     d.mask_off = (int32_t)masks.size();
     d.phase_off = (int32_t)phase_off;
+    d.pupil_off = (int32_t)std::min<int64_t>(pupil_off, (1LL << 31) - 1);
     d.noisy = S.photons > 0 ? 1 : 0;
     d.elong = (S.na_fwhm_m > 0 && finite_d(S.src_alt_m)) ? 1 : 0;
     d.kappa = (float)(lambda_ref_m / S.lambda_m);
@@ -350,6 +356,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     slope_off += 2 * d.n_valid;
     aux_off += d.n_valid;
     phase_off += (int64_t)d.n_valid * S.n_sub * S.n_sub;
+    pupil_off += (int64_t)g.n_pup * g.n_pup;
     P->n_valid.push_back(d.n_valid);
     P->pix_scale.push_back(S.bin * S.lambda_m / (S.n_fft * g.dx));
 
@@ -437,12 +444,15 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       A.ay = sc * g.dx / L.pitch_m;
       A.by0 = (sc * x0 + S.theta_y_rad * L.alt_m) / L.pitch_m + L.ny / 2.0 - 0.5;
       A.dby = -L.vy_mps * dt_s / L.pitch_m;
+      A.inv_ax = 1.0 / A.ax;
+      A.inv_ay = 1.0 / A.ay;
     }
   }
   P->hsen = ds;
   P->n_slopes = slope_off;
   P->n_valid_total = aux_off;
   P->phase_per_real = phase_off;
+  P->pupil_per_real = pupil_off;
   P->otf_ns = otf_ns;
 
   // tables -> one device blob
@@ -509,7 +519,17 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   set_proj(b, P->proj_all);
   b.phase_per_real = P->phase_per_real;
+  b.pupil_per_real = P->pupil_per_real;
   b.phase_in = nullptr;
+  {
+    int64_t acc = 0;
+    for (int l = 0; l < n_layers; ++l) {
+      P->gather_blk.push_back((int32_t)acc);
+      // adjoint gather tiles of 64 x 16 layer pixels
+      acc += (int64_t)((layers[l].nx + 63) / 64) * ((layers[l].ny + 15) / 16);
+    }
+    P->gather_blk.push_back((int32_t)acc);
+  }
   P->otf_tasks = (int64_t)b.otf.per_real * batch;
   P->fft_tasks = (int64_t)b.fft.per_real * batch;
   if (P->otf_tasks > (1LL << 31) - 1 || P->fft_tasks > (1LL << 31) - 1) {
@@ -589,6 +609,7 @@ int wfs_plan_destroy(wfs_plan_t P) {
   hipError_t e = hipDeviceSynchronize();
   if (P->d_blob) (void)hipFree(P->d_blob);
   if (P->d_phase) (void)hipFree(P->d_phase);
+  if (P->d_gimg) (void)hipFree(P->d_gimg);
   delete P;
   if (e != hipSuccess) return hip_fail(e, "wfs_plan_destroy");
   return WFS_OK;
@@ -837,6 +858,19 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   a.fwd_slopes = fwd_slopes;
   a.fwd_aux = fwd_aux;
   a.grad_layers = grad_layers;
+  // gather mode (default): phase gradients into the second phase buffer, then the layer
+  // gather; atomic mode: each pupil pixel scatters its taps
+  const bool gather = !(P->flags & WFS_FLAG_ADJOINT_ATOMIC) &&
+                      P->pupil_per_real < (1LL << 31) - 1;
+  if (gather && !P->d_gimg) {  // phase-gradient images, allocated on the first gather call
+    hipError_t ea = hipMalloc((void**)&P->d_gimg,
+                              sizeof(float) * (size_t)P->pupil_per_real * P->batch);
+    if (ea != hipSuccess) {
+      P->d_gimg = nullptr;
+      return hip_fail(ea, "wfs_adjoint: phase-gradient images");
+    }
+  }
+  a.gpsi = gather ? P->d_gimg : nullptr;
   a.f.lds_per_wave = P->adj_lds_per_wave;
   hipError_t e = hipSuccess;
   if (P->split && P->d_phase) {  // subaperture fields from the projection kernel's phase
@@ -848,6 +882,11 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   }
   e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: launch");
+  if (gather) {
+    e = launch_adjoint_gather(a.f, P->d_gimg, grad_layers, P->gather_blk.data(),
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: gather launch");
+  }
   return WFS_OK;
 }
 

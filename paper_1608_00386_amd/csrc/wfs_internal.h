@@ -31,6 +31,7 @@ struct DevLayer {
 struct DevAffine {
   double ax, bx0, dbx;
   double ay, by0, dby;
+  double inv_ax, inv_ay;  // 1 / ax, 1 / ay (adjoint gather)
 };
 
 struct DevSensor {
@@ -50,7 +51,7 @@ struct DevSensor {
   int32_t pad2;
   float inv_nsub;    // 1 / n_sub
   int32_t mtab_off;  // matrix-core image operands (n_pix <= 8), -1: vector path
-  int32_t pad5;
+  int32_t pupil_off;  // offset of this sensor's [n_pup][n_pup] image in a pupil-frame buffer
 };
 
 struct DevSubap {
@@ -108,6 +109,7 @@ struct FwdParams {
   const int32_t* subidx;     // valid-subaperture index of (sensor, a, b), -1 if not valid
   const float* phase_in;     // split mode: phase of every valid pixel (kappa applied), or null
   int64_t phase_per_real;    // floats per realisation in the phase buffer
+  int64_t pupil_per_real;    // floats per realisation in a pupil-frame buffer (sum n_pup^2)
   // pipelined frames: the spot launch of step k also projects step k + 1 into phase_out
   int32_t proj_blocks;       // projection blocks interleaved with the spot blocks (0: none)
   int32_t proj_lds;          // bytes of LDS a projection block needs
@@ -120,6 +122,15 @@ struct AdjParams {
   const float* fwd_slopes;  // or null
   const float* fwd_aux;     // or null
   float* grad_layers;       // [B][layer_stride]
+  float* gpsi;              // gather mode: [B][pupil_per_real] phase-gradient images, or null
+};
+
+// Gather of the layer gradient from the phase gradients: thread per layer pixel.
+struct GatherParams {
+  FwdParams f;
+  const float* gpsi;         // [B][pupil_per_real] pupil-frame images, kappa applied
+  float* grad;               // [B][layer_stride]
+  int32_t blk_start[kMaxLayers + 1];  // first block of each layer within a realisation
 };
 
 }  // namespace wfs

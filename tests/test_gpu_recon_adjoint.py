@@ -85,12 +85,14 @@ def _adjoint_case(name, seed=1):
                                   "lgs_n5_N10_b2_2sens_batch3", "dm_two_ngs_batch2", "cfg0",
                                   "ngs_n6_N12_b4_oddpix"])
 @pytest.mark.parametrize("saved", [False, True])
-@pytest.mark.parametrize("mode", ["split", "fused"])
+@pytest.mark.parametrize("mode", ["split", "fused", "split_atomic"])
 def test_adjoint_matches_oracle(name, saved, mode):
     torch, W = _gpu()
     cfg, x, g = _adjoint_case(name)
     step = 4
-    plan = W.Plan(cfg, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
+    flags = {"split": 0, "fused": W.WFS_FLAG_FUSED,
+             "split_atomic": W.WFS_FLAG_ADJOINT_ATOMIC}[mode]
+    plan = W.Plan(cfg, flags=flags)
     xt = torch.from_numpy(x).cuda()
     gt = torch.from_numpy(g).cuda()
     if saved:
@@ -103,6 +105,34 @@ def test_adjoint_matches_oracle(name, saved, mode):
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert rel <= 1e-4, rel
     assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["lgs_n10_N32_b4_noise", "dm_two_ngs_batch2"])
+def test_adjoint_gather_is_bitwise_deterministic(name):
+    torch, W = _gpu()
+    cfg, x, g = _adjoint_case(name)
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda()
+    gt = torch.from_numpy(g).cuda()
+    o1 = plan.adjoint(xt, gt, step=3).clone()
+    o2 = plan.adjoint(xt, gt, step=3)
+    assert torch.equal(o1, o2)
+
+
+def test_adjoint_small_periodic_grid_wraps():
+    """A screen smaller than the pupil footprint (several periodic images per pixel)."""
+    torch, W = _gpu()
+    from wfs_cases import ngs_case
+    cfg = ngs_case(6, 4, 8, 2, D=6.0, layers=1, n=16, pitch=0.25)
+    for s in cfg["sensors"]:
+        s["photons"] = 0.0
+    x = layers_for(cfg, scale=0.5)
+    g = synth.random_field((1, oracle.n_slopes(cfg)), seed=4)
+    plan = W.Plan(cfg)
+    out = plan.adjoint(torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda(), step=5)
+    ref = oracle.adjoint(x.astype(np.float64), cfg, 5, g.astype(np.float64))
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
 
 
 def test_autograd_function_uses_the_adjoint():
