@@ -30,7 +30,7 @@ __global__ void wfs_step_kernel(int64_t* step_dev, int64_t value, int32_t add) {
 template <int NS>
 hipError_t launch_fwd_ns(const FwdParams& p, hipStream_t st);
 
-hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st) {
+static hipError_t launch_forward_ns(const FwdParams& p, int ns, hipStream_t st) {
   switch (ns) {
     case 2: return launch_fwd_ns<2>(p, st);
     case 3: return launch_fwd_ns<3>(p, st);
@@ -45,6 +45,22 @@ hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st) {
     case 12: return launch_fwd_ns<12>(p, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// FFT-path and lag-domain subapertures go in two launches on the same stream: the FFT path's
+// registers and LDS would otherwise set the occupancy of every lag-domain wavefront.
+hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st) {
+  if (p.fft_blocks == 0 || (p.otf_blocks == 0 && p.proj_blocks == 0))
+    return launch_forward_ns(p, ns, st);
+  FwdParams a = p;
+  a.otf_blocks = 0;
+  a.proj_blocks = 0;
+  hipError_t e = launch_forward_ns(a, ns, st);
+  if (e != hipSuccess) return e;
+  FwdParams c = p;
+  c.fft_blocks = 0;
+  c.lds_per_wave = p.lds_per_wave_otf;
+  return launch_forward_ns(c, ns, st);
 }
 
 int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps) {

@@ -95,6 +95,7 @@ struct wfs_plan_s {
   int adj_lds_per_wave = 0;
   std::vector<int32_t> gather_blk;  // adjoint gather: first tile of each layer (+ total)
   int lds_split = 0, lds_fused = 0;  // LDS bytes per lag-domain wave, per schedule
+  int lds_split_otf = 0, lds_fused_otf = 0;  // same, in a launch without FFT-path blocks
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
   ProjTable proj_all{}, proj_fft{};
@@ -543,12 +544,12 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   for (int s : fft_ids)
     lds_fft = std::max(lds_fft, fft_lds_bytes(sensors[s].n_sub, sensors[s].n_fft,
                                               sensors[s].n_fft / sensors[s].bin));
-  auto wave_lds = [&](bool taps) {
+  auto wave_lds = [&](bool taps, bool with_fft) {
     int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps) : 0;
-    w = std::max(w, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
-    return (w + 15) & ~15;
+    if (with_fft) w = std::max(w, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
+    return std::max(16, (w + 15) & ~15);
   };
-  const int lds_wave = wave_lds(true);
+  const int lds_wave = wave_lds(true, true);
   if (lds_wave * kWavesPerBlock > 65536) {
     (void)hipFree(P->d_blob);
     delete P;
@@ -556,8 +557,11 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
                 lds_wave * kWavesPerBlock);
   }
   P->lds_fused = lds_wave;
-  P->lds_split = wave_lds(false);
+  P->lds_split = wave_lds(false, true);
+  P->lds_fused_otf = wave_lds(true, false);
+  P->lds_split_otf = wave_lds(false, false);
   b.lds_per_wave = P->lds_split;
+  b.lds_per_wave_otf = P->lds_split_otf;
   P->adj_lds_per_wave = otf_ns ? ((adj_lds_bytes(otf_ns, n_layers, P->otf_max_npix) + 15) & ~15) : 16;
   if (P->adj_lds_per_wave * kWavesPerBlock > 65536) P->adj_lds_per_wave = 0;  // adjoint unsupported
   // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
@@ -656,6 +660,7 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
   }
   p.otf_from_phase = split ? 1 : 0;
   p.lds_per_wave = split ? P->lds_split : P->lds_fused;
+  p.lds_per_wave_otf = split ? P->lds_split_otf : P->lds_fused_otf;
   return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
 }
 
