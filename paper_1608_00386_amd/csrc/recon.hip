@@ -102,8 +102,10 @@ __global__ __launch_bounds__(kRB) void recon_valu_kernel(const float* __restrict
 // ---------------------------------------------------------------------------------------
 // MFMA GEMM.  v_mfma_f32_16x16x4f32 operand layout (wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; the four accumulator registers of lane l hold D[4*(l/16)+i][l%16].
-// The K index of one MFMA is only a label shared by A and B, so lane (i, kq) feeds the four
-// consecutive columns k0 + 4 kq + t (t = 0..3) of one float4 load to four MFMAs.
+// The K index of one MFMA is only a label shared by A and B, so lane (i, kq) feeds the eight
+// consecutive columns k + 8 kq + t (t = 0..7) of two adjacent float4 loads to eight MFMAs:
+// the two loads of a row's four lanes cover whole 128-byte lines.  Plain (cached) loads: a
+// non-temporal hint let lines leave L2 between the two halves and doubled the HBM traffic.
 // Tile: D rows = 16 rows of R, D columns = 16 realisations (b0 .. b0+15, masked to B).
 // ---------------------------------------------------------------------------------------
 
@@ -135,30 +137,30 @@ __global__ __launch_bounds__(kRB) void recon_mfma_kernel(const float* __restrict
   // iteration's loads issued before this iteration's MFMAs (double-buffered registers)
   float4 ra[TR], rb[TR], sa = make_float4(0.f, 0.f, 0.f, 0.f), sb = sa;
   if (k + 32 <= k1) {
-    const int ka = k + 4 * kq, kb = k + 16 + 4 * kq;
+    const int ka = k + 8 * kq, kb = ka + 4;
     if (bok) {
       sa = *reinterpret_cast<const float4*>(srow + ka);
       sb = *reinterpret_cast<const float4*>(srow + kb);
     }
 #pragma unroll
     for (int t = 0; t < TR; ++t) {
-      ra[t] = ldnt4(rrow[t] + ka);
-      rb[t] = ldnt4(rrow[t] + kb);
+      ra[t] = *reinterpret_cast<const float4*>(rrow[t] + ka);
+      rb[t] = *reinterpret_cast<const float4*>(rrow[t] + kb);
     }
   }
   for (; k + 32 <= k1; k += 32) {
     float4 na[TR], nb[TR], nsa = make_float4(0.f, 0.f, 0.f, 0.f), nsb = nsa;
     const bool more = k + 64 <= k1;
     if (more) {
-      const int ka = k + 32 + 4 * kq, kb = k + 48 + 4 * kq;
+      const int ka = k + 32 + 8 * kq, kb = ka + 4;
       if (bok) {
         nsa = *reinterpret_cast<const float4*>(srow + ka);
         nsb = *reinterpret_cast<const float4*>(srow + kb);
       }
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
-        na[t] = ldnt4(rrow[t] + ka);
-        nb[t] = ldnt4(rrow[t] + kb);
+        na[t] = *reinterpret_cast<const float4*>(rrow[t] + ka);
+        nb[t] = *reinterpret_cast<const float4*>(rrow[t] + kb);
       }
     }
 #pragma unroll
