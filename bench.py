@@ -262,7 +262,8 @@ def bench_recon(torch, W, reps=10):
                 hbm_frac_b1=byts / (ms1 * 1e-3) / PEAK_HBM)
 
 
-def cpu_baseline(frames=8):
+def cpu_baseline(frames=40):
+    """The FP64 oracle on whole config-1 frames, one thread."""
     import oracle
     cfg = synth.config1()
     x = synth.make_batch(cfg, [0]).astype(np.float64)
@@ -274,6 +275,37 @@ def cpu_baseline(frames=8):
     return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": f"{frames} full config-1 frames (4,632 subapertures each), numpy FP64, "
                       f"1 thread, {dt:.1f} s"}
+
+
+_POOL_X = None
+
+
+def _oracle_frames(args):
+    import oracle
+    k0, n = args
+    cfg = synth.config1()
+    for k in range(k0, k0 + n):
+        oracle.forward(_POOL_X, cfg, k)
+    return n
+
+
+def cpu_baseline_pool(frames_per_core=4):
+    """The same oracle frames spread over every core of this process's affinity set, one
+    single-threaded worker per core (forked before anything touches the GPU)."""
+    import multiprocessing as mp
+    global _POOL_X
+    cores = len(os.sched_getaffinity(0))
+    _POOL_X = synth.make_batch(synth.config1(), [0]).astype(np.float64)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_frames, [(0, 1)] * cores)  # warm every worker
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_frames, [(c * frames_per_core, frames_per_core)
+                                             for c in range(cores)]))
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} full config-1 frames over {cores} single-threaded worker "
+                      f"processes, numpy FP64, {dt:.1f} s"}
 
 
 def profile_run(torch, W, n, flags=0):
@@ -336,7 +368,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="headline only (no extras, no CPU)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=8)
+    ap.add_argument("--cpu-frames", type=int, default=40)
     ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule")
     ap.add_argument("--fused", action="store_true", help="projection fused into the spot kernel")
     ap.add_argument("--profile-frames", type=int, default=0,
@@ -348,6 +380,17 @@ def main():
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the "
               "multi-GPU sharding is a design note, not a launched path.", file=sys.stderr)
         sys.exit(2)
+
+    cpu = cpu_pool = None
+    if not args.quick and not args.no_cpu and args.profile_frames == 0:
+        # the oracle baselines run first: the pool forks before anything touches the GPU
+        log("[bench] cpu baseline (oracle, 1 thread) ...")
+        cpu = cpu_baseline(args.cpu_frames)
+        log("[bench] cpu baseline (oracle, all cores) ...")
+        try:
+            cpu_pool = cpu_baseline_pool()
+        except Exception as e:  # report, do not hide
+            cpu_pool = {"error": repr(e)}
 
     import torch
     import paper_1608_00386_amd as W
@@ -445,9 +488,9 @@ def main():
             out["closed_loop"] = bench_closed_loop(torch, W)
         except Exception as e:
             out["closed_loop"] = {"error": repr(e)}
-        if not args.no_cpu:
-            log("[bench] cpu baseline (oracle) ...")
-            out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
+        if cpu is not None:
+            out["cpu_baseline"] = cpu
+            out["cpu_baseline_all_cores"] = cpu_pool
     print(json.dumps(out), flush=True)
 
 
