@@ -149,7 +149,7 @@ def bench_config1(torch, W, steps, warmup, k0=0, tune=True, flags=0):
     out = dict(cfg=cfg, plan=plan, wall=wallK, gpu_ms_per_frame=gpu_msK,
                single_wall=wall1, single_gpu_ms_per_frame=gpu_ms1,
                kernel_ms_eager=kernel_ms_eager, tuned_us=tuned_us, x=x,
-               schedule=plan.schedule(), pipelined=plan.schedule()["split"] == 1)
+               schedule=plan.schedule(), pipelined=plan.schedule()["pipelined"] == 1)
     out.update(kernel_split_ms(torch, plan, x, slopes, aux, k0, min(steps, 100)))
     return out
 
@@ -172,8 +172,9 @@ def kernel_split_ms(torch, plan, x, slopes, aux, k0, n):
 
 
 def bench_batched(torch, W, steps=20, batch=8):
-    """Config 2: 6 LGS + 3 NGS x 8 realisations, one wfs_forward per time step, the steps
-    captured in one HIP graph."""
+    """Config 2: 6 LGS + 3 NGS x 8 realisations.  The steps are one wfs_forward_steps call
+    captured in a HIP graph, pipelined (the projection of step k+1 inside the spot launch of
+    step k) if the tuner found that faster; one wfs_forward per step is reported beside it."""
     cfg = synth.config2(batch=batch)
     x = torch.from_numpy(synth.make_batch(cfg, range(batch))).cuda()
     plan = W.Plan(cfg, batch=batch)
@@ -185,19 +186,28 @@ def bench_batched(torch, W, steps=20, batch=8):
 
     g = graph_of(torch, step, steps)
     g.replay()
-    wall, gpu_ms = timed_replay(torch, g, steps)
+    _, single_ms = timed_replay(torch, g, steps)
+    del g
+    sK = torch.empty(steps, batch, plan.n_slopes, device="cuda")
+    aK = torch.empty(steps, batch, plan.n_valid_total, device="cuda")
+    gK = graph_of(torch, lambda i: plan.forward_steps(x, 0, steps, slopes=sK, aux=aK), 1)
+    gK.replay()
+    wall, gpu_ms = timed_replay(torch, gK, steps)
+    del gK
     n_lgs = sum(1 for s in cfg["sensors"] if np.isfinite(s["src_alt_m"]))
     lgs_subaps = sum(nv for s, nv in zip(cfg["sensors"], plan.n_valid) if np.isfinite(s["src_alt_m"]))
     flops = plan_flops(cfg, plan, batch)
     return dict(workload="config2: 6 LGS 80x80 + 3 NGS 2x2 (64 px, N=128), 8 realisations, "
-                         "10 layers 1024^2, noise on, graph of %d steps" % steps,
+                         "10 layers 1024^2, noise on, %d steps in one wfs_forward_steps graph "
+                         "(pipelined as tuned)" % steps,
                 ms_per_step=gpu_ms, steps=steps,
+                single_step_ms=single_ms,
                 lgs_frames_per_s=n_lgs * batch / (gpu_ms * 1e-3),
                 subap_spots_per_s=(sum(plan.n_valid) * batch) / (gpu_ms * 1e-3),
                 lgs_subaps_per_step=lgs_subaps * batch,
                 achieved_tflops=flops / (gpu_ms * 1e-3) / 1e12,
                 frac_fp32_valu=flops / (gpu_ms * 1e-3) / PEAK_FP32_VALU,
-                paths=plan.paths)
+                schedule=plan.schedule(), paths=plan.paths)
 
 
 def bench_closed_loop(torch, W, steps=20, batch=8, gain=0.4):
@@ -408,15 +418,18 @@ def main():
     subaps = r1["plan"].n_valid[0]
     frames_per_s = args.steps / r1["wall"]
     flops = plan_flops(cfg1, r1["plan"])
-    split = r1["schedule"]["split"] == 1
     # dominant kernel: the spot launch.  Pipelined (split schedule): one launch per frame that
     # forms the spots of step k and projects step k+1; its mean duration is the replayed
     # graph's time per frame less the one leading projection.  All of it is charged to the
     # spot stage's FLOPs (the projection's bytes are reported separately).
-    if split:
+    if r1["pipelined"]:
         kern_ms = (r1["gpu_ms_per_frame"] * args.steps - r1["project_ms"]) / args.steps
         kern_name = "wfs_forward_kernel<10> (spots of step k + projection of step k+1)"
         traffic_key = "wfs_forward_kernel<10, false, false, true>"
+    elif r1["schedule"]["split"] == 1:
+        kern_ms = r1["gpu_ms_per_frame"] - r1["project_ms"]
+        kern_name = "wfs_forward_kernel<10> (spots)"
+        traffic_key = "wfs_forward_kernel<10, false, false, false>"
     else:
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = "wfs_forward_kernel<10> (fused gather)"

@@ -138,7 +138,8 @@ int wfs_forward(wfs_plan_t plan, const float* layers, int64_t step, uint64_t see
  *   with step0 = WFS_STEP_DEVICE, the device counter + 0 .. n_steps - 1; the counter is not
  *   advanced): the same results, bit for bit, as n_steps calls of wfs_forward.  slopes:
  *   device [n_steps][B][n_slopes]; aux: device [n_steps][B][n_valid_total] or NULL.  With the
- *   split schedule the frames are pipelined: each launch forms the spots of step k and
+ *   split schedule the frames are pipelined unless wfs_plan_tune found that slower (large
+ *   batches, where each launch fills the chip on its own): each launch forms the spots of step k and
  *   projects the layers for step k + 1 into the plan's second phase buffer, so the
  *   memory-latency-bound projection overlaps the arithmetic-bound spot stage (frozen flow,
  *   Sec. 2.1, makes every frame's input known in advance).  Layers must not change during
@@ -159,12 +160,12 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
 /*
  * wfs_plan_schedule -- the launch schedule the plan currently uses (set at creation, changed
  *   by wfs_plan_tune): split = 1 when a frame is the projection kernel followed by the spot
- *   kernel, 0 when the spot kernel gathers the layers itself; subaperture tasks per wave of the
- *   lag-domain kernel (1 in this version); xcd_remap = 1 when blocks are renumbered so
- *   neighbouring tasks share an XCD.  Any output pointer may be NULL.
+ *   kernel, 0 when the spot kernel gathers the layers itself; pipelined = 1 when
+ *   wfs_forward_steps projects frame k + 1 inside the spot launch of frame k (split schedule
+ *   only), 0 when it runs the frames one after the other; xcd_remap = 1 when blocks are
+ *   renumbered so neighbouring tasks share an XCD.  Any output pointer may be NULL.
  */
-int wfs_plan_schedule(wfs_plan_t plan, int32_t* split, int32_t* subaps_per_wave,
-                      int32_t* xcd_remap);
+int wfs_plan_schedule(wfs_plan_t plan, int32_t* split, int32_t* pipelined, int32_t* xcd_remap);
 
 /*
  * wfs_plan_footprint -- algorithmic read footprint of the projection at time step `step`:
@@ -205,9 +206,10 @@ int wfs_advance_step(wfs_plan_t plan, int64_t delta, void* stream);
 
 /*
  * wfs_plan_tune -- time the launch schedules (block order, split or fused projection where
- *   both apply) on `layers` and keep the fastest in the plan.  Synchronises; writes scratch
- *   slopes internally.  iters: timed launches per candidate.  On return *best_us holds the
- *   best time per forward call (may be NULL).
+ *   both apply) on `layers` and keep the fastest in the plan; under the split schedule also
+ *   time max(2, iters) frames pipelined against one after the other and keep the faster for
+ *   wfs_forward_steps.  Synchronises; writes scratch slopes internally.  iters: timed launches
+ *   per candidate.  On return *best_us holds the best time per forward call (may be NULL).
  */
 int wfs_plan_tune(wfs_plan_t plan, const float* layers, int32_t iters, double* best_us,
                   void* stream);

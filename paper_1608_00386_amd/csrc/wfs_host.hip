@@ -102,6 +102,7 @@ struct wfs_plan_s {
   float* d_phase = nullptr;   // split-mode phase buffer [B][phase_per_real]
   float* d_phase2 = nullptr;  // second buffer (pipelined frames), same allocation
   int split = 0;             // 1: projection kernel + spot kernel; 0: fused gather
+  int pipeline = 1;          // wfs_forward_steps: projection of frame k+1 in spot launch k
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
@@ -246,7 +247,6 @@ static void fill_tasks(TaskTable& tt, const std::vector<int>& ids, const std::ve
 
 static void default_schedule(wfs_plan_s* P) {
   const int64_t tasks = P->otf_tasks;
-  P->base.subaps_per_wave = 1;  // one subaperture per wavefront
   const int64_t waves = tasks;
   P->base.otf_blocks = (int32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   P->base.xcd_remap = (P->flags & WFS_FLAG_NO_XCD_REMAP) ? 0 : 1;
@@ -678,6 +678,46 @@ int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, 
   return WFS_OK;
 }
 
+// Frames step0 .. step0 + n - 1 (or the device counter + k).  Outputs of frame k at slopes +
+// k * (slopes of one frame) when `advance_out`, else every frame overwrites the first.
+// Pipelined (split schedule only): project frame 0; then launch k computes the spots of frame k
+// from phase buffer k % 2 and projects frame k + 1 into the other buffer.
+static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, int n,
+                            uint64_t seed, float* slopes, float* aux, bool advance_out,
+                            bool pipelined, hipStream_t st) {
+  const int64_t ns_per = advance_out ? (int64_t)P->n_slopes * P->batch : 0;
+  const int64_t na_per = advance_out ? (int64_t)P->n_valid_total * P->batch : 0;
+  auto frame = [&](int k) {
+    const int64_t s = step0 == WFS_STEP_DEVICE ? WFS_STEP_DEVICE : step0 + k;
+    FwdParams p = call_params(P, layers, s, seed, slopes + k * ns_per, aux ? aux + k * na_per : nullptr);
+    if (s == WFS_STEP_DEVICE) p.step = k;
+    return p;
+  };
+  hipError_t e = hipSuccess;
+  if (!pipelined) {
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_fwd_modes(P, frame(k), st);
+    return e;
+  }
+  float* buf[2] = {P->d_phase, P->d_phase2};
+  {
+    FwdParams p = frame(0);
+    set_proj(p, P->proj_all);
+    e = launch_project(p, buf[0], P->proj_lds, st);
+  }
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    FwdParams p = frame(k);
+    p.phase_in = buf[k & 1];
+    p.otf_from_phase = 1;
+    if (k + 1 < n) {
+      set_proj(p, P->proj_all);
+      p.proj_blocks = P->proj_all.per_real * P->batch;
+      p.phase_out = buf[(k + 1) & 1];
+    }
+    e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+  }
+  return e;
+}
+
 int wfs_forward_steps(wfs_plan_t P, const float* layers, int64_t step0, int32_t n_steps,
                       uint64_t seed, float* slopes, float* aux, void* stream) {
   if (!P) return fail(WFS_EINVAL, "wfs_forward_steps: null plan");
@@ -689,41 +729,8 @@ int wfs_forward_steps(wfs_plan_t P, const float* layers, int64_t step0, int32_t 
     return fail(WFS_EINVAL, "wfs_forward_steps: step overflow");
   rc = check_device(P, "wfs_forward_steps");
   if (rc) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t ns_per = (int64_t)P->n_slopes * P->batch;
-  const int64_t na_per = (int64_t)P->n_valid_total * P->batch;
-  // frame k at step0 + k (or the device counter + k)
-  auto frame = [&](int k) {
-    const int64_t s = step0 == WFS_STEP_DEVICE ? WFS_STEP_DEVICE : step0 + k;
-    FwdParams p = call_params(P, layers, s, seed, slopes + k * ns_per, aux ? aux + k * na_per : nullptr);
-    if (s == WFS_STEP_DEVICE) p.step = k;
-    return p;
-  };
-  hipError_t e = hipSuccess;
-  if (!(P->split && P->d_phase)) {  // fused schedule: frames one after the other
-    for (int k = 0; k < n_steps && e == hipSuccess; ++k) e = launch_fwd_modes(P, frame(k), st);
-    if (e != hipSuccess) return hip_fail(e, "wfs_forward_steps: launch");
-    return WFS_OK;
-  }
-  // split schedule, pipelined: project step0; then launch k computes the spots of step k from
-  // buffer k % 2 and projects step k + 1 into the other buffer
-  float* buf[2] = {P->d_phase, P->d_phase2};
-  {
-    FwdParams p = frame(0);
-    set_proj(p, P->proj_all);
-    e = launch_project(p, buf[0], P->proj_lds, st);
-  }
-  for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
-    FwdParams p = frame(k);
-    p.phase_in = buf[k & 1];
-    p.otf_from_phase = 1;
-    if (k + 1 < n_steps) {
-      set_proj(p, P->proj_all);
-      p.proj_blocks = P->proj_all.per_real * P->batch;
-      p.phase_out = buf[(k + 1) & 1];
-    }
-    e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
-  }
+  hipError_t e = run_steps(P, layers, step0, n_steps, seed, slopes, aux, true,
+                           P->split && P->d_phase && P->pipeline, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_forward_steps: launch");
   return WFS_OK;
 }
@@ -744,11 +751,10 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
   return WFS_OK;
 }
 
-int wfs_plan_schedule(wfs_plan_t P, int32_t* split, int32_t* subaps_per_wave,
-                      int32_t* xcd_remap) {
+int wfs_plan_schedule(wfs_plan_t P, int32_t* split, int32_t* pipelined, int32_t* xcd_remap) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_schedule: null plan");
   if (split) *split = P->split;
-  if (subaps_per_wave) *subaps_per_wave = P->base.subaps_per_wave;
+  if (pipelined) *pipelined = P->split && P->d_phase && P->pipeline;
   if (xcd_remap) *xcd_remap = P->base.xcd_remap;
   return WFS_OK;
 }
@@ -947,6 +953,23 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   }
   P->base = best;
   P->split = best_split;
+  if (e == hipSuccess && P->split && P->d_phase) {
+    // frames in a row: pipelined against one frame after the other (same schedule)
+    const int n = std::max(2, iters);
+    double t[2] = {0.0, 0.0};
+    for (int pipe = 0; pipe < 2 && e == hipSuccess; ++pipe) {
+      e = run_steps(P, layers, 0, n, 1, slopes, aux, false, pipe == 1, st);  // warm-up
+      if (e != hipSuccess) break;
+      (void)hipEventRecord(e0, st);
+      e = run_steps(P, layers, 0, n, 1, slopes, aux, false, pipe == 1, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      t[pipe] = ms;
+    }
+    if (e == hipSuccess) P->pipeline = t[1] < t[0];
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(slopes);

@@ -97,7 +97,6 @@ struct FwdParams {
   // schedule
   int32_t otf_blocks;       // blocks serving the lag-domain tasks
   int32_t fft_blocks;       // blocks serving FFT tasks (one subaperture each), launched first
-  int32_t subaps_per_wave;  // lag-domain tasks per wave (always 1)
   int32_t xcd_remap;
   int32_t lds_per_wave;     // bytes (lag-domain waves, or a quarter of an FFT workgroup)
   int32_t lds_per_wave_otf; // bytes when the launch holds no FFT-path blocks

@@ -139,11 +139,11 @@ class Plan:
         return slopes, aux
 
     def schedule(self):
-        """dict(split, subaps_per_wave, xcd_remap) of the current launch schedule."""
+        """dict(split, pipelined, xcd_remap) of the current launch schedule."""
         v = [ctypes.c_int32() for _ in range(3)]
         L.check(self._lib.wfs_plan_schedule(self._h, *[ctypes.byref(x) for x in v]),
                 "wfs_plan_schedule")
-        return dict(split=v[0].value, subaps_per_wave=v[1].value, xcd_remap=v[2].value)
+        return dict(split=v[0].value, pipelined=v[1].value, xcd_remap=v[2].value)
 
     def footprint(self, step=0):
         """(distinct layer pixels read, projected pixels) per realisation at ``step``."""

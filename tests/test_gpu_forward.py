@@ -192,6 +192,23 @@ def test_forward_steps_config1_equals_single_frames():
         assert torch.equal(s[k], s1)
 
 
+def test_forward_steps_after_tune_config2_equals_single_frames():
+    """Config 2 (6 LGS + 3 NGS, 8 realisations) after the tuner has chosen between pipelined
+    and one-frame-after-the-other steps: each frame equals the single-frame call."""
+    torch, W = _gpu()
+    cfg = synth.config2(batch=8)
+    x = synth.make_batch(cfg, range(8))
+    plan = W.Plan(cfg, batch=8)
+    xt = torch.from_numpy(x).cuda()
+    plan.tune(xt, iters=2)
+    sch = plan.schedule()
+    assert sch["pipelined"] in (0, 1) and (sch["split"] or not sch["pipelined"])
+    s, a = plan.forward_steps(xt, 11, 3)
+    for k in range(3):
+        s1, a1 = plan.forward(xt, step=11 + k)
+        assert torch.equal(s[k], s1) and torch.equal(a[k], a1), (k, sch)
+
+
 def test_footprint_matches_oracle_coordinates():
     """Distinct layer pixels under the bilinear stencils of the valid subapertures' pixels."""
     torch, W = _gpu()
