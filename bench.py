@@ -149,7 +149,7 @@ def bench_config1(torch, W, steps, warmup, k0=0, tune=True, flags=0):
     out = dict(cfg=cfg, plan=plan, wall=wallK, gpu_ms_per_frame=gpu_msK,
                single_wall=wall1, single_gpu_ms_per_frame=gpu_ms1,
                kernel_ms_eager=kernel_ms_eager, tuned_us=tuned_us, x=x,
-               schedule=plan.schedule(), pipelined=plan.schedule()["pipelined"] == 1)
+               schedule=plan.schedule(), pipelined=plan.schedule()["frames"] != "sequential")
     out.update(kernel_split_ms(torch, plan, x, slopes, aux, k0, min(steps, 100)))
     return out
 
@@ -319,11 +319,11 @@ def cpu_baseline_pool(frames_per_core=4):
 
 
 def profile_run(torch, W, n, flags=0):
-    """Short run for a profiler: the headline's pipelined frames (one projection, then n spot
-    launches that also project the next step) and n plain copies of 256 MiB, the HBM counter
-    calibration.  The plan keeps its default schedule (split, one subaperture per wave, XCD
-    block order), the one the autotuner picks for config 1 in unprofiled runs: timings taken
-    under counter collection would mislead the tuner."""
+    """Short run for a profiler: the headline's n frames through wfs_forward_steps (with the
+    default schedule, one staged-footprint launch for all n frames), one split frame
+    (projection kernel, then the spot kernel) for the projection's counters, and n plain
+    copies of 256 MiB, the HBM counter calibration.  The plans keep their default schedules:
+    timings taken under counter collection would mislead the tuner."""
     cfg = synth.config1()
     x = torch.from_numpy(synth.make_batch(cfg, [0])).cuda()
     plan = W.Plan(cfg, flags=flags)
@@ -331,8 +331,10 @@ def profile_run(torch, W, n, flags=0):
     aK = torch.empty(n, 1, plan.n_valid_total, device="cuda")
     src = torch.empty(64 << 20, device="cuda")  # 256 MiB
     dst = torch.empty_like(src)
+    split = W.Plan(cfg, flags=flags | W.WFS_FLAG_SPLIT)
     torch.cuda.synchronize()
     plan.forward_steps(x, 0, n, slopes=sK, aux=aK)
+    split.forward(x, step=0, slopes=sK[0], aux=aK[0])
     for i in range(n):
         dst.copy_(src)
     torch.cuda.synchronize()
@@ -368,7 +370,10 @@ def recorded_traffic(kernel):
     if rec.get("source_digest") != kernel_source_digest():
         return None
     k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    if k is None:
+        return None
+    # per frame: a dispatch of the one-launch schedule covers several frames
+    return (k["fetch_bytes"] + k["write_bytes"]) / k.get("frames_per_dispatch", 1)
 
 
 def main():
@@ -418,22 +423,36 @@ def main():
     subaps = r1["plan"].n_valid[0]
     frames_per_s = args.steps / r1["wall"]
     flops = plan_flops(cfg1, r1["plan"])
-    # dominant kernel: the spot launch.  Pipelined (split schedule): one launch per frame that
-    # forms the spots of step k and projects step k+1; its mean duration is the replayed
-    # graph's time per frame less the one leading projection.  All of it is charged to the
-    # spot stage's FLOPs (the projection's bytes are reported separately).
-    if r1["pipelined"]:
+    # dominant kernel: the spot launch, all of it charged to the spot stage's FLOPs (its
+    # in-wave projection or the projection kernel's bytes are reported separately).
+    #   one launch (staged footprint): the K frames are one dispatch; per frame, the replayed
+    #     graph's time divided by K;
+    #   pipelined (split): one launch per frame that forms the spots of step k and projects
+    #     step k+1; the graph's time per frame less the one leading projection;
+    #   sequential split / gather: the spot launch of each frame.
+    frames = r1["schedule"]["frames"]
+    field = r1["schedule"]["field"]
+    if frames == "one_launch":
+        kern_ms = r1["gpu_ms_per_frame"]
+        kern_name = ("wfs_forward_kernel<10, footprint> (K frames in one launch, each wave "
+                     "projects its subaperture from a footprint staged in LDS)")
+        traffic_key = "wfs_forward_kernel<10, 2, false, false>"
+    elif frames == "pipelined":
         kern_ms = (r1["gpu_ms_per_frame"] * args.steps - r1["project_ms"]) / args.steps
-        kern_name = "wfs_forward_kernel<10> (spots of step k + projection of step k+1)"
-        traffic_key = "wfs_forward_kernel<10, false, false, true>"
-    elif r1["schedule"]["split"] == 1:
+        kern_name = "wfs_forward_kernel<10, split> (spots of step k + projection of step k+1)"
+        traffic_key = "wfs_forward_kernel<10, 1, false, true>"
+    elif field == "split":
         kern_ms = r1["gpu_ms_per_frame"] - r1["project_ms"]
-        kern_name = "wfs_forward_kernel<10> (spots)"
-        traffic_key = "wfs_forward_kernel<10, false, false, false>"
+        kern_name = "wfs_forward_kernel<10, split> (spots)"
+        traffic_key = "wfs_forward_kernel<10, 1, false, false>"
+    elif field == "footprint":
+        kern_ms = r1["gpu_ms_per_frame"]
+        kern_name = "wfs_forward_kernel<10, footprint> (one frame per launch)"
+        traffic_key = "wfs_forward_kernel<10, 2, false, false>"
     else:
         kern_ms = r1["gpu_ms_per_frame"]
-        kern_name = "wfs_forward_kernel<10> (fused gather)"
-        traffic_key = "wfs_forward_kernel<10, true, false, false>"
+        kern_name = "wfs_forward_kernel<10, gather> (per-pixel gather)"
+        traffic_key = "wfs_forward_kernel<10, 0, false, false>"
     achieved = flops / (kern_ms * 1e-3)
     foot, n_phase = r1["plan"].footprint(0)
     proj_bytes = 4.0 * (foot + n_phase)  # each layer pixel read once, each phase pixel written
@@ -453,7 +472,7 @@ def main():
         "config": {"workload": "config1: E-ELT 80x80 LGS, 39 m/11 m pupil, 4632 subaps of 10x10 "
                                "px, N=32, 8x8 px, 10 layers 1024^2 0-16 km, H=90 km, Na 10 km, "
                                "noise on", "frames_per_step": 1, "subaps": subaps,
-                   "graph_replay": True, "pipelined_frames": r1["pipelined"]},
+                   "graph_replay": True, "frames_schedule": r1["schedule"]["frames"]},
         "spots_per_s": frames_per_s * subaps,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,

@@ -49,10 +49,14 @@ enum {
 #define WFS_FLAG_FORCE_OTF (1u << 0)    /* every sensor on the lag-domain (autocorrelation) path */
 #define WFS_FLAG_FORCE_FFT (1u << 1)    /* every sensor on the FFT path (needs no elongation)     */
 #define WFS_FLAG_NO_XCD_REMAP (1u << 2) /* keep the hardware block order (no per-XCD grouping)    */
-#define WFS_FLAG_FUSED (1u << 3)        /* project inside the spot kernel (no projection pass and
-                                           no phase buffer); default: projection kernel first  */
+#define WFS_FLAG_FUSED (1u << 3)        /* spot waves gather the layers per pixel (no projection
+                                           pass); default: each wave stages its subaperture's
+                                           layer footprint in LDS where every lag-domain sensor
+                                           allows it, else a projection kernel first      */
 #define WFS_FLAG_ADJOINT_ATOMIC (1u << 4) /* wfs_adjoint scatters with FP32 atomics instead of
                                            the deterministic gather                        */
+#define WFS_FLAG_SPLIT (1u << 5)        /* projection kernel first, never the staged footprint
+                                           (same bits as the footprint field)             */
 
 /* `step` value meaning "read the step from the plan's device-resident counter". */
 #define WFS_STEP_DEVICE (-1)
@@ -137,13 +141,12 @@ int wfs_forward(wfs_plan_t plan, const float* layers, int64_t step, uint64_t see
  * wfs_forward_steps -- n_steps consecutive frames, steps step0 .. step0 + n_steps - 1 (or,
  *   with step0 = WFS_STEP_DEVICE, the device counter + 0 .. n_steps - 1; the counter is not
  *   advanced): the same results, bit for bit, as n_steps calls of wfs_forward.  slopes:
- *   device [n_steps][B][n_slopes]; aux: device [n_steps][B][n_valid_total] or NULL.  With the
- *   split schedule the frames are pipelined unless wfs_plan_tune found that slower (large
- *   batches, where each launch fills the chip on its own): each launch forms the spots of step k and
- *   projects the layers for step k + 1 into the plan's second phase buffer, so the
- *   memory-latency-bound projection overlaps the arithmetic-bound spot stage (frozen flow,
- *   Sec. 2.1, makes every frame's input known in advance).  Layers must not change during
- *   the call.
+ *   device [n_steps][B][n_slopes]; aux: device [n_steps][B][n_valid_total] or NULL.  The
+ *   frames run as wfs_plan_schedule's `frames` says: with the staged footprint, one launch
+ *   covers every frame (frame k's blocks follow frame k - 1's: no launch gap, no phase
+ *   buffer); pipelined, each launch forms the spots of step k and projects the layers for
+ *   step k + 1 into the plan's second phase buffer.  Frozen flow (Sec. 2.1) makes every
+ *   frame's input known in advance.  Layers must not change during the call.
  */
 int wfs_forward_steps(wfs_plan_t plan, const float* layers, int64_t step0, int32_t n_steps,
                       uint64_t seed, float* slopes, float* aux, void* stream);
@@ -159,13 +162,16 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
 
 /*
  * wfs_plan_schedule -- the launch schedule the plan currently uses (set at creation, changed
- *   by wfs_plan_tune): split = 1 when a frame is the projection kernel followed by the spot
- *   kernel, 0 when the spot kernel gathers the layers itself; pipelined = 1 when
- *   wfs_forward_steps projects frame k + 1 inside the spot launch of frame k (split schedule
- *   only), 0 when it runs the frames one after the other; xcd_remap = 1 when blocks are
- *   renumbered so neighbouring tasks share an XCD.  Any output pointer may be NULL.
+ *   by wfs_plan_tune).  field: where wfs_forward's lag-domain waves get the phase, 0 = they
+ *   gather the layers per pixel (WFS_FLAG_FUSED), 1 = a projection kernel writes it first
+ *   (split), 2 = each wave stages its subaperture's layer footprint in LDS and projects it
+ *   itself (one launch, no phase buffer).  frames: how wfs_forward_steps runs, 0 = one
+ *   wfs_forward per frame, 1 = pipelined split frames, 2 = one footprint launch for all
+ *   frames.  Fields 1 and 2 and frames 0-2 give the same bits; field 0 its own.  xcd_remap = 1
+ *   when blocks are renumbered so neighbouring tasks share an XCD.  Any output pointer may be
+ *   NULL.
  */
-int wfs_plan_schedule(wfs_plan_t plan, int32_t* split, int32_t* pipelined, int32_t* xcd_remap);
+int wfs_plan_schedule(wfs_plan_t plan, int32_t* field, int32_t* frames, int32_t* xcd_remap);
 
 /*
  * wfs_plan_footprint -- algorithmic read footprint of the projection at time step `step`:

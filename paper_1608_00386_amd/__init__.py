@@ -7,6 +7,7 @@ from ._lib import (  # noqa: F401
     WFS_FLAG_FUSED,
     WFS_FLAG_FORCE_OTF,
     WFS_FLAG_NO_XCD_REMAP,
+    WFS_FLAG_SPLIT,
     WFS_STEP_DEVICE,
     WfsError,
     lib,

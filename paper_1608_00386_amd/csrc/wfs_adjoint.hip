@@ -54,12 +54,12 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   const float gy = ap.grad_slopes[(int64_t)b * p.n_slopes + S.slope_off + S.n_valid + v];
   float s0, cx, cy;
   if (ap.fwd_slopes) {
-    otf_field<NS, FUSED>(p, S, sb, sid, b, (double)step, wsm, lo);
+    otf_field<NS, FUSED ? kFieldGather : kFieldPhase>(p, S, sb, sid, b, (double)step, wsm, lo);
     s0 = ap.fwd_aux[(int64_t)b * p.n_valid_total + S.aux_off + v];
     cx = ap.fwd_slopes[(int64_t)b * p.n_slopes + S.slope_off + v];
     cy = ap.fwd_slopes[(int64_t)b * p.n_slopes + S.slope_off + S.n_valid + v];
   } else {
-    otf_spot<NS, FUSED>(p, S, sb, sid, b, step, wsm, lo);
+    otf_spot<NS, FUSED ? kFieldGather : kFieldPhase>(p, S, sb, sid, b, step, wsm, lo);
     const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));
     s0 = c.s0;
     cx = s0 > 0.0f ? c.sx / s0 : 0.0f;

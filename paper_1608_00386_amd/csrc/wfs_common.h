@@ -124,8 +124,10 @@ __device__ __forceinline__ Tap make_tap(double c, int32_t n, double inv_n, int32
     const float f = (float)(cc - f0);
     const bool ok0 = i0 >= 0 && i0 < n;
     const bool ok1 = i0 + 1 >= 0 && i0 + 1 < n;
-    t.i0 = ok0 ? i0 * scale : 0;
-    t.i1 = ok1 ? (i0 + 1) * scale : 0;
+    // a tap off the grid has weight 0 and reads the nearest grid element (any finite value
+    // would do; the nearest one is what a footprint staged with clamped indices holds)
+    t.i0 = min(max(i0, 0), n - 1) * scale;
+    t.i1 = min(max(i0 + 1, 0), n - 1) * scale;
     t.w0 = ok0 ? 1.0f - f : 0.0f;
     t.w1 = ok1 ? f : 0.0f;
   }

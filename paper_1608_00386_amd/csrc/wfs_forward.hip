@@ -63,8 +63,8 @@ hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st) {
   return launch_forward_ns(c, ns, st);
 }
 
-int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps) {
-  return otf_lds_layout(ns, n_layers, n_pix, with_taps).total;
+int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats) {
+  return otf_lds_layout(ns, n_layers, n_pix, with_taps, foot_floats).total;
 }
 
 int project_lds_bytes(int n_layers) {

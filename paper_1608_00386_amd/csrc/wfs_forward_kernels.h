@@ -5,8 +5,9 @@
 //                              with (pipelined frames) the next step's projection blocks spread
 //                              evenly among them
 // The mode is a template parameter so that each kernel only holds the registers of its own
-// paths: FUSED gathers the layers in the lag-domain waves, FFT adds the FFT-path blocks, PROJ
-// the projection blocks.
+// paths: FIELD says where the lag-domain waves get the phase (kField*), FFT adds the FFT-path
+// blocks, PROJ the projection blocks.  With the staged footprint (kFieldFoot) one launch can
+// cover several frames: the lag-domain blocks repeat once per frame, frame k at step + k.
 #pragma once
 
 #include "wfs_fft.h"
@@ -24,9 +25,10 @@ constexpr int otf_waves_per_simd() {
   return NS <= 10 ? 5 : (NS == 11 ? 4 : 3);
 }
 
-template <int NS, bool FUSED, bool FFT, bool PROJ>
+template <int NS, int FIELD, bool FFT, bool PROJ>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu((FUSED || FFT) ? 1 : otf_waves_per_simd<NS, PROJ>())))
+__attribute__((amdgpu_waves_per_eu((FIELD == kFieldGather || FFT) ? 1
+                                                                  : otf_waves_per_simd<NS, PROJ>())))
 void wfs_forward_kernel(
     FwdParams p) {
   extern __shared__ __align__(16) char smem[];
@@ -53,18 +55,23 @@ void wfs_forward_kernel(
     }
     L -= c1;
   }
+  int frame = 0;
+  if constexpr (FIELD == kFieldFoot) {  // blocks of frame k follow those of frame k - 1
+    frame = L / p.otf_blocks;
+    L -= frame * p.otf_blocks;
+  }
   const int wave = threadIdx.x >> 6;
   char* wsm = smem + wave * p.lds_per_wave;
   const int total = p.otf.per_real * p.batch;
   // one subaperture per wave and no task loop: a loop would let the compiler hoist per-lane
   // index arithmetic out of it and hold those registers across every stage
   const int t = L * kWavesPerBlock + wave;
-  if (t < total) otf_subap<NS, FUSED>(p, t, step, wsm);
+  if (t < total) otf_subap<NS, FIELD>(p, t, step + frame, wsm, frame);
 }
 
-template <int NS, bool FUSED, bool FFT, bool PROJ>
+template <int NS, int FIELD, bool FFT, bool PROJ>
 static hipError_t launch_fwd_mode(const FwdParams& p, int grid, int lds, hipStream_t st) {
-  hipLaunchKernelGGL((wfs_forward_kernel<NS, FUSED, FFT, PROJ>), dim3(grid), dim3(kBlock), lds,
+  hipLaunchKernelGGL((wfs_forward_kernel<NS, FIELD, FFT, PROJ>), dim3(grid), dim3(kBlock), lds,
                      st, p);
   return hipGetLastError();
 }
@@ -72,21 +79,30 @@ static hipError_t launch_fwd_mode(const FwdParams& p, int grid, int lds, hipStre
 // Launch of the spot kernel for subaperture size NS (lag-domain path), mode from the params.
 template <int NS>
 hipError_t launch_fwd_ns(const FwdParams& p, hipStream_t st) {
-  const int grid = p.fft_blocks + p.otf_blocks + p.proj_blocks;
-  if (grid == 0) return hipSuccess;
+  const bool foot = p.otf_from_phase == kFieldFoot;
+  const int64_t grid64 = (int64_t)p.fft_blocks + p.proj_blocks +
+                         (int64_t)p.otf_blocks * (foot ? p.n_frames : 1);
+  if (grid64 == 0) return hipSuccess;
+  if (grid64 > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const int grid = (int)grid64;
   int lds = p.lds_per_wave * kWavesPerBlock;
   if (p.proj_blocks > 0 && p.proj_lds > lds) lds = p.proj_lds;
-  const bool fused = !p.otf_from_phase, fft = p.fft_blocks > 0, proj = p.proj_blocks > 0;
+  const bool fused = p.otf_from_phase == kFieldGather, fft = p.fft_blocks > 0,
+             proj = p.proj_blocks > 0;
+  if (foot) {  // one launch for every frame; no FFT-path or projection blocks
+    if (fft || proj || p.n_frames < 1) return hipErrorInvalidValue;
+    return launch_fwd_mode<NS, kFieldFoot, false, false>(p, grid, lds, st);
+  }
   if (fused) {  // the pipelined projection only exists in the split schedule
     if (proj) return hipErrorInvalidValue;
-    return fft ? launch_fwd_mode<NS, true, true, false>(p, grid, lds, st)
-               : launch_fwd_mode<NS, true, false, false>(p, grid, lds, st);
+    return fft ? launch_fwd_mode<NS, kFieldGather, true, false>(p, grid, lds, st)
+               : launch_fwd_mode<NS, kFieldGather, false, false>(p, grid, lds, st);
   }
   if (fft)
-    return proj ? launch_fwd_mode<NS, false, true, true>(p, grid, lds, st)
-                : launch_fwd_mode<NS, false, true, false>(p, grid, lds, st);
-  return proj ? launch_fwd_mode<NS, false, false, true>(p, grid, lds, st)
-              : launch_fwd_mode<NS, false, false, false>(p, grid, lds, st);
+    return proj ? launch_fwd_mode<NS, kFieldPhase, true, true>(p, grid, lds, st)
+                : launch_fwd_mode<NS, kFieldPhase, true, false>(p, grid, lds, st);
+  return proj ? launch_fwd_mode<NS, kFieldPhase, false, true>(p, grid, lds, st)
+              : launch_fwd_mode<NS, kFieldPhase, false, false>(p, grid, lds, st);
 }
 
 }  // namespace wfs

@@ -28,7 +28,7 @@ hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* g
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
                         int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma);
-int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps);
+int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats);
 int fft_lds_bytes(int n_sub, int n_fft, int n_pix);
 bool fft_supported(int n_sub, int n_fft, int bin);
 }  // namespace wfs
@@ -102,7 +102,13 @@ struct wfs_plan_s {
   float* d_phase = nullptr;   // split-mode phase buffer [B][phase_per_real]
   float* d_phase2 = nullptr;  // second buffer (pipelined frames), same allocation
   int split = 0;             // 1: projection kernel + spot kernel; 0: fused gather
-  int pipeline = 1;          // wfs_forward_steps: projection of frame k+1 in spot launch k
+  int foot_ok = 0;           // every lag-domain sensor can stage its footprint, no FFT path
+  int foot = 0;              // staged-footprint field (overrides split / fused gather)
+  // wfs_forward_steps: 0 one wfs_forward per frame, 1 pipelined split frames, 2 one
+  // staged-footprint launch for all frames (1 and 2 only when the single-frame field is the
+  // split or the footprint one: all three give the same bits)
+  int frames = 0;
+  int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
@@ -299,6 +305,11 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<int> otf_ids, fft_ids;
   std::vector<int32_t> subidx;
   std::vector<std::vector<int2>> proj_desc_s(n_sensors);  // projection blocks per sensor
+  std::vector<int4> foot((size_t)n_sensors * n_layers, make_int4(0, 0, 0, 0));
+  std::vector<FootCol> foot_cols;
+  std::vector<FootAxis> foot_axis((size_t)n_sensors * n_layers * 2);
+  bool foot_ok = true;
+  int foot_max_floats = 0;
   int32_t slope_off = 0, aux_off = 0;
   int64_t phase_off = 0, pupil_off = 0;
   int otf_ns = 0;
@@ -448,6 +459,48 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       A.inv_ax = 1.0 / A.ax;
       A.inv_ay = 1.0 / A.ay;
     }
+    // staged footprint of one subaperture: n_sub consecutive pixels span (n_sub - 1)|a|
+    // layer pixels, so their stencils touch at most ceil((n_sub - 1)|a|) + 2 grid lines per
+    // axis (a margin covers the rounding of the FP64 coordinates)
+    if (path == kPathOtf) {
+      int cols = 0, floats = 0;
+      bool ok = true;
+      for (int l = 0; l < n_layers && ok; ++l) {
+        const wfs_layer_desc& L = layers[l];
+        const DevAffine& A = aff[(size_t)s * n_layers + l];
+        const double ex = (S.n_sub - 1) * std::fabs(A.ax), ey = (S.n_sub - 1) * std::fabs(A.ay);
+        if (!(ex < 64.0 && ey < 64.0)) {
+          ok = false;
+          break;
+        }
+        const int fw = (int)std::ceil(ex + 1e-7) + 2, fh = (int)std::ceil(ey + 1e-7) + 2;
+        ok = fh <= S.n_sub + 2 && cols + fw <= kFootMaxCols &&
+             (L.boundary != 0 || (fw <= L.nx && fh <= L.ny)) &&
+             L.offset + (int64_t)L.nx * L.ny <= (1LL << 30);
+        if (!ok) break;
+        foot[(size_t)s * n_layers + l] = make_int4(fw, fh, floats, 0);
+        for (int j = 0; j < fw; ++j)
+          foot_cols.push_back(FootCol{(int32_t)L.offset, L.nx, L.ny, L.boundary, fw, fh,
+                                      floats + j, (l << 8) | j});
+        FootAxis& X = foot_axis[((size_t)s * n_layers + l) * 2];
+        FootAxis& Y = foot_axis[((size_t)s * n_layers + l) * 2 + 1];
+        X = FootAxis{A.ax, A.bx0, A.dbx, 1.0 / L.nx, L.nx, L.boundary, 1, 0, 1.0f, {0, 0, 0}};
+        Y = FootAxis{A.ay, A.by0, A.dby, 1.0 / L.ny, L.ny, L.boundary, fw, floats, L.weight,
+                     {0, 0, 0}};
+        cols += fw;
+        floats += fw * fh;
+      }
+      if (ok) {
+        d.foot_cols_off = (int32_t)foot_cols.size() - cols;
+        d.foot_ncols = cols;
+        d.foot_floats = floats;
+        foot_max_floats = std::max(foot_max_floats, floats);
+      } else {
+        foot_ok = false;
+      }
+    } else {
+      foot_ok = false;  // the FFT path reads the projected phase
+    }
   }
   P->hsen = ds;
   P->n_slopes = slope_off;
@@ -467,6 +520,10 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   const size_t o_wtab = push_table(blob, wtab);
   const size_t o_mtab = push_table(blob, mtab);
   const size_t o_subidx = push_table(blob, subidx);
+  const size_t o_foot = push_table(blob, foot);
+  if (foot_cols.empty()) foot_cols.push_back(FootCol{});
+  const size_t o_fcols = push_table(blob, foot_cols);
+  const size_t o_faxis = push_table(blob, foot_axis);
   std::vector<int2> desc_all, desc_fft;
   for (int s = 0; s < n_sensors; ++s) {
     desc_all.insert(desc_all.end(), proj_desc_s[s].begin(), proj_desc_s[s].end());
@@ -499,6 +556,10 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.wtab = reinterpret_cast<const float2*>(P->d_blob + o_wtab);
   b.mtab = reinterpret_cast<const float*>(P->d_blob + o_mtab);
   b.subidx = reinterpret_cast<const int32_t*>(P->d_blob + o_subidx);
+  b.foot = reinterpret_cast<const int4*>(P->d_blob + o_foot);
+  b.foot_cols = reinterpret_cast<const FootCol*>(P->d_blob + o_fcols);
+  b.foot_axis = reinterpret_cast<const FootAxis*>(P->d_blob + o_faxis);
+  b.n_frames = 1;
   P->proj_all.desc = reinterpret_cast<const int2*>(P->d_blob + o_pall);
   P->proj_all.per_real = (int32_t)desc_all.size();
   P->proj_fft.desc = reinterpret_cast<const int2*>(P->d_blob + o_pfft);
@@ -545,7 +606,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     lds_fft = std::max(lds_fft, fft_lds_bytes(sensors[s].n_sub, sensors[s].n_fft,
                                               sensors[s].n_fft / sensors[s].bin));
   auto wave_lds = [&](bool taps, bool with_fft) {
-    int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps) : 0;
+    int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps, 0) : 0;
     if (with_fft) w = std::max(w, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
     return std::max(16, (w + 15) & ~15);
   };
@@ -558,6 +619,10 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   P->lds_fused = lds_wave;
   P->lds_split = wave_lds(false, true);
+  P->lds_foot = otf_ns ? std::max(16, (otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, false,
+                                                     foot_max_floats) + 15) & ~15)
+                       : 0;
+  P->foot_ok = otf_ns && foot_ok && fft_ids.empty() && P->lds_foot * kWavesPerBlock <= 65536;
   P->lds_fused_otf = wave_lds(true, false);
   P->lds_split_otf = wave_lds(false, false);
   b.lds_per_wave = P->lds_split;
@@ -580,6 +645,9 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   P->base.proj_lds = P->proj_lds;
   P->split = (flags & WFS_FLAG_FUSED) ? 0 : 1;
   if (P->proj_lds > 65536) P->split = 0;  // taps of one subaperture exceed the LDS budget
+  if (flags & WFS_FLAG_SPLIT) P->foot_ok = 0;
+  P->foot = (P->foot_ok && !(flags & WFS_FLAG_FUSED)) ? 1 : 0;
+  P->frames = P->foot ? 2 : (P->split && P->d_phase ? 1 : 0);
   if (P->proj_lds_fft > 65536) {
     (void)hipFree(P->d_blob);
     if (P->d_phase) (void)hipFree(P->d_phase);
@@ -651,6 +719,13 @@ static FwdParams call_params(wfs_plan_t P, const float* layers, int64_t step, ui
 
 // fused: one launch; split: projection into the plan's phase buffer, then the spot launch
 static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
+  if (P->foot) {  // staged footprint: the spot launch alone (no FFT-path sensor here)
+    p.otf_from_phase = 2;
+    p.n_frames = 1;
+    p.lds_per_wave = P->lds_foot;
+    p.lds_per_wave_otf = P->lds_foot;
+    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+  }
   const bool split = P->split && P->d_phase;
   if (split || P->fft_tasks > 0) {  // FFT-path sensors always read the projected phase
     set_proj(p, split ? P->proj_all : P->proj_fft);
@@ -678,15 +753,16 @@ int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, 
   return WFS_OK;
 }
 
-// Frames step0 .. step0 + n - 1 (or the device counter + k).  Outputs of frame k at slopes +
-// k * (slopes of one frame) when `advance_out`, else every frame overwrites the first.
-// Pipelined (split schedule only): project frame 0; then launch k computes the spots of frame k
-// from phase buffer k % 2 and projects frame k + 1 into the other buffer.
+// Frames step0 .. step0 + n - 1 (or the device counter + k), outputs of frame k at slopes +
+// k * (slopes of one frame).  Staged footprint: one launch for all frames.  Pipelined (split
+// schedule only): project frame 0; then launch k computes the spots of frame k from phase
+// buffer k % 2 and projects frame k + 1 into the other buffer.
 static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, int n,
-                            uint64_t seed, float* slopes, float* aux, bool advance_out,
-                            bool pipelined, hipStream_t st) {
-  const int64_t ns_per = advance_out ? (int64_t)P->n_slopes * P->batch : 0;
-  const int64_t na_per = advance_out ? (int64_t)P->n_valid_total * P->batch : 0;
+                            uint64_t seed, float* slopes, float* aux, int frames,
+                            hipStream_t st) {
+  const bool pipelined = frames == 1;
+  const int64_t ns_per = (int64_t)P->n_slopes * P->batch;
+  const int64_t na_per = (int64_t)P->n_valid_total * P->batch;
   auto frame = [&](int k) {
     const int64_t s = step0 == WFS_STEP_DEVICE ? WFS_STEP_DEVICE : step0 + k;
     FwdParams p = call_params(P, layers, s, seed, slopes + k * ns_per, aux ? aux + k * na_per : nullptr);
@@ -694,6 +770,14 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
     return p;
   };
   hipError_t e = hipSuccess;
+  if (frames == 2) {
+    FwdParams p = frame(0);
+    p.otf_from_phase = 2;
+    p.n_frames = n;
+    p.lds_per_wave = P->lds_foot;
+    p.lds_per_wave_otf = P->lds_foot;
+    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+  }
   if (!pipelined) {
     for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_fwd_modes(P, frame(k), st);
     return e;
@@ -729,8 +813,8 @@ int wfs_forward_steps(wfs_plan_t P, const float* layers, int64_t step0, int32_t 
     return fail(WFS_EINVAL, "wfs_forward_steps: step overflow");
   rc = check_device(P, "wfs_forward_steps");
   if (rc) return rc;
-  hipError_t e = run_steps(P, layers, step0, n_steps, seed, slopes, aux, true,
-                           P->split && P->d_phase && P->pipeline, (hipStream_t)stream);
+  hipError_t e = run_steps(P, layers, step0, n_steps, seed, slopes, aux, P->frames,
+                           (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_forward_steps: launch");
   return WFS_OK;
 }
@@ -751,10 +835,11 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
   return WFS_OK;
 }
 
-int wfs_plan_schedule(wfs_plan_t P, int32_t* split, int32_t* pipelined, int32_t* xcd_remap) {
+int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xcd_remap) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_schedule: null plan");
-  if (split) *split = P->split;
-  if (pipelined) *pipelined = P->split && P->d_phase && P->pipeline;
+  const bool split = P->split && P->d_phase;
+  if (field) *field = P->foot ? 2 : (split ? 1 : 0);
+  if (frames) *frames = P->frames;
   if (xcd_remap) *xcd_remap = P->base.xcd_remap;
   return WFS_OK;
 }
@@ -884,7 +969,7 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   a.gpsi = gather ? P->d_gimg : nullptr;
   a.f.lds_per_wave = P->adj_lds_per_wave;
   hipError_t e = hipSuccess;
-  if (P->split && P->d_phase) {  // subaperture fields from the projection kernel's phase
+  if ((P->split || P->foot) && P->d_phase) {  // subaperture fields from the projection kernel's phase
     set_proj(a.f, P->proj_all);
     e = launch_project(a.f, P->d_phase, P->proj_lds, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: projection launch");
@@ -908,10 +993,13 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   int rc = check_device(P, "wfs_plan_tune");
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  const int nf = std::max(2, iters);  // frames of the multi-frame candidates
   float *slopes = nullptr, *aux = nullptr;
-  HIP_TRY(hipMalloc((void**)&slopes, sizeof(float) * (size_t)std::max(1, P->n_slopes) * P->batch),
+  HIP_TRY(hipMalloc((void**)&slopes,
+                    sizeof(float) * (size_t)std::max(1, P->n_slopes) * P->batch * nf),
           "wfs_plan_tune: scratch");
-  hipError_t e = hipMalloc((void**)&aux, sizeof(float) * (size_t)std::max(1, P->n_valid_total) * P->batch);
+  hipError_t e = hipMalloc((void**)&aux,
+                           sizeof(float) * (size_t)std::max(1, P->n_valid_total) * P->batch * nf);
   if (e != hipSuccess) {
     (void)hipFree(slopes);
     return hip_fail(e, "wfs_plan_tune: scratch");
@@ -919,56 +1007,66 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
+  auto elapsed_ms = [&]() {
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return (double)ms;
+  };
   const FwdParams keep = P->base;
+  const int keep_split = P->split, keep_foot = P->foot, keep_frames = P->frames;
   FwdParams best = keep;
   double best_t = 1e30;
-  const int keep_split = P->split;
-  int best_split = keep_split;
-  for (int mode = 0; mode < 4; ++mode) {
-    const int remap = mode & 1;
-    P->split = (mode >> 1) & 1;
-    if (P->split && (!P->d_phase || P->proj_lds > 65536)) continue;
-    if (P->flags & WFS_FLAG_FUSED) P->split = 0;
-    {
-      FwdParams c = keep;
-      c.xcd_remap = remap;
-      P->base = c;
-      FwdParams p = call_params(P, layers, 0, 1, slopes, aux);
-      e = launch_fwd_modes(P, p, st);  // warm-up
-      if (e != hipSuccess) break;
-      (void)hipEventRecord(e0, st);
-      for (int it = 0; it < iters; ++it) e = launch_fwd_modes(P, p, st);
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      const double us = 1000.0 * ms / iters;
-      if (e == hipSuccess && us < best_t) {
-        best_t = us;
-        best = c;
-        best_split = P->split;
-      }
+  int best_field = P->foot ? 2 : (P->split ? 1 : 0);
+  // single frames: field source (gather, split, staged footprint) x block order
+  for (int mode = 0; mode < 6; ++mode) {
+    const int remap = mode & 1, field = mode >> 1;
+    if (field == 1 && (!P->d_phase || P->proj_lds > 65536)) continue;
+    if (field == 2 && !P->foot_ok) continue;
+    if ((P->flags & WFS_FLAG_FUSED) && field != 0) continue;
+    if ((P->flags & WFS_FLAG_SPLIT) && field != 1) continue;
+    P->split = field == 1;
+    P->foot = field == 2;
+    FwdParams c = keep;
+    c.xcd_remap = remap;
+    P->base = c;
+    FwdParams p = call_params(P, layers, 0, 1, slopes, aux);
+    e = launch_fwd_modes(P, p, st);  // warm-up
+    if (e != hipSuccess) break;
+    (void)hipEventRecord(e0, st);
+    for (int it = 0; it < iters; ++it) e = launch_fwd_modes(P, p, st);
+    (void)hipEventRecord(e1, st);
+    const double us = 1000.0 * elapsed_ms() / iters;
+    if (e == hipSuccess && us < best_t) {
+      best_t = us;
+      best = c;
+      best_field = field;
     }
     if (e != hipSuccess) break;
   }
   P->base = best;
-  P->split = best_split;
-  if (e == hipSuccess && P->split && P->d_phase) {
-    // frames in a row: pipelined against one frame after the other (same schedule)
-    const int n = std::max(2, iters);
-    double t[2] = {0.0, 0.0};
-    for (int pipe = 0; pipe < 2 && e == hipSuccess; ++pipe) {
-      e = run_steps(P, layers, 0, n, 1, slopes, aux, false, pipe == 1, st);  // warm-up
+  P->split = best_field == 1 ? 1 : keep_split;
+  P->foot = best_field == 2;
+  if (best_field == 0) P->split = 0;
+  P->frames = 0;
+  if (e == hipSuccess && best_field != 0) {
+    // frames in a row: one wfs_forward after the other, pipelined split frames, one
+    // footprint launch (the same bits whichever runs)
+    double tbest = 1e30;
+    for (int fr = 0; fr < 3 && e == hipSuccess; ++fr) {
+      if (fr == 1 && !(P->d_phase && P->proj_lds <= 65536)) continue;
+      if (fr == 2 && !P->foot_ok) continue;
+      e = run_steps(P, layers, 0, nf, 1, slopes, aux, fr, st);  // warm-up
       if (e != hipSuccess) break;
       (void)hipEventRecord(e0, st);
-      e = run_steps(P, layers, 0, n, 1, slopes, aux, false, pipe == 1, st);
+      e = run_steps(P, layers, 0, nf, 1, slopes, aux, fr, st);
       (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      t[pipe] = ms;
+      const double ms = elapsed_ms();
+      if (e == hipSuccess && ms < tbest) {
+        tbest = ms;
+        P->frames = fr;
+      }
     }
-    if (e == hipSuccess) P->pipeline = t[1] < t[0];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -977,6 +1075,8 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   if (e != hipSuccess) {
     P->base = keep;
     P->split = keep_split;
+    P->foot = keep_foot;
+    P->frames = keep_frames;
     return hip_fail(e, "wfs_plan_tune: launch");
   }
   if (best_us) *best_us = best_t;

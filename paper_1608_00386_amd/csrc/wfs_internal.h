@@ -48,10 +48,33 @@ struct DevSensor {
   int32_t wtab_off;  // first entry of this sensor's n_pix-point twiddle table
   float inv_npix;    // 1 / n_pix
   int32_t subidx_off;  // first entry of this sensor's [n_sa][n_sa] valid-index table (-1 = unused)
-  int32_t pad2;
+  int32_t foot_ncols;  // staged footprint: layer columns of one subaperture, all layers
   float inv_nsub;    // 1 / n_sub
   int32_t mtab_off;  // matrix-core image operands (n_pix <= 8), -1: vector path
   int32_t pupil_off;  // offset of this sensor's [n_pup][n_pup] image in a pupil-frame buffer
+  int32_t foot_cols_off;  // first entry of this sensor's footprint-column table
+  int32_t foot_floats;    // footprint floats of one subaperture, all layers
+  int32_t pad3;
+};
+
+// Staged-footprint field: the layer pixels one subaperture's bilinear stencils can touch,
+// per layer a [rows][cols] window (bounds fixed per sensor and layer) at a running offset.
+constexpr int kFootMaxCols = 2 * kWave;  // columns summed over layers: two per lane
+
+// One axis of one (sensor, layer) for the staged footprint: coordinate c = a i + b0 + k db of
+// pupil index i at step k on a grid of n points (1/n, boundary), and how a stencil entry is
+// stored: weights times `weight`, window index koff + kmul * (tap - window origin).
+struct FootAxis {
+  double a, b0, db, inv_n;
+  int32_t n, boundary, kmul, koff;
+  float weight;
+  int32_t pad[3];
+};
+
+// One window column of one sensor's footprint: where it is read and where it goes.
+struct FootCol {
+  int32_t offset, nx, ny, boundary;  // layer start (floats), grid, 0 periodic / 1 zero
+  int32_t fw, fh, dst, lj;           // window columns and rows, first LDS float, layer << 8 | column
 };
 
 struct DevSubap {
@@ -100,7 +123,7 @@ struct FwdParams {
   int32_t xcd_remap;
   int32_t lds_per_wave;     // bytes (lag-domain waves, or a quarter of an FFT workgroup)
   int32_t lds_per_wave_otf; // bytes when the launch holds no FFT-path blocks
-  int32_t otf_from_phase;   // lag-domain path reads phase_in (split mode) instead of gathering
+  int32_t otf_from_phase;   // lag-domain field source: 0 gather, 1 phase_in (split), 2 footprint
   TaskTable otf;
   TaskTable fft;
   // projection blocks of one realisation: (first pupil row | column strip << 16, sensor)
@@ -114,6 +137,12 @@ struct FwdParams {
   int32_t proj_blocks;       // projection blocks interleaved with the spot blocks (0: none)
   int32_t proj_lds;          // bytes of LDS a projection block needs
   float* phase_out;
+  // staged footprint: per (sensor, layer) {cols, rows, first float, 0}, the per-axis
+  // coordinate tables and the window columns; frames of one launch
+  const int4* foot;
+  const FootAxis* foot_axis;   // [n_sensors][n_layers][2] (x, y)
+  const FootCol* foot_cols;    // per sensor: its window columns, layer by layer
+  int32_t n_frames;
 };
 
 struct AdjParams {

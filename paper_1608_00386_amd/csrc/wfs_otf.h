@@ -17,6 +17,7 @@
 #pragma once
 
 #include "wfs_common.h"
+#include "wfs_project.h"
 
 namespace wfs {
 
@@ -46,12 +47,16 @@ __host__ __device__ constexpr int otf_jobs_per_round(int ns) {
 //          partial lag rows (one round, one pass over the lag row at a time:
 //          [jobs][ceil((2 n_sub - 1) / kOtfLagParts)] float2),
 //          P (later B) + Z (after the last round) )
+// With a staged footprint (foot_floats > 0) the field stage also lays out, from the start of
+// AW (free until the lag sums): stencil entries [n_layers][2 n_sub] FootTap (12 bytes) | the
+// footprint [foot_floats] float (first holding the window origins, [n_layers][2] int).
 struct OtfLds {
-  int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off, total;
+  int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off;
+  int fw_off, fp_off, total;
 };
 
 __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix,
-                                                 bool with_taps = true) {
+                                                 bool with_taps = true, int foot_floats = 0) {
   OtfLds o;
   const int jobs = otf_jobs_per_round(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
@@ -70,6 +75,10 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   if (o.p_off + 1024 > end) end = o.p_off + 1024;  // matrix-core image: 16 x 16 floats
   if (u0 + part > end) end = u0 + part;
   if (with_taps && u0 + taps > end) end = u0 + taps;
+  o.fw_off = (o.aw_off + 15) & ~15;
+  o.fp_off = (o.fw_off + 2 * ns * n_layers * 12 + 15) & ~15;
+  const int fpb = 4 * (foot_floats > 2 * n_layers ? foot_floats : 2 * n_layers);
+  if (foot_floats > 0 && o.fp_off + fpb > end) end = o.fp_off + fpb;
   o.total = (end + 15) & ~15;
   return o;
 }
@@ -102,12 +111,210 @@ __device__ __forceinline__ Tap tap_of(const DevLayer& L, const DevAffine& A, boo
   return make_tap(v, L.ny, L.inv_ny, L.boundary, L.nx);
 }
 
+// Where the lag-domain field stage gets the phase (a compile-time choice, so that each kernel
+// only holds the registers of its own path).
+constexpr int kFieldGather = 0;  // bilinear stencils straight from the layers, per pixel
+constexpr int kFieldPhase = 1;   // the projection kernel's phase buffer p.phase_in
+constexpr int kFieldFoot = 2;    // the subaperture's layer footprint, staged in LDS
+
+// Footprint origin along one axis: the grid index of the smallest coordinate c the
+// subaperture's stencils touch, wrapped into [0, n) on a periodic grid (same arithmetic as
+// make_tap, so both agree on every index), the unclamped floor of the clamped coordinate on a
+// zero-boundary grid.
+__device__ __forceinline__ int foot_origin(double c, int32_t n, double inv_n, int32_t boundary) {
+  if (boundary == 0) {
+    const double cw = c - (double)n * floor(c * inv_n);
+    int i0 = (int32_t)floor(cw);
+    if (i0 >= n) i0 -= n;
+    if (i0 < 0) i0 += n;
+    return i0;
+  }
+  return (int32_t)floor(fmin(fmax(c, -4.0), (double)n + 4.0));
+}
+
+// One axis of a bilinear stencil against a staged footprint: the weights of make_tap (same
+// arithmetic, bit for bit) and the first tap's index relative to the footprint origin o.
+__device__ __forceinline__ float2 foot_tap(double c, int32_t n, double inv_n, int32_t boundary,
+                                           int o, int* rel) {
+  if (boundary == 0) {
+    const double cw = c - (double)n * floor(c * inv_n);
+    const double f0 = floor(cw);
+    int32_t i0 = (int32_t)f0;
+    const float f = (float)(cw - f0);
+    if (i0 >= n) i0 -= n;
+    if (i0 < 0) i0 += n;
+    int r = i0 - o;
+    if (r < 0) r += n;
+    *rel = r;
+    return make_float2(1.0f - f, f);
+  }
+  const double cc = fmin(fmax(c, -4.0), (double)n + 4.0);
+  const double f0 = floor(cc);
+  const int32_t i0 = (int32_t)f0;
+  const float f = (float)(cc - f0);
+  const bool ok0 = i0 >= 0 && i0 < n;
+  const bool ok1 = i0 + 1 >= 0 && i0 + 1 < n;
+  *rel = i0 - o;
+  return make_float2(ok0 ? 1.0f - f : 0.0f, ok1 ? f : 0.0f);
+}
+
+// Stencil entry of one pupil column (w0, w1, window-relative column) or row (w0 * layer
+// weight, w1 * layer weight, first float of the window row) of one layer.
+struct FootTap {
+  float w0, w1;
+  int32_t k;
+};
+
+// Phase of the lane's pixels from a footprint staged in LDS (Sec. 2.2, inside the spot wave):
+//   1. every stencil entry (lane per layer, axis and pupil index; FP64 coordinates) with the
+//      origin of the layer window along that axis: the window holds the layer pixels the
+//      subaperture's stencils can touch (bounds fixed per sensor and layer);
+//   2. each lane loads up to two window columns (all rows; the column descriptors are read
+//      at the start), then the window goes to LDS over the origins table;
+//   3. each pixel sums its stencils from LDS, layer by layer.
+// Indices, weights and the order of every floating-point operation are those of the
+// projection kernel, so the phase (and everything after it) matches the split schedule bit
+// for bit.
+template <int NS>
+__device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& S,
+                                           const DevSubap& sb, int sid, int b, double stepd,
+                                           char* wsm, const OtfLds& lo, float* ph) {
+  constexpr int NPIX = NS * NS;
+  constexpr int PPL = (NPIX + kWave - 1) / kWave;
+  constexpr int ROWS = NS + 2;
+  constexpr int TPL = 2 * NS;       // stencil entries per layer: columns, then rows
+  constexpr int LPP = kWave / TPL;  // layers per pass
+  const int lane = lane_id();
+  const int nl = p.n_layers;
+  FootTap* tab = reinterpret_cast<FootTap*>(wsm + lo.fw_off);  // [nl][2 NS]
+  int* forg = reinterpret_cast<int*>(wsm + lo.fp_off);         // [nl][2], until step 2
+  float* fp = reinterpret_cast<float*>(wsm + lo.fp_off);
+  const int64_t fbase = (int64_t)sid * nl;
+  FootCol fc[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int pc = lane + k * kWave;
+    fc[k] = pc < S.foot_ncols ? p.foot_cols[S.foot_cols_off + pc]
+                              : FootCol{0, 1, 1, 0, 0, 0, 0, 0};
+  }
+  // 1. stencil entries; lanes j = 0 and j = NS of a layer also record its window origin
+  {
+    const int lp = lane / TPL, j = lane - lp * TPL;
+    const bool row = j >= NS;
+    const int i0 = row ? sb.a * NS : sb.b * NS;
+    const int idx = i0 + (row ? j - NS : j);
+    for (int l0 = 0; l0 < nl; l0 += LPP) {
+      const int l = l0 + lp;
+      if (lp < LPP && l < nl) {
+        const FootAxis X = p.foot_axis[(fbase + l) * 2 + (row ? 1 : 0)];
+        const double sh = stepd * X.db;
+        const double c = fma(X.a, (double)idx, X.b0) + sh;
+        const double cf = fma(X.a, (double)i0, X.b0) + sh;
+        const double cl = fma(X.a, (double)(i0 + NS - 1), X.b0) + sh;
+        const int o = foot_origin(fmin(cf, cl), X.n, X.inv_n, X.boundary);
+        int rel;
+        const float2 w = foot_tap(c, X.n, X.inv_n, X.boundary, o, &rel);
+        FootTap t;
+        t.w0 = w.x * X.weight;  // rows: the projection kernel's ry.w0 * wl
+        t.w1 = w.y * X.weight;
+        t.k = X.koff + rel * X.kmul;
+        tab[l * TPL + j] = t;
+        if (j == 0 || j == NS) forg[2 * l + (row ? 1 : 0)] = o;
+      }
+    }
+  }
+  wave_sync();
+  // 2. window columns (32-bit element offsets: the plan keeps every layer below 2^30 floats).
+  // Rows leave the grid (wrap, or clamp on a zero-boundary grid) only for windows at a grid
+  // edge: when no lane's window does, the rows are plain strides.
+  const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
+  float val[2][ROWS];
+  int cbase[2], oyv[2];
+  bool edge = false;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const FootCol& C = fc[k];
+    const int l = C.lj >> 8, j = C.lj & 255;
+    const int ox = forg[2 * l];
+    oyv[k] = forg[2 * l + 1];
+    int col = ox + j;
+    if (C.boundary == 0) col -= col >= C.nx ? C.nx : 0;
+    else col = min(max(col, 0), C.nx - 1);
+    cbase[k] = C.offset + col;
+    edge = edge || (C.fh > 0 && (oyv[k] < 0 || oyv[k] + C.fh > C.ny));
+  }
+  if (__builtin_amdgcn_ballot_w64(edge) == 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int r0 = cbase[k] + oyv[k] * fc[k].nx;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i)
+        if (i < fc[k].fh) val[k][i] = ld_idx(lay_b, (uint32_t)(r0 + i * fc[k].nx));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const FootCol& C = fc[k];
+      const bool periodic = C.boundary == 0;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        int rr = oyv[k] + i;
+        if (rr >= C.ny) rr = periodic ? rr - C.ny : C.ny - 1;
+        rr = max(rr, 0);
+        if (i < C.fh) val[k][i] = ld_idx(lay_b, (uint32_t)(cbase[k] + rr * C.nx));
+      }
+    }
+  }
+  wave_sync();  // the window overwrites the origins
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i)
+      if (i < fc[k].fh) fp[fc[k].dst + i * fc[k].fw] = val[k][i];
+  wave_sync();
+  // 3. stencils, in the projection kernel's chunks of layers (a last partial chunk is padded
+  // with zero-weight repeats of the last layer, as there)
+  int pr[PPL], pc[PPL];
+  float psi[PPL];
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) {
+    const int q = min(lane + i * kWave, NPIX - 1);
+    pr[i] = q / NS;
+    pc[i] = q - pr[i] * NS;
+    psi[i] = 0.0f;
+  }
+  auto stencil = [&](int l, bool pad) {
+    const int fw = cload(p.foot, fbase + l).x;
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const FootTap cx = tab[l * TPL + pc[i]];
+      const FootTap ry = tab[l * TPL + NS + pr[i]];
+      const int b0 = ry.k + cx.k, b1 = b0 + fw;
+      const float v00 = fp[b0], v01 = fp[b0 + 1];
+      const float v10 = fp[b1], v11 = fp[b1 + 1];
+      const float r0v = fmaf(cx.w0, v00, cx.w1 * v01);
+      const float r1v = fmaf(cx.w0, v10, cx.w1 * v11);
+      const float wy0 = pad ? 0.0f : ry.w0, wy1 = pad ? 0.0f : ry.w1;
+      psi[i] = fmaf(wy0, r0v, fmaf(wy1, r1v, psi[i]));
+    }
+  };
+  int l0 = 0;
+  for (; l0 + kProjLC <= nl; l0 += kProjLC) {
+#pragma unroll
+    for (int jj = 0; jj < kProjLC; ++jj) stencil(l0 + jj, false);
+  }
+  if (l0 < nl) {
+#pragma unroll
+    for (int jj = 0; jj < kProjLC; ++jj) stencil(min(l0 + jj, nl - 1), l0 + jj >= nl);
+  }
+#pragma unroll
+  for (int i = 0; i < PPL; ++i) ph[i] = psi[i] * S.kappa;
+}
+
 // Fills the wave's E region with the subaperture field E[r][c] = A exp(i(psi - pi (r+c)/N)),
 // and the wave's copies of the sensor's lag-phase and twiddle tables.  All per-subaperture
-// values (S, sb, sid, b) are wave-uniform.  FUSED: the phase is gathered from the layers here;
-// otherwise it is read from the projection kernel's buffer p.phase_in (a compile-time choice,
-// so that each kernel only holds the registers of its own path).
-template <int NS, bool FUSED>
+// values (S, sb, sid, b) are wave-uniform.  FIELD says where the phase comes from.
+template <int NS, int FIELD>
 __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S,
                                           const DevSubap& sb, int sid, int b, double stepd,
                                           char* wsm, const OtfLds& lo) {
@@ -124,7 +331,25 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       else wt[k - (2 * NS - 1)] = p.wtab[S.wtab_off + k - (2 * NS - 1)];
     }
   }
-  if constexpr (!FUSED) {  // split mode: the projection kernel already wrote kappa * psi
+  if constexpr (FIELD == kFieldFoot) {
+    float ph[PPL];
+    foot_phase<NS>(p, S, sb, sid, b, stepd, wsm, lo, ph);
+    float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      const int q = lane + i * kWave;
+      if (q < NPIX) {
+        const int r = q / NS, c = q - r * NS;
+        const uint8_t amp = p.mask[S.mask_off + (sb.a * NS + r) * S.n_pup + sb.b * NS + c];
+        float turns = fmaf(ph[i], 0.15915494309189535f, -(float)(r + c) * S.ramp);
+        turns -= rintf(turns);
+        float sn, cs;
+        sincos_rev(turns, &sn, &cs);
+        E[q] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+      }
+    }
+    wave_sync();
+  } else if constexpr (FIELD == kFieldPhase) {  // the projection kernel already wrote kappa psi
     const float* ph = p.phase_in + (int64_t)b * p.phase_per_real + S.phase_off +
                       (int64_t)sb.v * NPIX;
     float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
@@ -515,24 +740,26 @@ __device__ __forceinline__ Cog cog_sums(const FwdParams& p, const DevSensor& S, 
   return c;
 }
 
-// Slopes (0 when the flux is not positive) and the flux of subaperture v.
+// Slopes (0 when the flux is not positive) and the flux of subaperture v, of frame `frame`
+// of a multi-frame launch (outputs [frame][B][...]).
 __device__ __forceinline__ void write_slopes(const FwdParams& p, const DevSensor& S, int b,
-                                             int v, const Cog& c) {
+                                             int v, const Cog& c, int frame = 0) {
   if (lane_id() == 0) {
     const bool ok = c.s0 > 0.0f;
-    float* out = p.slopes + (int64_t)b * p.n_slopes + S.slope_off;
+    const int64_t fb = (int64_t)frame * p.batch + b;
+    float* out = p.slopes + fb * p.n_slopes + S.slope_off;
     out[v] = ok ? c.sx / c.s0 : 0.0f;
     out[S.n_valid + v] = ok ? c.sy / c.s0 : 0.0f;
-    if (p.aux) p.aux[(int64_t)b * p.n_valid_total + S.aux_off + v] = c.s0;
+    if (p.aux) p.aux[fb * p.n_valid_total + S.aux_off + v] = c.s0;
   }
 }
 
 // Binned noise-free (or noisy) image of one subaperture into the wave's B region.
-template <int NS, bool FUSED>
+template <int NS, int FIELD>
 __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
                                          const DevSubap& sb, int sid, int b, int64_t step,
                                          char* wsm, const OtfLds& lo) {
-  otf_field<NS, FUSED>(p, S, sb, sid, b, (double)step, wsm, lo);
+  otf_field<NS, FIELD>(p, S, sb, sid, b, (double)step, wsm, lo);
 #pragma unroll
   for (int rd = 0; rd < Otf<NS>::kRounds; ++rd)
     otf_corr_round<NS>(S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
@@ -540,17 +767,18 @@ __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
   otf_image(p, S, wsm, lo);
 }
 
-template <int NS, bool FUSED>
-__device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm) {
+template <int NS, int FIELD>
+__device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm, int frame = 0) {
   int b, sid, v;
   t = __builtin_amdgcn_readfirstlane(t);  // wave-uniform: per-subaperture data in SGPRs
   task_of(p.otf, t, b, sid, v);
   const DevSensor S = cload(p.sen, sid);
   const DevSubap sb = cload(p.sub, S.valid_off + v);
-  const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix);
-  otf_spot<NS, FUSED>(p, S, sb, sid, b, step, wsm, lo);
+  const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix, false,
+                                   FIELD == kFieldFoot ? S.foot_floats : 0);
+  otf_spot<NS, FIELD>(p, S, sb, sid, b, step, wsm, lo);
   const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));
-  write_slopes(p, S, b, v, c);
+  write_slopes(p, S, b, v, c, frame);
   wave_sync();
 }
 

@@ -138,12 +138,18 @@ class Plan:
                                     _ptr(aux), _stream(stream)), "wfs_spots")
         return slopes, aux
 
+    FIELDS = ("gather", "split", "footprint")
+    FRAMES = ("sequential", "pipelined", "one_launch")
+
     def schedule(self):
-        """dict(split, pipelined, xcd_remap) of the current launch schedule."""
+        """dict(field, frames, xcd_remap) of the current launch schedule: field is where a
+        frame's spot waves get the phase ("gather", "split", "footprint"), frames how
+        ``forward_steps`` runs ("sequential", "pipelined", "one_launch")."""
         v = [ctypes.c_int32() for _ in range(3)]
         L.check(self._lib.wfs_plan_schedule(self._h, *[ctypes.byref(x) for x in v]),
                 "wfs_plan_schedule")
-        return dict(split=v[0].value, pipelined=v[1].value, xcd_remap=v[2].value)
+        return dict(field=self.FIELDS[v[0].value], frames=self.FRAMES[v[1].value],
+                    xcd_remap=v[2].value)
 
     def footprint(self, step=0):
         """(distinct layer pixels read, projected pixels) per realisation at ``step``."""

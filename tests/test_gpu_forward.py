@@ -16,6 +16,12 @@ def _gpu():
     return torch, W
 
 
+def _flags(W, mode):
+    """Plan flags of a field mode: projection kernel first, per-pixel gather in the spot
+    waves, or the default (staged footprint where every lag-domain sensor allows it)."""
+    return {"split": W.WFS_FLAG_SPLIT, "fused": W.WFS_FLAG_FUSED, "footprint": 0}[mode]
+
+
 def _run(cfg, x, step, seed=42, flags=0):
     torch, W = _gpu()
     plan = W.Plan(cfg, flags=flags, batch=x.shape[0])
@@ -37,12 +43,16 @@ def _check(cfg, x, s_gpu, a_gpu, step, seed=42):
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("step", [0, 7])
-@pytest.mark.parametrize("mode", ["split", "fused"])
+@pytest.mark.parametrize("mode", ["split", "fused", "footprint"])
 def test_forward_matches_oracle(name, step, mode):
     torch, W = _gpu()
     cfg = CASES[name]()
     x = layers_for(cfg)
-    s, a, plan, _ = _run(cfg, x, step, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
+    s, a, plan, _ = _run(cfg, x, step, flags=_flags(W, mode))
+    want = {"split": "split", "fused": "gather", "footprint": "footprint"}[mode]
+    if mode == "footprint" and 1 in plan.paths:
+        want = "split"  # FFT-path sensors read the projected phase
+    assert plan.schedule()["field"] == want
     assert s.shape == (cfg["batch"], oracle.n_slopes(cfg))
     _check(cfg, x, s, a, step)
 
@@ -155,16 +165,37 @@ def test_spots_of_projection_is_the_forward(name):
     assert torch.equal(s1, s2) and torch.equal(a1, a2)
 
 
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_footprint_field_equals_split_bitwise(name):
+    """The staged-footprint field repeats the projection kernel's indices, weights and
+    operation order, so its slopes equal the split schedule's bit for bit (periodic wrap,
+    zero-boundary DM grid and a step far from the origin included)."""
+    torch, W = _gpu()
+    cfg = CASES[name]()
+    x = layers_for(cfg)
+    xt = torch.from_numpy(x).cuda()
+    pf = W.Plan(cfg, batch=x.shape[0])
+    if pf.schedule()["field"] != "footprint":
+        assert 1 in pf.paths
+        pytest.skip("FFT-path sensors read the projected phase")
+    ps = W.Plan(cfg, flags=W.WFS_FLAG_SPLIT, batch=x.shape[0])
+    assert ps.schedule()["field"] == "split"
+    for step in (0, 7, 100003):
+        s1, a1 = pf.forward(xt, step=step, seed=9)
+        s2, a2 = ps.forward(xt, step=step, seed=9)
+        assert torch.equal(s1, s2) and torch.equal(a1, a2), step
+
+
 @pytest.mark.parametrize("name", ["lgs_n10_N32_b4_noise", "mixed_lgs_ngs_batch2",
                                   "dm_two_ngs_batch2", "fft_ngs_n64_N128_b4"])
-@pytest.mark.parametrize("mode", ["split", "fused"])
+@pytest.mark.parametrize("mode", ["split", "fused", "footprint"])
 def test_forward_steps_equals_single_frames(name, mode):
     """Pipelined frames (projection of step k+1 inside the spot launch of step k) give the
     single-frame results bit for bit, also from the device step counter."""
     torch, W = _gpu()
     cfg = CASES[name]()
     x = layers_for(cfg)
-    plan = W.Plan(cfg, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
+    plan = W.Plan(cfg, flags=_flags(W, mode))
     xt = torch.from_numpy(x).cuda()
     n, k0 = 5, 3
     s, a = plan.forward_steps(xt, k0, n, seed=7)
@@ -180,15 +211,18 @@ def test_forward_steps_equals_single_frames(name, mode):
 
 
 def test_forward_steps_config1_equals_single_frames():
-    """Config 1, 6 pipelined frames: every frame's slopes equal the single-frame call."""
+    """Config 1, 6 frames in one staged-footprint launch: every frame's slopes equal the
+    split schedule's single-frame call."""
     torch, W = _gpu()
     cfg = synth.config1()
     x = synth.make_batch(cfg, [0])
     plan = W.Plan(cfg)
+    assert plan.schedule()["frames"] == "one_launch"
+    split = W.Plan(cfg, flags=W.WFS_FLAG_SPLIT)
     xt = torch.from_numpy(x).cuda()
     s, _ = plan.forward_steps(xt, 40, 6)
     for k in (0, 5):
-        s1, _ = plan.forward(xt, step=40 + k)
+        s1, _ = split.forward(xt, step=40 + k)
         assert torch.equal(s[k], s1)
 
 
@@ -202,7 +236,8 @@ def test_forward_steps_after_tune_config2_equals_single_frames():
     xt = torch.from_numpy(x).cuda()
     plan.tune(xt, iters=2)
     sch = plan.schedule()
-    assert sch["pipelined"] in (0, 1) and (sch["split"] or not sch["pipelined"])
+    assert sch["field"] != "footprint" and sch["frames"] != "one_launch"  # FFT-path NGS
+    assert sch["field"] == "split" or sch["frames"] == "sequential"
     s, a = plan.forward_steps(xt, 11, 3)
     for k in range(3):
         s1, a1 = plan.forward(xt, step=11 + k)
@@ -237,13 +272,14 @@ def test_footprint_matches_oracle_coordinates():
     assert abs(got - want) <= 0.002 * want, (got, want)
 
 
-@pytest.mark.parametrize("step,mode", [(0, "split"), (61, "split"), (61, "fused")])
+@pytest.mark.parametrize("step,mode", [(0, "split"), (61, "split"), (61, "fused"),
+                                       (61, "footprint")])
 def test_config1_full_frame_matches_oracle(step, mode):
     """E-ELT 80x80 LGS (config 1), every one of the 4,632 subapertures, noise on."""
     torch, W = _gpu()
     cfg = synth.config1()
     x = synth.make_batch(cfg, [0])
-    s, a, plan, _ = _run(cfg, x, step, flags=W.WFS_FLAG_FUSED if mode == "fused" else 0)
+    s, a, plan, _ = _run(cfg, x, step, flags=_flags(W, mode))
     assert plan.n_slopes == 9264
     worst = _check(cfg, x, s, a, step)
     print(f"config1 step {step}: worst slope error {worst:.3g} of tolerance")

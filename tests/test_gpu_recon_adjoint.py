@@ -85,13 +85,13 @@ def _adjoint_case(name, seed=1):
                                   "lgs_n5_N10_b2_2sens_batch3", "dm_two_ngs_batch2", "cfg0",
                                   "ngs_n6_N12_b4_oddpix"])
 @pytest.mark.parametrize("saved", [False, True])
-@pytest.mark.parametrize("mode", ["split", "fused", "split_atomic"])
+@pytest.mark.parametrize("mode", ["split", "fused", "split_atomic", "footprint"])
 def test_adjoint_matches_oracle(name, saved, mode):
     torch, W = _gpu()
     cfg, x, g = _adjoint_case(name)
     step = 4
-    flags = {"split": 0, "fused": W.WFS_FLAG_FUSED,
-             "split_atomic": W.WFS_FLAG_ADJOINT_ATOMIC}[mode]
+    flags = {"split": W.WFS_FLAG_SPLIT, "fused": W.WFS_FLAG_FUSED,
+             "split_atomic": W.WFS_FLAG_SPLIT | W.WFS_FLAG_ADJOINT_ATOMIC, "footprint": 0}[mode]
     plan = W.Plan(cfg, flags=flags)
     xt = torch.from_numpy(x).cuda()
     gt = torch.from_numpy(g).cuda()
