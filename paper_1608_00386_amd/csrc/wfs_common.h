@@ -94,6 +94,15 @@ __device__ __forceinline__ void add_noise_pair(float& b0, float& b1, uint4 w, fl
   b1 += sqrtf(fmaxf(b1, 0.0f)) * (rb * c1) + ro * (rb * s1);
 }
 
+// The same noise for one pixel from its half of a Philox block (wr: radius word, wa: angle
+// word), with the hardware square root (about 1 ulp; the noise needs no more).
+__device__ __forceinline__ void add_noise_one(float& b, uint32_t wr, uint32_t wa, float ro) {
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u24(wr)));
+  float s, c;
+  sincos_rev(u24(wa), &s, &c);
+  b += __builtin_amdgcn_sqrtf(fmaxf(b, 0.0f)) * (r * c) + ro * (r * s);
+}
+
 // One axis of a bilinear stencil: element indices (row offsets for the y axis) and weights.
 // Periodic layers wrap modulo n; zero-boundary grids give weight 0 to taps off the grid.
 struct Tap {

@@ -33,11 +33,18 @@ struct Otf {
   static constexpr int kChunk = (kLags + kParts - 1) / kParts;  // lag columns per pass
   static constexpr int kRounds = (kJobs + kWave - 1) / kWave;
   static constexpr int kJobsPerRound = (kJobs + kRounds - 1) / kRounds;
+  // one round (n_sub <= 10): partial-row slots grouped by pairs of lag rows (dy, NS - 1 - dy),
+  // NS + 1 slots a pair (the middle row of an odd NS pairs with itself and leaves slots free)
+  static constexpr int kPairs = (NS + 1) / 2;
+  static constexpr int kSlots = kRounds == 1 ? kPairs * (NS + 1) : kJobsPerRound;
 };
 
-__host__ __device__ constexpr int otf_jobs_per_round(int ns) {
-  return (ns * (ns + 1) / 2 + ((ns * (ns + 1) / 2 + kWave - 1) / kWave) - 1) /
-         ((ns * (ns + 1) / 2 + kWave - 1) / kWave);
+// Partial-row slots of one round (the LDS layout's `part` region).
+__host__ __device__ constexpr int otf_part_rows(int ns) {
+  return (ns * (ns + 1) / 2 + kWave - 1) / kWave == 1
+             ? ((ns + 1) / 2) * (ns + 1)
+             : (ns * (ns + 1) / 2 + ((ns * (ns + 1) / 2 + kWave - 1) / kWave) - 1) /
+                   ((ns * (ns + 1) / 2 + kWave - 1) / kWave);
 }
 
 // Per-wave LDS layout (bytes), shared with the host sizing code:
@@ -58,7 +65,7 @@ struct OtfLds {
 __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix,
                                                  bool with_taps = true, int foot_floats = 0) {
   OtfLds o;
-  const int jobs = otf_jobs_per_round(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
+  const int jobs = otf_part_rows(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
   o.stab_off = ns * ns * 8;
   o.wtab_off = o.stab_off + lags * 8;
@@ -97,6 +104,20 @@ __device__ __forceinline__ void job_of(int j, int& dy, int& r) {
 template <int NS>
 __device__ __forceinline__ int job_base(int dy) {
   return dy * NS - (dy * (dy - 1)) / 2;
+}
+
+// Row-pair job of partial-row slot j in the one-round layout (false: a free slot).
+template <int NS>
+__device__ __forceinline__ bool slot_job(int j, int& dy, int& r) {
+  const int q = j / (NS + 1), t = j - q * (NS + 1), nA = NS - q;
+  if (t < nA) {
+    dy = q;
+    r = t;
+    return true;
+  }
+  dy = NS - 1 - q;
+  r = t - nA;
+  return dy != q;
 }
 
 // Tap of a given layer for the lanes of one half-wave: the layer parameters are wave-uniform
@@ -158,8 +179,8 @@ __device__ __forceinline__ float2 foot_tap(double c, int32_t n, double inv_n, in
   return make_float2(ok0 ? 1.0f - f : 0.0f, ok1 ? f : 0.0f);
 }
 
-// Stencil entry of one pupil column (w0, w1, window-relative column) or row (w0 * layer
-// weight, w1 * layer weight, first float of the window row) of one layer.
+// Stencil entry of one pupil column (w0, w1, byte offset of the window-relative column) or
+// row (w0 * layer weight, w1 * layer weight, byte offset of the window row) of one layer.
 struct FootTap {
   float w0, w1;
   int32_t k;
@@ -217,7 +238,7 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
         FootTap t;
         t.w0 = w.x * X.weight;  // rows: the projection kernel's ry.w0 * wl
         t.w1 = w.y * X.weight;
-        t.k = X.koff + rel * X.kmul;
+        t.k = (X.koff + rel * X.kmul) * 4;  // byte offset in the window
         tab[l * TPL + j] = t;
         if (j == 0 || j == NS) forg[2 * l + (row ? 1 : 0)] = o;
       }
@@ -284,14 +305,16 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
     psi[i] = 0.0f;
   }
   auto stencil = [&](int l, bool pad) {
-    const int fw = cload(p.foot, fbase + l).x;
+    const int fw4 = cload(p.foot, fbase + l).x * 4;
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       const FootTap cx = tab[l * TPL + pc[i]];
       const FootTap ry = tab[l * TPL + NS + pr[i]];
-      const int b0 = ry.k + cx.k, b1 = b0 + fw;
-      const float v00 = fp[b0], v01 = fp[b0 + 1];
-      const float v10 = fp[b1], v11 = fp[b1 + 1];
+      const char* w0p = reinterpret_cast<const char*>(fp) + (ry.k + cx.k);
+      const float v00 = reinterpret_cast<const float*>(w0p)[0];
+      const float v01 = reinterpret_cast<const float*>(w0p)[1];
+      const float v10 = reinterpret_cast<const float*>(w0p + fw4)[0];
+      const float v11 = reinterpret_cast<const float*>(w0p + fw4)[1];
       const float r0v = fmaf(cx.w0, v00, cx.w1 * v01);
       const float r1v = fmaf(cx.w0, v10, cx.w1 * v11);
       const float wy0 = pad ? 0.0f : ry.w0, wy1 = pad ? 0.0f : ry.w1;
@@ -474,18 +497,19 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
   };
   if constexpr (Otf<NS>::kRounds == 1) {
     // every job in one round: lane per (pair of lag rows dy and NS-1-dy, column).  The two
-    // rows hold NS - dy and dy + 1 jobs, so each lane sums exactly NS + 1 partial rows.
+    // rows hold NS - dy and dy + 1 jobs, in NS + 1 consecutive slots, so each lane sums
+    // exactly NS + 1 partial rows.
     constexpr int NQ = (NS + 1) / 2;
     static_assert(NQ * W <= kWave, "one pass");
     const int q = lane / W, k = lane - q * W;
     if (q < NQ) {
       const int dyA = q, dyB = NS - 1 - q, nA = NS - q;
-      const int baseA = job_base<NS>(dyA), baseB = job_base<NS>(dyB) - nA;
+      const float2* rows = part + q * (NS + 1) * Otf<NS>::kChunk + k;  // the pair's slots
       float2 a = make_float2(0.0f, 0.0f), bsum = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int t = 0; t <= NS; ++t) {
         const bool inA = t < nA;
-        const float2 v = part[((inA ? baseA : baseB) + t) * Otf<NS>::kChunk + k];
+        const float2 v = rows[t * Otf<NS>::kChunk];
         if (inA) {
           a.x += v.x;
           a.y += v.y;
@@ -541,10 +565,16 @@ __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap
   const int lane = lane_id();
   const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
   float2* part = reinterpret_cast<float2*>(wsm + lo.part_off);
-  const int j = j0 + lane;
-  if (lane < Otf<NS>::kJobsPerRound && j < Otf<NS>::kJobs) {
-    int dy, r;
-    job_of<NS>(j, dy, r);
+  int dy = 0, r = 0;
+  bool ok;
+  if constexpr (Otf<NS>::kRounds == 1) {
+    ok = lane < Otf<NS>::kSlots && slot_job<NS>(lane, dy, r);
+  } else {
+    const int j = j0 + lane;
+    ok = lane < Otf<NS>::kJobsPerRound && j < Otf<NS>::kJobs;
+    if (ok) job_of<NS>(j, dy, r);
+  }
+  if (ok) {
     // the second row stays in registers; the first streams from LDS one pixel at a time
     float2 e2[NS];
 #pragma unroll
@@ -703,8 +733,9 @@ __device__ __forceinline__ void otf_image(const FwdParams& p, const DevSensor& S
   wave_sync();
 }
 
-// Noise and centre-of-gravity sums over the binned image (sum B', sum x B', sum y B'),
-// pixels in pairs (one Philox block per pair); every lane returns the wave totals.
+// Noise and centre-of-gravity sums over the binned image (sum B', sum x B', sum y B'), one
+// pixel per lane: pixels 2j and 2j + 1 share Philox block j (words x, y and z, w); every lane
+// returns the wave totals.
 struct Cog {
   float s0, sx, sy;
 };
@@ -712,26 +743,23 @@ struct Cog {
 __device__ __forceinline__ Cog cog_sums(const FwdParams& p, const DevSensor& S, int sid, int b,
                                         int v, int64_t step, const float* B) {
   const int lane = lane_id();
-  const int np = S.n_pix, np2 = np * np, npairs = (np2 + 1) >> 1;
+  const int np = S.n_pix, np2 = np * np;
   const float half = 0.5f * (float)(np - 1);
   float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
   const bool noisy = S.noisy && p.noise_on;
-  for (int pr = lane; pr < npairs; pr += kWave) {
-    const int q0 = 2 * pr, q1 = 2 * pr + 1;
-    float b0 = B[q0];
-    float b1 = q1 < np2 ? B[q1] : 0.0f;
+  for (int q = lane; q < np2; q += kWave) {
+    float bq = B[q];
     if (noisy) {
-      const uint4 ctr = make_uint4((uint32_t)pr, (uint32_t)v,
+      const uint4 ctr = make_uint4((uint32_t)(q >> 1), (uint32_t)v,
                                    ((uint32_t)b << 8) | (uint32_t)sid, (uint32_t)step);
       const uint4 w = philox4x32_10(ctr, p.seed_lo, p.seed_hi);
-      add_noise_pair(b0, b1, w, S.read_noise);
-      if (q1 >= np2) b1 = 0.0f;
+      const bool odd = (q & 1) != 0;
+      add_noise_one(bq, odd ? w.z : w.x, odd ? w.w : w.y, S.read_noise);
     }
-    const int y0 = fdiv(q0, np, S.inv_npix), x0 = q0 - y0 * np;
-    const int y1 = fdiv(q1, np, S.inv_npix), x1 = q1 - y1 * np;
-    s0 += b0 + b1;
-    sx = fmaf((float)x0 - half, b0, fmaf((float)x1 - half, b1, sx));
-    sy = fmaf((float)y0 - half, b0, fmaf((float)y1 - half, b1, sy));
+    const int y = fdiv(q, np, S.inv_npix), x = q - y * np;
+    s0 += bq;
+    sx = fmaf((float)x - half, bq, sx);
+    sy = fmaf((float)y - half, bq, sy);
   }
   Cog c;
   c.s0 = wave_sum(s0);
