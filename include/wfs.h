@@ -50,13 +50,17 @@ enum {
 #define WFS_FLAG_FORCE_FFT (1u << 1)    /* every sensor on the FFT path (needs no elongation)     */
 #define WFS_FLAG_NO_XCD_REMAP (1u << 2) /* keep the hardware block order (no per-XCD grouping)    */
 #define WFS_FLAG_FUSED (1u << 3)        /* spot waves gather the layers per pixel (no projection
-                                           pass); default: each wave stages its subaperture's
-                                           layer footprint in LDS where every lag-domain sensor
-                                           allows it, else a projection kernel first      */
+                                           pass; frames one after the other); default: a
+                                           projection kernel first, and wfs_forward_steps as
+                                           one staged-footprint launch where every lag-domain
+                                           sensor allows it                               */
 #define WFS_FLAG_ADJOINT_ATOMIC (1u << 4) /* wfs_adjoint scatters with FP32 atomics instead of
                                            the deterministic gather                        */
 #define WFS_FLAG_SPLIT (1u << 5)        /* projection kernel first, never the staged footprint
                                            (same bits as the footprint field)             */
+#define WFS_FLAG_FOOTPRINT (1u << 6)    /* staged footprint for single frames too (one launch
+                                           per wfs_forward); ignored where a sensor cannot
+                                           stage its footprint                            */
 
 /* `step` value meaning "read the step from the plan's device-resident counter". */
 #define WFS_STEP_DEVICE (-1)

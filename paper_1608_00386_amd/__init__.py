@@ -5,6 +5,7 @@ from ._lib import (  # noqa: F401
     WFS_FLAG_ADJOINT_ATOMIC,
     WFS_FLAG_FORCE_FFT,
     WFS_FLAG_FUSED,
+    WFS_FLAG_FOOTPRINT,
     WFS_FLAG_FORCE_OTF,
     WFS_FLAG_NO_XCD_REMAP,
     WFS_FLAG_SPLIT,

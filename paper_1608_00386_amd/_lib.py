@@ -20,6 +20,7 @@ WFS_FLAG_NO_XCD_REMAP = 1 << 2
 WFS_FLAG_FUSED = 1 << 3
 WFS_FLAG_ADJOINT_ATOMIC = 1 << 4
 WFS_FLAG_SPLIT = 1 << 5
+WFS_FLAG_FOOTPRINT = 1 << 6
 WFS_STEP_DEVICE = -1
 
 

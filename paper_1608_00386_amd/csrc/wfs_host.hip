@@ -645,9 +645,11 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   P->base.proj_lds = P->proj_lds;
   P->split = (flags & WFS_FLAG_FUSED) ? 0 : 1;
   if (P->proj_lds > 65536) P->split = 0;  // taps of one subaperture exceed the LDS budget
-  if (flags & WFS_FLAG_SPLIT) P->foot_ok = 0;
-  P->foot = (P->foot_ok && !(flags & WFS_FLAG_FUSED)) ? 1 : 0;
-  P->frames = P->foot ? 2 : (P->split && P->d_phase ? 1 : 0);
+  if (flags & (WFS_FLAG_SPLIT | WFS_FLAG_FUSED)) P->foot_ok = 0;
+  // single frames: the projection kernel first (one footprint launch per frame exposes the
+  // window loads of every wave at once); frames in a row: one footprint launch
+  P->foot = (P->foot_ok && (flags & WFS_FLAG_FOOTPRINT)) ? 1 : 0;
+  P->frames = P->foot_ok ? 2 : (P->split && P->d_phase ? 1 : 0);
   if (P->proj_lds_fft > 65536) {
     (void)hipFree(P->d_blob);
     if (P->d_phase) (void)hipFree(P->d_phase);
@@ -1025,6 +1027,7 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
     if (field == 2 && !P->foot_ok) continue;
     if ((P->flags & WFS_FLAG_FUSED) && field != 0) continue;
     if ((P->flags & WFS_FLAG_SPLIT) && field != 1) continue;
+    if ((P->flags & WFS_FLAG_FOOTPRINT) && P->foot_ok && field != 2) continue;
     P->split = field == 1;
     P->foot = field == 2;
     FwdParams c = keep;

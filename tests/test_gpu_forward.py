@@ -19,7 +19,8 @@ def _gpu():
 def _flags(W, mode):
     """Plan flags of a field mode: projection kernel first, per-pixel gather in the spot
     waves, or the default (staged footprint where every lag-domain sensor allows it)."""
-    return {"split": W.WFS_FLAG_SPLIT, "fused": W.WFS_FLAG_FUSED, "footprint": 0}[mode]
+    return {"split": W.WFS_FLAG_SPLIT, "fused": W.WFS_FLAG_FUSED,
+            "footprint": W.WFS_FLAG_FOOTPRINT, "default": 0}[mode]
 
 
 def _run(cfg, x, step, seed=42, flags=0):
@@ -174,7 +175,7 @@ def test_footprint_field_equals_split_bitwise(name):
     cfg = CASES[name]()
     x = layers_for(cfg)
     xt = torch.from_numpy(x).cuda()
-    pf = W.Plan(cfg, batch=x.shape[0])
+    pf = W.Plan(cfg, flags=W.WFS_FLAG_FOOTPRINT, batch=x.shape[0])
     if pf.schedule()["field"] != "footprint":
         assert 1 in pf.paths
         pytest.skip("FFT-path sensors read the projected phase")
@@ -188,10 +189,11 @@ def test_footprint_field_equals_split_bitwise(name):
 
 @pytest.mark.parametrize("name", ["lgs_n10_N32_b4_noise", "mixed_lgs_ngs_batch2",
                                   "dm_two_ngs_batch2", "fft_ngs_n64_N128_b4"])
-@pytest.mark.parametrize("mode", ["split", "fused", "footprint"])
+@pytest.mark.parametrize("mode", ["split", "fused", "footprint", "default"])
 def test_forward_steps_equals_single_frames(name, mode):
-    """Pipelined frames (projection of step k+1 inside the spot launch of step k) give the
-    single-frame results bit for bit, also from the device step counter."""
+    """Frames in a row (pipelined split launches, or one staged-footprint launch) give the
+    single-frame results bit for bit, also from the device step counter; by default the single
+    frames run split and the frames in a row as one footprint launch."""
     torch, W = _gpu()
     cfg = CASES[name]()
     x = layers_for(cfg)

@@ -91,7 +91,8 @@ def test_adjoint_matches_oracle(name, saved, mode):
     cfg, x, g = _adjoint_case(name)
     step = 4
     flags = {"split": W.WFS_FLAG_SPLIT, "fused": W.WFS_FLAG_FUSED,
-             "split_atomic": W.WFS_FLAG_SPLIT | W.WFS_FLAG_ADJOINT_ATOMIC, "footprint": 0}[mode]
+             "split_atomic": W.WFS_FLAG_SPLIT | W.WFS_FLAG_ADJOINT_ATOMIC,
+             "footprint": W.WFS_FLAG_FOOTPRINT}[mode]
     plan = W.Plan(cfg, flags=flags)
     xt = torch.from_numpy(x).cuda()
     gt = torch.from_numpy(g).cuda()
