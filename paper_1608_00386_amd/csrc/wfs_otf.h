@@ -187,9 +187,9 @@ struct FootTap {
 };
 
 // Phase of the lane's pixels from a footprint staged in LDS (Sec. 2.2, inside the spot wave):
-//   1. every stencil entry (lane per layer, axis and pupil index; FP64 coordinates) with the
-//      origin of the layer window along that axis: the window holds the layer pixels the
-//      subaperture's stencils can touch (bounds fixed per sensor and layer);
+//   1. the origin of each layer window along each axis (the window holds the layer pixels the
+//      subaperture's stencils can touch; bounds fixed per sensor and layer), then every
+//      stencil entry (lane per layer, axis and pupil index; FP64 coordinates);
 //   2. each lane loads up to two window columns (all rows; the column descriptors are read
 //      at the start), then the window goes to LDS over the origins table;
 //   3. each pixel sums its stencils from LDS, layer by layer.
@@ -218,33 +218,36 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
     fc[k] = pc < S.foot_ncols ? p.foot_cols[S.foot_cols_off + pc]
                               : FootCol{0, 1, 1, 0, 0, 0, 0, 0};
   }
-  // 1. stencil entries; lanes j = 0 and j = NS of a layer also record its window origin
+  // 1. window origins, lane per (layer, axis); then the stencil entries, lane per (layer,
+  //    axis, pupil index)
+  for (int e = lane; e < 2 * nl; e += kWave) {
+    const FootAxis X = p.foot_axis[fbase * 2 + e];
+    const int i0 = (e & 1) ? sb.a * NS : sb.b * NS;
+    const double sh = stepd * X.db;
+    const double cf = fma(X.a, (double)i0, X.b0) + sh;
+    const double cl = fma(X.a, (double)(i0 + NS - 1), X.b0) + sh;
+    forg[e] = foot_origin(fmin(cf, cl), X.n, X.inv_n, X.boundary);
+  }
+  wave_sync();
   {
     const int lp = lane / TPL, j = lane - lp * TPL;
-    const bool row = j >= NS;
-    const int i0 = row ? sb.a * NS : sb.b * NS;
-    const int idx = i0 + (row ? j - NS : j);
+    const int axis = j >= NS ? 1 : 0;
+    const int idx = axis ? sb.a * NS + (j - NS) : sb.b * NS + j;
     for (int l0 = 0; l0 < nl; l0 += LPP) {
       const int l = l0 + lp;
       if (lp < LPP && l < nl) {
-        const FootAxis X = p.foot_axis[(fbase + l) * 2 + (row ? 1 : 0)];
-        const double sh = stepd * X.db;
-        const double c = fma(X.a, (double)idx, X.b0) + sh;
-        const double cf = fma(X.a, (double)i0, X.b0) + sh;
-        const double cl = fma(X.a, (double)(i0 + NS - 1), X.b0) + sh;
-        const int o = foot_origin(fmin(cf, cl), X.n, X.inv_n, X.boundary);
+        const FootAxis X = p.foot_axis[(fbase + l) * 2 + axis];
+        const double c = fma(X.a, (double)idx, X.b0) + stepd * X.db;
         int rel;
-        const float2 w = foot_tap(c, X.n, X.inv_n, X.boundary, o, &rel);
+        const float2 w = foot_tap(c, X.n, X.inv_n, X.boundary, forg[2 * l + axis], &rel);
         FootTap t;
         t.w0 = w.x * X.weight;  // rows: the projection kernel's ry.w0 * wl
         t.w1 = w.y * X.weight;
         t.k = (X.koff + rel * X.kmul) * 4;  // byte offset in the window
         tab[l * TPL + j] = t;
-        if (j == 0 || j == NS) forg[2 * l + (row ? 1 : 0)] = o;
       }
     }
   }
-  wave_sync();
   // 2. window columns (32-bit element offsets: the plan keeps every layer below 2^30 floats).
   // Rows leave the grid (wrap, or clamp on a zero-boundary grid) only for windows at a grid
   // edge: when no lane's window does, the rows are plain strides.
