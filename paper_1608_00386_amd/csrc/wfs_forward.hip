@@ -49,17 +49,31 @@ static hipError_t launch_forward_ns(const FwdParams& p, int ns, hipStream_t st) 
 
 // FFT-path and lag-domain subapertures go in two launches on the same stream: the FFT path's
 // registers and LDS would otherwise set the occupancy of every lag-domain wavefront.
-hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st) {
+// The FFT-path blocks (large fields, one workgroup each, 48 KB of LDS) and the lag-domain
+// blocks go to separate launches, so that the lag-domain waves keep their own occupancy; with
+// a side stream the FFT-path launch runs concurrently (fork after everything already queued
+// on st, join before anything queued after this call).
+hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const SideStream* side) {
   if (p.fft_blocks == 0 || (p.otf_blocks == 0 && p.proj_blocks == 0))
     return launch_forward_ns(p, ns, st);
   FwdParams a = p;
   a.otf_blocks = 0;
   a.proj_blocks = 0;
-  hipError_t e = launch_forward_ns(a, ns, st);
-  if (e != hipSuccess) return e;
   FwdParams c = p;
   c.fft_blocks = 0;
   c.lds_per_wave = p.lds_per_wave_otf;
+  hipError_t e;
+  if (side && side->stream) {
+    e = hipEventRecord(side->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+    if (e == hipSuccess) e = launch_forward_ns(a, ns, side->stream);
+    if (e == hipSuccess) e = launch_forward_ns(c, ns, st);
+    if (e == hipSuccess) e = hipEventRecord(side->join, side->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->join, 0);
+    return e;
+  }
+  e = launch_forward_ns(a, ns, st);
+  if (e != hipSuccess) return e;
   return launch_forward_ns(c, ns, st);
 }
 

@@ -16,7 +16,7 @@
 #include "wfs_internal.h"
 
 namespace wfs {
-hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st);
+hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const SideStream* side);
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
 int project_lds_bytes(int n_layers);
 int project_strip();
@@ -109,6 +109,7 @@ struct wfs_plan_s {
   // split or the footprint one: all three give the same bits)
   int frames = 0;
   int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
+  SideStream side{};         // FFT-path blocks run here concurrently (plans with both paths)
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
@@ -656,6 +657,20 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     delete P;
     return fail(WFS_EUNSUPPORTED, "wfs_plan: projection taps of an FFT-path sensor exceed 64 KiB");
   }
+  if (P->fft_tasks > 0 && P->otf_tasks > 0) {  // both paths: FFT-path blocks on a side stream
+    e = hipStreamCreateWithFlags(&P->side.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->side.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->side.join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (P->side.join) (void)hipEventDestroy(P->side.join);
+      if (P->side.fork) (void)hipEventDestroy(P->side.fork);
+      if (P->side.stream) (void)hipStreamDestroy(P->side.stream);
+      (void)hipFree(P->d_blob);
+      if (P->d_phase) (void)hipFree(P->d_phase);
+      delete P;
+      return hip_fail(e, "wfs_plan: side stream");
+    }
+  }
   *out = P;
   return WFS_OK;
 }
@@ -684,6 +699,9 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (P->d_blob) (void)hipFree(P->d_blob);
   if (P->d_phase) (void)hipFree(P->d_phase);
   if (P->d_gimg) (void)hipFree(P->d_gimg);
+  if (P->side.join) (void)hipEventDestroy(P->side.join);
+  if (P->side.fork) (void)hipEventDestroy(P->side.fork);
+  if (P->side.stream) (void)hipStreamDestroy(P->side.stream);
   delete P;
   if (e != hipSuccess) return hip_fail(e, "wfs_plan_destroy");
   return WFS_OK;
@@ -726,7 +744,7 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
     p.n_frames = 1;
     p.lds_per_wave = P->lds_foot;
     p.lds_per_wave_otf = P->lds_foot;
-    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
   }
   const bool split = P->split && P->d_phase;
   if (split || P->fft_tasks > 0) {  // FFT-path sensors always read the projected phase
@@ -738,7 +756,7 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
   p.otf_from_phase = split ? 1 : 0;
   p.lds_per_wave = split ? P->lds_split : P->lds_fused;
   p.lds_per_wave_otf = split ? P->lds_split_otf : P->lds_fused_otf;
-  return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+  return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
 }
 
 int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, float* slopes,
@@ -778,7 +796,7 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
     p.n_frames = n;
     p.lds_per_wave = P->lds_foot;
     p.lds_per_wave_otf = P->lds_foot;
-    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
   }
   if (!pipelined) {
     for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_fwd_modes(P, frame(k), st);
@@ -799,7 +817,7 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
       p.proj_blocks = P->proj_all.per_real * P->batch;
       p.phase_out = buf[(k + 1) & 1];
     }
-    e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st);
+    e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
   }
   return e;
 }
@@ -832,7 +850,7 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
   FwdParams p = call_params(P, nullptr, step, seed, slopes, aux);
   p.phase_in = phase;
   p.otf_from_phase = 1;
-  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream, &P->side);
   if (e != hipSuccess) return hip_fail(e, "wfs_spots: launch");
   return WFS_OK;
 }

@@ -145,6 +145,13 @@ struct FwdParams {
   int32_t n_frames;
 };
 
+// A plan-owned second stream with fork/join events: a launch that holds FFT-path blocks runs
+// them there, concurrently with the lag-domain blocks on the caller's stream.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct AdjParams {
   FwdParams f;              // forward tables (noise off)
   const float* grad_slopes; // [B][n_slopes]

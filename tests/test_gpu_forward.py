@@ -294,3 +294,42 @@ def test_config0_paper_sampling_counts():
     plan1 = W.Plan(synth.config1())
     assert plan1.n_valid == [4632]
     np.testing.assert_allclose(plan1.pix_scale[0], oracle.pixel_scale(synth.config1()["sensors"][0]))
+
+
+def test_side_stream_graph_replays_match_eager():
+    """A plan with FFT-path and lag-domain sensors runs the FFT-path blocks on a side stream
+    (fork and join events); a captured graph of single frames and of frames in a row replays
+    to the eager results every time, with eager work in between."""
+    torch, W = _gpu()
+    cfg = CASES["mixed_lgs_ngs_batch2"]()
+    x = layers_for(cfg)
+    plan = W.Plan(cfg, batch=x.shape[0])
+    assert 1 in plan.paths and 0 in plan.paths
+    xt = torch.from_numpy(x).cuda()
+    n = 3
+    ref = torch.stack([plan.forward(xt, step=4 + k, seed=5)[0].clone() for k in range(n)])
+    ref_steps, _ = plan.forward_steps(xt, 4, n, seed=5)
+    assert torch.equal(ref_steps, ref)
+    out = torch.empty_like(ref)
+    aux = torch.empty(n, x.shape[0], plan.n_valid_total, device="cuda")
+    out2 = torch.empty_like(ref)
+    aux2 = torch.empty_like(aux)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.forward(xt, step=0, seed=5, slopes=out[0], aux=aux[0])
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for k in range(n):
+            plan.forward(xt, step=4 + k, seed=5, slopes=out[k], aux=aux[k])
+        plan.forward_steps(xt, 4, n, seed=5, slopes=out2, aux=aux2)
+    for rep in range(3):
+        out.zero_()
+        out2.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(out2, ref), rep
+        plan.forward(xt, step=11, seed=1)  # eager work between the replays
+        torch.cuda.synchronize()
