@@ -37,4 +37,5 @@ from .wfs_oracle import (  # noqa: F401
     n_slopes,
     pixel_scale,
 )
+from .calib_oracle import interaction_matrix, reference_slopes, regularised_lse  # noqa: F401,E501
 from .philox import philox4x32_10, philox4x32_10_scalar, uniforms_from_words  # noqa: F401
