@@ -15,7 +15,7 @@
  *   - All data buffers are DEVICE pointers owned by the caller (float32, row-major).
  *   - Every call that takes a `stream` (a hipStream_t; NULL = the default stream) is
  *     asynchronous on it and never synchronises the device, except wfs_plan, wfs_plan_destroy
- *     and wfs_plan_tune.  No call allocates device memory except wfs_plan, recon_apply
+ *     and wfs_plan_tune (and wfs_tlse).  No call allocates device memory except wfs_plan, recon_apply
  *     (first use on a device, or a larger problem than seen before) and wfs_adjoint (first
  *     use of a plan).
  *   - Arguments are validated on the host before anything is launched: a bad argument returns
@@ -234,6 +234,43 @@ int wfs_plan_tune(wfs_plan_t plan, const float* layers, int32_t iters, double* b
  */
 int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B, float* C,
                 int64_t ldc, float alpha, float beta, void* stream);
+
+/*
+ * wfs_calibrate -- interaction-matrix calibration (Sec. 2.5: the chosen modes are pushed
+ *   through the sensor model and their slopes recorded, optionally with noise or with a
+ *   turbulence screen present, together with the reference slopes).  The modes are single
+ *   actuator pokes: actuator j (0 <= j < n_act) is element act_offset + j of a realisation's
+ *   layer buffer (a DM grid declared as a layer, so its bilinear interpolation is the influence
+ *   function).  With h = plan batch / 2 (the batch must be even), each chunk of h actuators is
+ *   one wfs_forward of a batch whose realisation r < h holds actuator j0 + r at +amplitude and
+ *   realisation h + r the same actuator at -amplitude, on top of `base` (device
+ *   [layer_stride], one realisation: e.g. an on-sky screen; NULL = flat); then row j of `im`
+ *   is (s+ - s-) / (2 amplitude).  Chunk c runs at step `step` + c, so noise (sensors with
+ *   photons > 0) differs between chunks; static grids do not move.  im: device
+ *   [n_act][ld_im] (ld_im >= n_slopes): row j = d slopes / d actuator j, i.e. the
+ *   interaction matrix transposed.  ref_slopes: device [n_slopes], realisation 0 of an
+ *   unpoked batch at `step` (NULL = not wanted).  work: device, at least the number of floats
+ *   wfs_calibrate_work returns.  Asynchronous on `stream`; deterministic for fixed inputs.
+ */
+int wfs_calibrate_work(wfs_plan_t plan, int64_t* work_floats);
+int wfs_calibrate(wfs_plan_t plan, const float* base, int64_t act_offset, int32_t n_act,
+                  float amplitude, int64_t step, uint64_t seed, float* im, int64_t ld_im,
+                  float* ref_slopes, float* work, int64_t work_floats, void* stream);
+
+/*
+ * wfs_tlse -- control matrix from an interaction matrix (Sec. 2.6: least-squares estimator,
+ *   with a regularisation coefficient and per-actuator weights that set how the correction is
+ *   shared between the DMs):  R = (D^T D + lambda diag(w))^-1 D^T,  lambda = eps * mean of
+ *   diag(D^T D), where D[k][j] = im[j][k] (n_s slopes x m actuators).  im: device [m][ld_im]
+ *   as wfs_calibrate writes it.  weights: device [m], >= 0, or NULL (all 1).  R: device
+ *   [m][ld_r], row-major as recon_apply takes it; R == im (in place, ld_r == ld_im) is
+ *   allowed.  work: device, >= m*m + 64 floats.  Set-up work: rocBLAS syrk and trsm with a
+ *   rocSOLVER Cholesky factorisation, FP32; synchronises `stream`.  Returns WFS_EINVAL when
+ *   the regularised matrix is not positive definite (eps = 0 with a rank-deficient D).
+ */
+int wfs_tlse(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
+             const float* weights, float* R, int64_t ld_r, float* work, int64_t work_floats,
+             void* stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* wfs_last_error(void);

@@ -13,4 +13,5 @@ from ._lib import (  # noqa: F401
     WfsError,
     lib,
 )
-from .wfs import Plan, WFSFunction, recon_apply, wfs_slopes  # noqa: F401
+from .wfs import Plan, WFSFunction, recon_apply, tlse, wfs_slopes  # noqa: F401
+from . import calib  # noqa: F401

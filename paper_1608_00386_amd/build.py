@@ -61,7 +61,10 @@ def build(verbose=False, extra=()):
         if any(rc != 0 for rc, _ in results):
             raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
         tmp = LIB + ".tmp"
-        link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
+        # rocBLAS / rocSOLVER: the one-off dense algebra of the control matrix (wfs_tlse)
+        rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+        link = ([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs +
+                [f"-L{rocm_lib}", "-lrocsolver", "-lrocblas", "-o", tmp])
         rc, lines = _run(link)
         if rc != 0:
             raise RuntimeError("link failed:\n" + "\n".join(lines))

@@ -28,6 +28,13 @@ hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* g
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
                         int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma);
+hipError_t calib_poke(float* layers, const float* base, int64_t stride, int32_t h, int64_t act0,
+                      int32_t n_chunk, float amp, hipStream_t st);
+hipError_t calib_diff(const float* slopes, int32_t h, int32_t n_slopes, int32_t n_chunk,
+                      float amp, float* im, int64_t ld_im, hipStream_t st);
+const char* tlse_run(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
+                     const float* w, float* R, int64_t ld_r, float* work, hipStream_t st,
+                     int* info);
 int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats);
 int fft_lds_bytes(int n_sub, int n_fft, int n_pix);
 bool fft_supported(int n_sub, int n_fft, int bin);
@@ -1116,6 +1123,115 @@ int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
   int mfma = 0;
   hipError_t e = recon_launch(R, M, N, S, B, C, ldc, alpha, beta, (hipStream_t)stream, &mfma);
   if (e != hipSuccess) return hip_fail(e, "recon_apply");
+  return WFS_OK;
+}
+
+// Calibration workspace: a [B][layer_stride] layer batch, then [B][n_slopes] slopes and
+// [B][n_valid_total] fluxes, each region starting on a 64-float boundary.
+static int64_t round64(int64_t x) { return (x + 63) / 64 * 64; }
+
+static int64_t calib_floats(wfs_plan_t P, int64_t* o_slopes, int64_t* o_aux) {
+  const int64_t B = P->batch;
+  const int64_t a = round64(B * P->layer_stride);
+  const int64_t b = a + round64(B * P->n_slopes);
+  if (o_slopes) *o_slopes = a;
+  if (o_aux) *o_aux = b;
+  return b + round64(B * P->n_valid_total);
+}
+
+int wfs_calibrate_work(wfs_plan_t P, int64_t* work_floats) {
+  if (!P || !work_floats) return fail(WFS_EINVAL, "wfs_calibrate_work: null argument");
+  *work_floats = calib_floats(P, nullptr, nullptr);
+  return WFS_OK;
+}
+
+int wfs_calibrate(wfs_plan_t P, const float* base, int64_t act_offset, int32_t n_act,
+                  float amplitude, int64_t step, uint64_t seed, float* im, int64_t ld_im,
+                  float* ref_slopes, float* work, int64_t work_floats, void* stream) {
+  if (!P) return fail(WFS_EINVAL, "wfs_calibrate: null plan");
+  if (!work) return fail(WFS_EINVAL, "wfs_calibrate: null work");
+  if (P->batch < 2 || P->batch % 2)
+    return fail(WFS_EINVAL, "wfs_calibrate: plan batch %d must be even and >= 2", P->batch);
+  if (n_act < 0) return fail(WFS_EINVAL, "wfs_calibrate: n_act=%d < 0", n_act);
+  if (n_act > 0 && !im) return fail(WFS_EINVAL, "wfs_calibrate: null im");
+  if (act_offset < 0 || act_offset + n_act > P->layer_stride)
+    return fail(WFS_EINVAL, "wfs_calibrate: actuators [%lld, %lld) outside the layer stride %lld",
+                (long long)act_offset, (long long)(act_offset + n_act),
+                (long long)P->layer_stride);
+  if (!std::isfinite(amplitude) || amplitude == 0.0f)
+    return fail(WFS_EINVAL, "wfs_calibrate: amplitude must be finite and non-zero");
+  if (ld_im < P->n_slopes)
+    return fail(WFS_EINVAL, "wfs_calibrate: ld_im=%lld < n_slopes=%d", (long long)ld_im,
+                P->n_slopes);
+  int rc = check_step(step, "wfs_calibrate");
+  if (rc) return rc;
+  if (step == WFS_STEP_DEVICE)
+    return fail(WFS_EINVAL, "wfs_calibrate: step must be an explicit step >= 0");
+  const int32_t h = P->batch / 2;
+  const int64_t chunks = ((int64_t)n_act + h - 1) / h;
+  if (step > INT64_MAX - chunks) return fail(WFS_EINVAL, "wfs_calibrate: step overflow");
+  int64_t o_s = 0, o_a = 0;
+  const int64_t need = calib_floats(P, &o_s, &o_a);
+  if (work_floats < need)
+    return fail(WFS_EINVAL, "wfs_calibrate: work holds %lld floats, needs %lld",
+                (long long)work_floats, (long long)need);
+  rc = check_device(P, "wfs_calibrate");
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  float* wl = work;
+  float* ws = work + o_s;
+  float* wa = work + o_a;
+  hipError_t e = hipSuccess;
+  if (ref_slopes) {  // realisation 0 of an unpoked batch
+    if ((e = calib_poke(wl, base, P->layer_stride, h, act_offset, 0, amplitude, st)) !=
+        hipSuccess)
+      return hip_fail(e, "wfs_calibrate: poke");
+    rc = wfs_forward(P, wl, step, seed, ws, wa, stream);
+    if (rc) return rc;
+    e = hipMemcpyAsync(ref_slopes, ws, (size_t)P->n_slopes * sizeof(float),
+                       hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "wfs_calibrate: reference slopes");
+  }
+  for (int64_t c = 0; c < chunks; ++c) {
+    const int32_t j0 = (int32_t)(c * h);
+    const int32_t nc = std::min<int32_t>(h, n_act - j0);
+    if ((e = calib_poke(wl, base, P->layer_stride, h, act_offset + j0, nc, amplitude, st)) !=
+        hipSuccess)
+      return hip_fail(e, "wfs_calibrate: poke");
+    rc = wfs_forward(P, wl, step + c, seed, ws, wa, stream);
+    if (rc) return rc;
+    if ((e = calib_diff(ws, h, P->n_slopes, nc, amplitude, im + (int64_t)j0 * ld_im, ld_im,
+                        st)) != hipSuccess)
+      return hip_fail(e, "wfs_calibrate: difference");
+  }
+  return WFS_OK;
+}
+
+int wfs_tlse(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
+             const float* weights, float* R, int64_t ld_r, float* work, int64_t work_floats,
+             void* stream) {
+  if (!im || !R || !work) return fail(WFS_EINVAL, "wfs_tlse: null im, R or work");
+  if (m < 1 || n_s < 1) return fail(WFS_EINVAL, "wfs_tlse: m=%d n_s=%d must be >= 1", m, n_s);
+  if (m > 46000) return fail(WFS_EINVAL, "wfs_tlse: m=%d > 46000 actuators", m);
+  if (ld_im < n_s || ld_r < n_s || ld_im > INT32_MAX || ld_r > INT32_MAX)
+    return fail(WFS_EINVAL, "wfs_tlse: ld_im=%lld and ld_r=%lld must lie in [n_s=%d, 2^31)",
+                (long long)ld_im, (long long)ld_r, n_s);
+  if (R == im && ld_r != ld_im)
+    return fail(WFS_EINVAL, "wfs_tlse: in place (R == im) needs ld_r == ld_im");
+  if (!std::isfinite(eps) || eps < 0.0f)
+    return fail(WFS_EINVAL, "wfs_tlse: eps must be finite and >= 0");
+  const int64_t need = (int64_t)m * m + 64;
+  if (work_floats < need)
+    return fail(WFS_EINVAL, "wfs_tlse: work holds %lld floats, needs %lld",
+                (long long)work_floats, (long long)need);
+  int info = 0;
+  const char* err = tlse_run(im, m, n_s, ld_im, eps, weights, R, ld_r, work,
+                             (hipStream_t)stream, &info);
+  if (err) return fail(WFS_EDEVICE, "wfs_tlse: %s", err);
+  if (info != 0)
+    return fail(WFS_EINVAL,
+                "wfs_tlse: the regularised normal matrix is not positive definite (leading "
+                "minor %d): raise eps or the weights", info);
   return WFS_OK;
 }
 

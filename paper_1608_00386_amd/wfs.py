@@ -192,6 +192,33 @@ class Plan:
         L.check(self._lib.wfs_advance_step(self._h, int(delta), _stream(stream)),
                 "wfs_advance_step")
 
+    def calibrate(self, act_offset, n_act, amplitude=0.1, step=0, seed=42, base=None,
+                  im=None, ref=None, stream=None):
+        """Push-pull interaction matrix of actuators act_offset .. act_offset + n_act - 1 of a
+        realisation's buffer (``wfs_calibrate``): returns (im [n_act][n_slopes], ref
+        [n_slopes]); row j is d slopes / d actuator j.  The plan's batch (even) sets the
+        actuators per forward call (batch / 2)."""
+        n_act = int(n_act)
+        dev = torch.device("cuda", self.device)
+        if base is not None:
+            _need(base, "base", numel=self.layer_stride)
+        if im is None:
+            im = torch.empty(n_act, self.n_slopes, device=dev)
+        if ref is None:
+            ref = torch.empty(self.n_slopes, device=dev)
+        _need(im, "im")
+        _need(ref, "ref", numel=self.n_slopes)
+        if im.dim() != 2 or im.shape[0] != n_act or im.shape[1] < self.n_slopes:
+            raise ValueError(f"im {tuple(im.shape)} must be [{n_act}][>= {self.n_slopes}]")
+        nw = ctypes.c_int64()
+        L.check(self._lib.wfs_calibrate_work(self._h, ctypes.byref(nw)), "wfs_calibrate_work")
+        work = torch.empty(nw.value, device=dev)
+        L.check(self._lib.wfs_calibrate(self._h, _ptr(base), int(act_offset), n_act,
+                                        float(amplitude), int(step), int(seed), _ptr(im),
+                                        int(im.stride(0)), _ptr(ref), _ptr(work), nw.value,
+                                        _stream(stream)), "wfs_calibrate")
+        return im, ref
+
     def tune(self, layers, iters=20, stream=None):
         """Time the launch schedules on ``layers`` and keep the fastest; returns its us/call."""
         self._layers(layers)
@@ -223,6 +250,26 @@ def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None):
     L.check(L.lib().recon_apply(_ptr(R), int(M), int(N), _ptr(S), int(B), _ptr(C), int(ldc),
                                 float(alpha), float(beta), _stream(stream)), "recon_apply")
     return C
+
+
+def tlse(im, eps=1e-3, weights=None, out=None, stream=None):
+    """Control matrix R [m][n_s] = (D^T D + eps mean(diag D^T D) diag(w))^-1 D^T of the
+    interaction matrix im [m][n_s] (row j = slopes of actuator j), ``wfs_tlse``.  ``out`` may
+    be ``im`` itself (computed in place).  Synchronises the stream."""
+    _need(im, "im")
+    if im.dim() != 2:
+        raise ValueError(f"im must be [m][n_s] (got {tuple(im.shape)})")
+    m, n_s = im.shape
+    if weights is not None:
+        _need(weights, "weights", numel=m)
+    if out is None:
+        out = torch.empty(m, n_s, device=im.device)
+    _need(out, "out", shape=(m, n_s))
+    work = torch.empty(m * m + 64, device=im.device)
+    L.check(L.lib().wfs_tlse(_ptr(im), int(m), int(n_s), int(n_s), float(eps), _ptr(weights),
+                             _ptr(out), int(n_s), _ptr(work), work.numel(), _stream(stream)),
+            "wfs_tlse")
+    return out
 
 
 class WFSFunction(torch.autograd.Function):

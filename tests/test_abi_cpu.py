@@ -119,3 +119,40 @@ def test_recon_rejects_bad_shapes_without_a_device():
     assert L.recon_apply(fake, 8, 4, fake, 1, fake, 4, 1.0, 0.0, None) == -1
     assert "ldc" in L.wfs_last_error().decode()
     assert L.recon_apply(fake, 8, 4, fake, 1, fake, 8, math.nan, 0.0, None) == -1
+
+
+def test_calibration_calls_reject_bad_arguments_without_a_device():
+    from paper_1608_00386_amd import _lib
+    L = _lib.lib()
+    fake = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    n = ctypes.c_int64()
+    assert L.wfs_calibrate_work(None, ctypes.byref(n)) == -1
+    assert L.wfs_calibrate(None, None, 0, 1, 0.1, 0, 42, fake, 8, None, fake, 1 << 20,
+                           None) == -1
+    assert "null plan" in L.wfs_last_error().decode()
+    # wfs_tlse: shapes, leading dimensions, eps, workspace, in-place stride
+    assert L.wfs_tlse(None, 4, 8, 8, 0.1, None, fake, 8, fake, 100, None) == -1
+    assert L.wfs_tlse(fake, 0, 8, 8, 0.1, None, fake, 8, fake, 100, None) == -1
+    assert L.wfs_tlse(fake, 4, 8, 7, 0.1, None, fake, 8, fake, 100, None) == -1
+    assert "ld_im" in L.wfs_last_error().decode()
+    assert L.wfs_tlse(fake, 4, 8, 8, -1.0, None, fake, 8, fake, 100, None) == -1
+    assert L.wfs_tlse(fake, 4, 8, 8, math.nan, None, fake, 8, fake, 100, None) == -1
+    assert L.wfs_tlse(fake, 4, 8, 8, 0.1, None, fake, 8, fake, 79, None) == -1
+    assert "work" in L.wfs_last_error().decode()
+    assert L.wfs_tlse(fake, 4, 8, 8, 0.1, None, ctypes.c_void_p(4096), 9, fake, 100,
+                      None) == -1
+    assert "in place" in L.wfs_last_error().decode()
+
+
+def test_dm_calibration_config_keeps_actuator_order():
+    from paper_1608_00386_amd import calib
+    cfg = synth.config4(batch=1)
+    ccfg, n_act = calib.dm_config(cfg, batch=64)
+    assert n_act == 40 * 40 + 42 * 42 + 45 * 45 == 5389
+    assert [L["offset"] for L in ccfg["layers"]] == [0, 1600, 1600 + 1764]
+    assert all(L["weight"] < 0 and L["boundary"] == 1 for L in ccfg["layers"])
+    assert ccfg["layer_stride"] % 64 == 0 and ccfg["layer_stride"] >= n_act
+    assert all(s["photons"] == 0 and s["read_noise_e"] == 0 for s in ccfg["sensors"])
+    assert any(s["photons"] > 0 for s in cfg["sensors"])  # the original is left alone
+    with pytest.raises(ValueError):
+        calib.dm_config(cfg, batch=3)
