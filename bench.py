@@ -16,6 +16,7 @@ roofline fraction of the dominant kernel and the FP64 oracle's rate on the host 
 """
 
 import argparse
+import copy
 import glob
 import json
 import os
@@ -242,6 +243,74 @@ def bench_closed_loop(torch, W, steps=20, batch=8, gain=0.4):
     return dict(workload="config4: config2 sensors + 3 DMs (40^2, 42^2, 45^2 @ 0/4/12.7 km), "
                          "R 5400 x 55608 FP32, integrator g=0.4, graph of %d steps" % steps,
                 ms_per_step=gpu_ms, steps_per_s=1e3 / gpu_ms, n_slopes=plan.n_slopes)
+
+
+def bench_calibration(torch, W, batch=128, amp=0.5, eps=0.05, loop_steps=60, gain=0.4):
+    """Interaction matrix of the 5,389 config-4 DM actuators by push-pull through the batched
+    forward (a DM-only plan, noise off, batch / 2 actuators per call), the regularised
+    least-squares control matrix from it, and the config-4 loop closed with that matrix:
+    slope norms against the open loop over the same frozen-flow steps (noise on)."""
+    cfg4 = synth.config4(batch=8)
+    ccfg, n = W.calib.dm_config(cfg4, batch=batch)
+    plan = W.Plan(ccfg)
+    im, ref = plan.calibrate(0, n, amplitude=amp)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.calibrate(0, n, amplitude=amp, im=im, ref=ref)
+    e1.record()
+    torch.cuda.synchronize()
+    cal_ms = e0.elapsed_time(e1)
+    W.tlse(im, eps=eps)  # warm the library handles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R = W.tlse(im, eps=eps)
+    tlse_ms = (time.perf_counter() - t0) * 1e3
+    del im
+    # closed loop against open loop, same layers and steps, with and without noise
+    B = cfg4["batch"]
+    x0 = torch.from_numpy(synth.make_batch(cfg4, range(B))).cuda()
+    o, ldc = cfg4["dm_offset"], cfg4["layer_stride"]
+    x0[:, o:] = 0.0
+    tail = max(1, loop_steps // 3)
+
+    def loop(cfg):
+        lp = W.Plan(cfg)
+        xc = x0.clone()
+        dm = xc[:, o:o + n]
+        s = torch.empty(B, lp.n_slopes, device="cuda")
+        a = torch.empty(B, lp.n_valid_total, device="cuda")
+        open_n, closed_n = [], []
+        for k in range(loop_steps):
+            lp.forward(x0, step=k, slopes=s, aux=a)
+            open_n.append(float(s.norm()))
+            lp.forward(xc, step=k, slopes=s, aux=a)
+            closed_n.append(float(s.norm()))
+            W.recon_apply(R, s, dm, alpha=-gain, beta=1.0, ldc=ldc)
+        return float(np.mean(closed_n[-tail:]) / np.mean(open_n[-tail:]))
+
+    ratio = loop(cfg4)
+    n_lgs = sum(1 for sd in cfg4["sensors"] if np.isfinite(sd["src_alt_m"]))
+    real_flops = plan_flops(ccfg, plan)  # one realisation, all nine sensors, FFT convention
+    quiet = copy.deepcopy(cfg4)
+    for sd in quiet["sensors"]:
+        sd["photons"] = 0.0
+        sd["read_noise_e"] = 0.0
+    ratio_nf = loop(quiet)
+    return dict(workload="config4 DMs (5,389 actuators at 0/4/12.7 km) seen by 6 LGS + 3 NGS "
+                         "(55,608 slopes); push-pull amplitude %.2f rad, %d realisations per "
+                         "call; R = (D^T D + %.2g mean diag I)^-1 D^T" % (amp, batch, eps),
+                calibration_ms=cal_ms, actuators_per_s=n / (cal_ms * 1e-3),
+                sensor_frames_per_s=2 * n / (cal_ms * 1e-3),
+                lgs_frames_per_s=n_lgs * 2 * n / (cal_ms * 1e-3),
+                effective_tflops=2 * n * real_flops / (cal_ms * 1e-3) / 1e12,
+                tlse_ms=tlse_ms,
+                closed_loop_steps=loop_steps,
+                closed_over_open_slope_norm=ratio,
+                closed_over_open_slope_norm_noise_free=ratio_nf,
+                note="slope norms over the last %d steps, integrator a <- a - %.1f R s"
+                     % (tail, gain))
 
 
 def bench_adjoint(torch, W, reps=20):
@@ -533,6 +602,11 @@ def main():
             out["closed_loop"] = bench_closed_loop(torch, W)
         except Exception as e:
             out["closed_loop"] = {"error": repr(e)}
+        try:
+            log("[bench] config4 calibration and calibrated loop ...")
+            out["calibration"] = bench_calibration(torch, W)
+        except Exception as e:
+            out["calibration"] = {"error": repr(e)}
         if cpu is not None:
             out["cpu_baseline"] = cpu
             out["cpu_baseline_all_cores"] = cpu_pool
