@@ -38,4 +38,7 @@ from .wfs_oracle import (  # noqa: F401
     pixel_scale,
 )
 from .calib_oracle import interaction_matrix, reference_slopes, regularised_lse  # noqa: F401,E501
+from .psf_oracle import (  # noqa: F401
+    science_pupil, residual_phase, psf_frame, phase_variance, long_exposure, strehl_from_psf,
+    strehl_marechal)
 from .philox import philox4x32_10, philox4x32_10_scalar, uniforms_from_words  # noqa: F401
