@@ -272,6 +272,44 @@ int wfs_tlse(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
              const float* weights, float* R, int64_t ld_r, float* work, int64_t work_floats,
              void* stream);
 
+/*
+ * Point-spread functions and Strehl ratios (Sec. 2.8: PSFs at user wavelengths and pixel
+ * scales for a constellation of test stars; Strehl ratio from the PSF or, with the Marechal
+ * approximation, from the history of the residual wavefront).
+ *
+ * psf_plan -- test stars at infinity in directions star_theta_xy[2*s], [2*s+1] (rad), seeing
+ *   the layers (turbulence +1, DM grids -1: the residual phase) on a full n_pup x n_pup pupil
+ *   grid of pitch pupil_d_m / n_pup (pixel centres (i + 1/2 - n_pup/2) dx, amplitude 1 where
+ *   obs_d_m/2 <= r <= pupil_d_m/2).  Per wavelength lambda_m[l] the field
+ *   A exp(i (lambda_ref/lambda) phi) is zero-padded to n_fft[l] x n_fft[l] (a power of two in
+ *   [max(16, n_pup), 4096]; PSF pixel = lambda / (n_fft dx) rad).  Layers as in wfs_plan
+ *   (offsets inside layer_stride, periodic or zero boundary, frozen flow at t = step dt_s).
+ *   Allocates the plan's device tables and a [n_stars][n_pup][max n_fft] complex work buffer.
+ * psf_plan_info -- floats of the PSF buffer (sum over l of n_stars n_fft[l]^2), the first float
+ *   of each wavelength's images (psf_offsets[n_lambda]), and the lit pupil pixels.  Any output
+ *   may be NULL.
+ * psf_accumulate -- adds one frame: psf (device, psf_floats) gets, per wavelength l and star s,
+ *   the image [n_fft][n_fft] at psf + psf_offsets[l] + s n_fft^2 of |DFT(field)|^2 / (n_fft^2
+ *   n_lit) (unit sum per frame; zero frequency at pixel (n_fft/2, n_fft/2); row = y frequency).
+ *   layers: device [layer_stride], one realisation.  phase_var: device double [n_lambda]
+ *   [n_stars] or NULL; gets the piston-removed variance over the lit pupil of the phase at
+ *   each wavelength (rad^2).  Asynchronous; deterministic.
+ * psf_strehl -- after n_frames accumulations: sr_psf[l][s] = the long-exposure image at zero
+ *   frequency over the diffraction-limited peak (n_frames n_lit / n_fft^2); sr_marechal[l][s] =
+ *   exp(-phase_var[l][s] / n_frames).  Device outputs (float), either may be NULL.
+ */
+typedef struct psf_plan_s* psf_plan_t;
+int psf_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_stride,
+             const double* star_theta_xy, int32_t n_stars, double pupil_d_m, double obs_d_m,
+             int32_t n_pup, const double* lambda_m, const int32_t* n_fft, int32_t n_lambda,
+             double lambda_ref_m, double dt_s, psf_plan_t* out);
+int psf_plan_info(psf_plan_t plan, int64_t* psf_floats, int64_t* psf_offsets, int64_t* n_lit);
+int psf_plan_destroy(psf_plan_t plan);
+int psf_accumulate(psf_plan_t plan, const float* layers, int64_t step, float* psf,
+                   double* phase_var, void* stream);
+int psf_strehl(psf_plan_t plan, const float* psf, const double* phase_var, int64_t n_frames,
+               float* sr_psf, float* sr_marechal, void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* wfs_last_error(void);
 

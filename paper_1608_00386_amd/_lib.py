@@ -96,6 +96,15 @@ _PROTOS = {
                                  _c.c_uint64, _P, _c.c_int64, _P, _P, _c.c_int64, _P]),
     "wfs_tlse": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_float, _P, _P,
                             _c.c_int64, _P, _c.c_int64, _P]),
+    "psf_plan": (_c.c_int, [_c.POINTER(LayerDesc), _c.c_int32, _c.c_int64,
+                            _c.POINTER(_c.c_double), _c.c_int32, _c.c_double, _c.c_double,
+                            _c.c_int32, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int32),
+                            _c.c_int32, _c.c_double, _c.c_double, _c.POINTER(_P)]),
+    "psf_plan_info": (_c.c_int, [_P, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                 _c.POINTER(_c.c_int64)]),
+    "psf_plan_destroy": (_c.c_int, [_P]),
+    "psf_accumulate": (_c.c_int, [_P, _P, _c.c_int64, _P, _P, _P]),
+    "psf_strehl": (_c.c_int, [_P, _P, _P, _c.c_int64, _P, _P, _P]),
     "wfs_last_error": (_c.c_char_p, []),
 }
 

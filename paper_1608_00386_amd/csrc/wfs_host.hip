@@ -55,6 +55,14 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+namespace wfs {
+// Error reporting for the other translation units of the C ABI (same thread-local message).
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace wfs
+
 static int hip_fail(hipError_t e, const char* what) {
   return fail(e == hipErrorOutOfMemory ? WFS_ENOMEM : WFS_EDEVICE, "%s: %s", what,
               hipGetErrorString(e));
