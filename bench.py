@@ -313,6 +313,34 @@ def bench_calibration(torch, W, batch=128, amp=0.5, eps=0.05, loop_steps=60, gai
                      % (tail, gain))
 
 
+def bench_psf(torch, W, frames=20, lam=2.2e-6, N=2048):
+    """Long-exposure K-band PSFs of a 3 x 3 grid of test stars (30 arcsec spacing) through the
+    config-4 layers and DMs: 800 x 800 pupil padded to 2048 x 2048, one psf_accumulate per
+    frame (row-FFT and column-FFT passes per star), frames captured in one HIP graph."""
+    from synth.configs import ARCSEC
+    cfg = synth.config4(batch=1)
+    x = torch.from_numpy(synth.make_batch(cfg, [0])[0]).cuda()
+    stars = [(a * 30 * ARCSEC, b * 30 * ARCSEC) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+    n_pup = 800
+    plan = W.PsfPlan(cfg, stars, 39.0, 11.0, n_pup, [lam], [N])
+    psf, var = plan.buffers()
+    g = graph_of(torch, lambda i: plan.accumulate(x, i, psf, var), frames)
+    g.replay()
+    wall, gpu_ms = timed_replay(torch, g, frames)
+    ns = len(stars)
+    # HBM bytes a two-pass transform cannot avoid: the row transforms written and read back
+    # (n_pup x N complex per star) and the long-exposure image read and written (N^2 floats)
+    byts = ns * (2 * n_pup * N * 8 + 2 * N * N * 4)
+    return dict(workload="config4 layers + DMs, 9 test stars, 800^2 pupil padded to %d^2, "
+                         "lambda %.2f um (pixel %.1f mas), graph of %d frames"
+                         % (N, lam * 1e6, lam / (N * 39.0 / n_pup) / ARCSEC * 1e3, frames),
+                ms_per_frame=gpu_ms, psf_frames_per_s=1e3 / gpu_ms,
+                star_psfs_per_s=ns * 1e3 / gpu_ms,
+                roofline={"bound": "hbm", "algorithmic_bytes_per_frame": byts,
+                          "achieved": byts / (gpu_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                          "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM})
+
+
 def bench_adjoint(torch, W, reps=20):
     cfg = synth.config3()
     x = torch.from_numpy(synth.make_batch(cfg, [cfg["guess_realisation"]])).cuda()
@@ -607,6 +635,11 @@ def main():
             out["calibration"] = bench_calibration(torch, W)
         except Exception as e:
             out["calibration"] = {"error": repr(e)}
+        try:
+            log("[bench] PSF module ...")
+            out["psf"] = bench_psf(torch, W)
+        except Exception as e:
+            out["psf"] = {"error": repr(e)}
         if cpu is not None:
             out["cpu_baseline"] = cpu
             out["cpu_baseline_all_cores"] = cpu_pool

@@ -26,9 +26,9 @@ namespace wfs {
 int set_error(int code, const char* msg);
 
 constexpr int kPsfBlock = 256;
-constexpr int kPsfPoints = 4096;  // LDS points of one workgroup (C columns x N, or one row)
-constexpr int kPsfB4 = kPsfPoints / 4 / kPsfBlock;  // radix-4 butterflies per thread
-constexpr int kPsfB2 = kPsfPoints / 2 / kPsfBlock;  // radix-2 butterflies per thread
+constexpr int kPsfPoints = 4096;     // largest transform (and one row-pass workgroup's LDS)
+constexpr int kPsfColPoints = 16384; // LDS points of a column-pass workgroup (C columns x N)
+constexpr int kPsfColLds = 132 * 1024;  // its LDS bytes at most: C (N + 1) float2
 constexpr int kPsfMaxLambda = 16;
 constexpr int kPsfMaxStars = 256;
 
@@ -59,8 +59,11 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 // In-place forward DFT, X[k] = sum_j x[j] exp(-2 pi i j k / N), of `cnt` sequences of N = 2^log2N
 // points held in LDS at buf + c * ld.  Each Stockham stage reads its inputs into registers,
 // waits for the whole workgroup, writes its outputs and waits again, so one buffer suffices.
+template <int POINTS, int THREADS>
 __device__ void lds_fft(float2* buf, int cnt, int ld, int N, int log2N,
                         const float2* __restrict__ tw) {
+  constexpr int kPsfB4 = POINTS / 4 / THREADS;  // radix-4 butterflies per thread
+  constexpr int kPsfB2 = POINTS / 2 / THREADS;  // radix-2 butterflies per thread
   const int tid = threadIdx.x;
   const int q = N >> 2, lq = log2N - 2;
   int Ns = 1;
@@ -71,7 +74,7 @@ __device__ void lds_fft(float2* buf, int cnt, int ld, int N, int log2N,
     int ob[kPsfB4];
 #pragma unroll
     for (int it = 0; it < kPsfB4; ++it) {
-      const int b = tid + it * kPsfBlock;
+      const int b = tid + it * THREADS;
       if (b < nb) {
         const int c = b >> lq, j = b & (q - 1);
         const int k = j & (Ns - 1);
@@ -97,7 +100,7 @@ __device__ void lds_fft(float2* buf, int cnt, int ld, int N, int log2N,
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kPsfB4; ++it) {
-      const int b = tid + it * kPsfBlock;
+      const int b = tid + it * THREADS;
       if (b < nb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) buf[ob[it] + r * Ns] = y[it][r];
@@ -111,7 +114,7 @@ __device__ void lds_fft(float2* buf, int cnt, int ld, int N, int log2N,
     const int nb = cnt << lh;
 #pragma unroll
     for (int it = 0; it < kPsfB2; ++it) {
-      const int b = tid + it * kPsfBlock;
+      const int b = tid + it * THREADS;
       if (b < nb) {
         const int c = b >> lh, j = b & (h - 1);
         float2* x = buf + c * ld + j;
@@ -125,26 +128,56 @@ __device__ void lds_fft(float2* buf, int cnt, int ld, int N, int log2N,
   }
 }
 
-// Row pass: workgroup (row y, star s).  Phase of the pupil row, field, N-point FFT, row of T.
+// Per-layer parameters of one pupil row, staged in LDS by the workgroup: the row tap (fixed
+// for the row) and the column affine map.
+struct RowLayer {
+  double a, b, inv_n;
+  int64_t offset;
+  int32_t n, boundary, r0, r1;
+  float w0, w1, weight;
+  int32_t pad;
+};
+
+// Row pass: workgroup (row y, star s).  Phase of the pupil row, field, N-point FFT, row of T
+// stored in C-column tiles: T[s][k / C][y][k % C], so the column pass reads whole tiles.
 __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
   extern __shared__ float2 sh[];
   __shared__ double red[2][kPsfBlock];
+  __shared__ RowLayer rl[kMaxLayers];
   const int y = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
-  const int n = p.n_pup, N = p.N;
-  const double stepd = (double)p.step;
+  const int n = p.n_pup, N = p.N, C = p.cols;
+  if (tid < p.n_layers) {
+    const DevLayer L = p.lay[tid];
+    const PsfAff A = p.aff[s * p.n_layers + tid];
+    const double stepd = (double)p.step;
+    const Tap ry = make_tap(fma(A.ay, (double)y, A.by0) + stepd * A.dby, L.ny, L.inv_ny,
+                            L.boundary, L.nx);
+    RowLayer r;
+    r.a = A.ax;
+    r.b = A.bx0 + stepd * A.dbx;
+    r.inv_n = L.inv_nx;
+    r.offset = L.offset;
+    r.n = L.nx;
+    r.boundary = L.boundary;
+    r.r0 = ry.i0;
+    r.r1 = ry.i1;
+    r.w0 = ry.w0;
+    r.w1 = ry.w1;
+    r.weight = L.weight;
+    r.pad = 0;
+    rl[tid] = r;
+  }
+  __syncthreads();
   double s1 = 0.0, s2 = 0.0;
   for (int x = tid; x < N; x += kPsfBlock) {
     float2 e = make_float2(0.0f, 0.0f);
     if (x < n && p.mask[(int64_t)y * n + x]) {
       float phi = 0.0f;
       for (int l = 0; l < p.n_layers; ++l) {
-        const DevLayer L = p.lay[l];
-        const PsfAff A = p.aff[s * p.n_layers + l];
-        const Tap cx = make_tap(fma(A.ax, (double)x, A.bx0) + stepd * A.dbx, L.nx, L.inv_nx,
-                                L.boundary, 1);
-        const Tap ry = make_tap(fma(A.ay, (double)y, A.by0) + stepd * A.dby, L.ny, L.inv_ny,
-                                L.boundary, L.nx);
-        phi = fmaf(L.weight, bilinear(p.layers + L.offset, cx, ry), phi);
+        const RowLayer& r = rl[l];
+        const Tap cx = make_tap(fma(r.a, (double)x, r.b), r.n, r.inv_n, r.boundary, 1);
+        const Tap ry{r.r0, r.r1, r.w0, r.w1};
+        phi = fmaf(r.weight, bilinear(p.layers + r.offset, cx, ry), phi);
       }
       s1 += (double)phi;
       s2 += (double)phi * (double)phi;
@@ -172,30 +205,35 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
     }
   }
   __syncthreads();
-  lds_fft(sh, 1, N, N, p.log2N, p.tw);
-  float2* out = p.T + ((int64_t)s * n + y) * N;
-  for (int x = tid; x < N; x += kPsfBlock) out[x] = sh[x];
+  lds_fft<kPsfPoints, kPsfBlock>(sh, 1, N, N, p.log2N, p.tw);
+  float2* out = p.T + (int64_t)s * n * N + (int64_t)y * C;
+  for (int x = tid; x < N; x += kPsfBlock) {
+    const int kt = x / C;
+    out[(int64_t)kt * n * C + (x - kt * C)] = sh[x];
+  }
 }
 
 // Column pass: workgroup (C adjacent columns, star s), blocks renumbered so that neighbouring
 // column groups share an XCD (and its L2 lines of T).  Zero rows beyond the pupil are implicit.
-__global__ __launch_bounds__(kPsfBlock) void psf_cols_kernel(PsfParams p) {
+constexpr int kPsfColBlock = 1024;  // 16 waves: the column pass is LDS-latency bound
+
+__global__ __launch_bounds__(kPsfColBlock) void psf_cols_kernel(PsfParams p) {
   extern __shared__ float2 sh[];
   const int tid = threadIdx.x;
   const int C = p.cols, N = p.N, n = p.n_pup, ld = N + 1;
   const int groups = N / C;
   const int lb = xcd_logical_block(blockIdx.x, groups * p.n_stars);
   const int s = lb / groups, k0 = (lb - s * groups) * C;
-  const float2* src = p.T + (int64_t)s * n * N + k0;
-  for (int i = tid; i < C * N; i += kPsfBlock) {
+  const float2* src = p.T + (int64_t)s * n * N + (int64_t)k0 * n;  // tile k0 / C: [n][C]
+  for (int i = tid; i < C * N; i += kPsfColBlock) {
     const int c = i & (C - 1), y = i / C;
-    sh[c * ld + y] = y < n ? src[(int64_t)y * N + c] : make_float2(0.0f, 0.0f);
+    sh[c * ld + y] = y < n ? src[i] : make_float2(0.0f, 0.0f);
   }
   __syncthreads();
-  lds_fft(sh, C, ld, N, p.log2N, p.tw);
+  lds_fft<kPsfColPoints, kPsfColBlock>(sh, C, ld, N, p.log2N, p.tw);
   float* dst = p.psf + (int64_t)s * N * N;
   const int h = N >> 1;
-  for (int i = tid; i < C * N; i += kPsfBlock) {
+  for (int i = tid; i < C * N; i += kPsfColBlock) {
     const int c = i & (C - 1), v = i / C;
     const float2 f = sh[c * ld + v];
     float* o = dst + (int64_t)((v + h) & (N - 1)) * N + ((k0 + c + h) & (N - 1));
@@ -211,19 +249,31 @@ struct PsfVarParams {
   float kappa2[kPsfMaxLambda];
 };
 
-// Piston-removed pupil variance of this frame's phase, per star, added at every wavelength.
+// Piston-removed pupil variance of this frame's phase, per star (one workgroup each: strided
+// row sums, then a fixed-order tree), added at every wavelength.
 __global__ __launch_bounds__(kPsfBlock) void psf_var_kernel(PsfVarParams q) {
-  const int s = blockIdx.x * kPsfBlock + threadIdx.x;
-  if (s >= q.n_stars) return;
+  __shared__ double red[2][kPsfBlock];
+  const int s = blockIdx.x, tid = threadIdx.x;
   double a = 0.0, b = 0.0;
-  for (int y = 0; y < q.n_pup; ++y) {
+  for (int y = tid; y < q.n_pup; y += kPsfBlock) {
     a += q.part[((int64_t)s * q.n_pup + y) * 2];
     b += q.part[((int64_t)s * q.n_pup + y) * 2 + 1];
   }
-  const double m = a * q.inv_lit;
-  const double var = b * q.inv_lit - m * m;
-  for (int l = 0; l < q.n_lambda; ++l)
-    q.phase_var[l * q.n_stars + s] += (double)q.kappa2[l] * var;
+  red[0][tid] = a;
+  red[1][tid] = b;
+  __syncthreads();
+  for (int w = kPsfBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid < q.n_lambda) {
+    const double m = red[0][0] * q.inv_lit;
+    const double var = red[1][0] * q.inv_lit - m * m;
+    q.phase_var[tid * q.n_stars + s] += (double)q.kappa2[tid] * var;
+  }
 }
 
 struct PsfStrehlParams {
@@ -401,7 +451,7 @@ int psf_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     while ((1 << lg) < N) ++lg;
     P->N.push_back(N);
     P->log2N.push_back(lg);
-    P->cols.push_back(std::max(1, std::min(16, kPsfPoints / N)));
+    P->cols.push_back(std::min(16, kPsfColPoints / N));
     P->kappa.push_back((float)(lambda_ref_m / lambda_m[l]));
     P->psf_off.push_back(P->psf_floats);
     P->psf_floats += (int64_t)n_stars * N * N;
@@ -411,6 +461,13 @@ int psf_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
     }
     Nmax = std::max(Nmax, N);
+  }
+  // the column pass holds up to 16,384 points (+ padding) in LDS: more than the default 64 KB
+  if ((e = hipFuncSetAttribute((const void*)psf_cols_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kPsfColLds)) !=
+      hipSuccess) {
+    psf_free(P);
+    return psf_hip(e, "psf_plan: column-pass LDS");
   }
   if ((e = upload(&P->lay, lay)) != hipSuccess || (e = upload(&P->aff, aff)) != hipSuccess ||
       (e = upload(&P->mask, mask)) != hipSuccess || (e = upload(&P->tw, tw)) != hipSuccess ||
@@ -486,12 +543,12 @@ int psf_accumulate(psf_plan_t P, const float* layers, int64_t step, float* psf,
       q.n_lambda = P->n_lambda;
       q.inv_lit = 1.0 / (double)P->n_lit;
       for (int m = 0; m < P->n_lambda; ++m) q.kappa2[m] = P->kappa[m] * P->kappa[m];
-      psf_var_kernel<<<(P->n_stars + kPsfBlock - 1) / kPsfBlock, kPsfBlock, 0, st>>>(q);
+      psf_var_kernel<<<P->n_stars, kPsfBlock, 0, st>>>(q);
       if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: variance");
     }
     const int blocks = (p.N / p.cols) * P->n_stars;
     const size_t lds = (size_t)p.cols * (p.N + 1) * sizeof(float2);
-    psf_cols_kernel<<<blocks, kPsfBlock, lds, st>>>(p);
+    psf_cols_kernel<<<blocks, kPsfColBlock, lds, st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: columns");
   }
   return WFS_OK;
