@@ -495,6 +495,9 @@ def main():
                     help="short run for a profiler: N pipelined config-1 frames (default "
                          "schedule) and N plain copies of 256 MiB (the HBM counter "
                          "calibration), then exit")
+    ap.add_argument("--only", choices=["psf", "calibration", "adjoint", "recon", "batched",
+                                       "closed_loop"],
+                    help="run one of the extra workloads alone and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the "
@@ -519,6 +522,12 @@ def main():
 
     if args.profile_frames > 0:
         profile_run(torch, W, args.profile_frames, flags=W.WFS_FLAG_FUSED if args.fused else 0)
+        return
+    if args.only:  # one extra on its own (a short run for a profiler)
+        fn = {"psf": bench_psf, "calibration": bench_calibration, "adjoint": bench_adjoint,
+              "recon": bench_recon, "batched": bench_batched,
+              "closed_loop": bench_closed_loop}[args.only]
+        print(json.dumps({args.only: fn(torch, W)}), flush=True)
         return
 
     log("[bench] config1 forward ...")

@@ -10,7 +10,7 @@
 // FFT in LDS; only the n_pup non-zero rows exist) and a column pass (a few adjacent columns per
 // workgroup, FFT in LDS, intensity accumulated in place).  Both FFTs are Stockham radix-4
 // stages with one radix-2 stage when log2 N is odd; twiddles come from an N-point table
-// computed in double precision on the host.
+// computed in double precision on the host (staged in LDS by the column pass).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,7 +28,8 @@ int set_error(int code, const char* msg);
 constexpr int kPsfBlock = 256;
 constexpr int kPsfPoints = 4096;     // largest transform (and one row-pass workgroup's LDS)
 constexpr int kPsfColPoints = 16384; // LDS points of a column-pass workgroup (C columns x N)
-constexpr int kPsfColLds = 132 * 1024;  // its LDS bytes at most: C (N + 1) float2
+constexpr int kPsfColLds = 160 * 1024;  // its LDS bytes at most: C (N + 1) + N float2
+constexpr int kPsfRowLds = kPsfPoints * 8;  // one row
 constexpr int kPsfMaxLambda = 16;
 constexpr int kPsfMaxStars = 256;
 
@@ -225,20 +226,38 @@ __global__ __launch_bounds__(kPsfColBlock) void psf_cols_kernel(PsfParams p) {
   const int lb = xcd_logical_block(blockIdx.x, groups * p.n_stars);
   const int s = lb / groups, k0 = (lb - s * groups) * C;
   const float2* src = p.T + (int64_t)s * n * N + (int64_t)k0 * n;  // tile k0 / C: [n][C]
+  float2* tws = sh + C * ld;  // the twiddle table, staged in LDS after the data
   for (int i = tid; i < C * N; i += kPsfColBlock) {
     const int c = i & (C - 1), y = i / C;
     sh[c * ld + y] = y < n ? src[i] : make_float2(0.0f, 0.0f);
   }
+  for (int i = tid; i < N; i += kPsfColBlock) tws[i] = p.tw[i];
   __syncthreads();
-  lds_fft<kPsfColPoints, kPsfColBlock>(sh, C, ld, N, p.log2N, p.tw);
-  float* dst = p.psf + (int64_t)s * N * N;
+  lds_fft<kPsfColPoints, kPsfColBlock>(sh, C, ld, N, p.log2N, tws);
+  // intensities from LDS, then every read of the long-exposure image before any write (one
+  // memory latency per thread instead of one per pixel)
+  float* __restrict__ dst = p.psf + (int64_t)s * N * N;
   const int h = N >> 1;
-  for (int i = tid; i < C * N; i += kPsfColBlock) {
-    const int c = i & (C - 1), v = i / C;
-    const float2 f = sh[c * ld + v];
-    float* o = dst + (int64_t)((v + h) & (N - 1)) * N + ((k0 + c + h) & (N - 1));
-    *o += (f.x * f.x + f.y * f.y) * p.scale;
+  constexpr int kPer = kPsfColPoints / kPsfColBlock;
+  float val[kPer];
+  int64_t at[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int i = tid + r * kPsfColBlock;
+    if (i < C * N) {
+      const int c = i & (C - 1), v = i / C;
+      const float2 f = sh[c * ld + v];
+      val[r] = (f.x * f.x + f.y * f.y) * p.scale;
+      at[r] = (int64_t)((v + h) & (N - 1)) * N + ((k0 + c + h) & (N - 1));
+    }
   }
+  float old[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r)
+    if (tid + r * kPsfColBlock < C * N) old[r] = dst[at[r]];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r)
+    if (tid + r * kPsfColBlock < C * N) dst[at[r]] = old[r] + val[r];
 }
 
 struct PsfVarParams {
@@ -451,7 +470,8 @@ int psf_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     while ((1 << lg) < N) ++lg;
     P->N.push_back(N);
     P->log2N.push_back(lg);
-    P->cols.push_back(std::min(16, kPsfColPoints / N));
+    // C columns of N points plus the N twiddles must fit the 160 KB of LDS
+    P->cols.push_back(N >= 4096 ? 2 : std::min(16, kPsfColPoints / N));
     P->kappa.push_back((float)(lambda_ref_m / lambda_m[l]));
     P->psf_off.push_back(P->psf_floats);
     P->psf_floats += (int64_t)n_stars * N * N;
@@ -462,10 +482,13 @@ int psf_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     }
     Nmax = std::max(Nmax, N);
   }
-  // the column pass holds up to 16,384 points (+ padding) in LDS: more than the default 64 KB
+  // the column pass holds more than the default 64 KB of LDS (data, padding and twiddles)
   if ((e = hipFuncSetAttribute((const void*)psf_cols_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, kPsfColLds)) !=
-      hipSuccess) {
+          hipSuccess ||
+      (e = hipFuncSetAttribute((const void*)psf_rows_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kPsfRowLds)) !=
+          hipSuccess) {
     psf_free(P);
     return psf_hip(e, "psf_plan: column-pass LDS");
   }
@@ -531,8 +554,8 @@ int psf_accumulate(psf_plan_t P, const float* layers, int64_t step, float* psf,
     p.kappa = P->kappa[l];
     p.scale = (float)(1.0 / ((double)p.N * p.N * (double)P->n_lit));
     p.write_part = (l == 0 && phase_var) ? 1 : 0;
-    psf_rows_kernel<<<dim3(P->n_pup, P->n_stars), kPsfBlock, (size_t)p.N * sizeof(float2), st>>>(
-        p);
+    psf_rows_kernel<<<dim3(P->n_pup, P->n_stars), kPsfBlock, (size_t)p.N * sizeof(float2),
+                      st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: rows");
     if (p.write_part) {
       PsfVarParams q{};
@@ -547,7 +570,7 @@ int psf_accumulate(psf_plan_t P, const float* layers, int64_t step, float* psf,
       if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: variance");
     }
     const int blocks = (p.N / p.cols) * P->n_stars;
-    const size_t lds = (size_t)p.cols * (p.N + 1) * sizeof(float2);
+    const size_t lds = ((size_t)p.cols * (p.N + 1) + p.N) * sizeof(float2);
     psf_cols_kernel<<<blocks, kPsfColBlock, lds, st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: columns");
   }
