@@ -41,4 +41,6 @@ from .calib_oracle import interaction_matrix, reference_slopes, regularised_lse 
 from .psf_oracle import (  # noqa: F401
     science_pupil, residual_phase, psf_frame, phase_variance, long_exposure, strehl_from_psf,
     strehl_marechal)
+from .screen_oracle import (  # noqa: F401
+    screen_normals, von_karman_psd, screen_spectrum, phase_screen)
 from .philox import philox4x32_10, philox4x32_10_scalar, uniforms_from_words  # noqa: F401
