@@ -310,6 +310,24 @@ int psf_accumulate(psf_plan_t plan, const float* layers, int64_t step, float* ps
 int psf_strehl(psf_plan_t plan, const float* psf, const double* phase_var, int64_t n_frames,
                float* sr_psf, float* sr_marechal, void* stream);
 
+/*
+ * screen_generate -- one periodic n x n phase screen (Sec. 2.1: random noise filtered in the
+ *   Fourier domain with the von Karman phase spectrum of given r0 and L0; L0 = INFINITY gives
+ *   the Kolmogorov spectrum):
+ *     screen[y][x] = Re sum_k (a_k + i b_k) sqrt(PSD(f_k)) df exp(+2 pi i (k_x x + k_y y) / n),
+ *     PSD(f) = 0.023 r0^(-5/3) (|f|^2 + L0^-2)^(-11/6), df = 1 / (n pitch_m), the f = 0 sample
+ *   zeroed; frequencies f_k = k / (n pitch_m) with k in [-n/2, n/2) per axis (DFT order).
+ *   a_k, b_k: Box-Muller normals from the first two words of the Philox4x32-10 block with
+ *   counter (k_y n + k_x, 0, stream_id low, stream_id high) and key (seed low, seed high),
+ *   u = ((w >> 8) + 1/2) 2^-24, a = sqrt(-2 ln u0) cos(2 pi u1), b = sqrt(-2 ln u0) sin(2 pi u1).
+ *   Radians at the wavelength r0 refers to.  n: a power of two in [16, 4096].  screen: device
+ *   [n][n] (written).  work: device, >= 2 n^2 + 2 n floats.  Asynchronous; deterministic.
+ *   No subharmonics: they would break the periodicity the layers' wrap-around relies on.
+ */
+int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_t seed,
+                    uint64_t stream_id, float* screen, float* work, int64_t work_floats,
+                    void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* wfs_last_error(void);
 

@@ -15,4 +15,4 @@ from ._lib import (  # noqa: F401
 )
 from .wfs import Plan, WFSFunction, recon_apply, tlse, wfs_slopes  # noqa: F401
 from . import calib  # noqa: F401
-from .psf import PsfPlan  # noqa: F401
+from .psf import PsfPlan, screen_generate  # noqa: F401

@@ -105,6 +105,8 @@ _PROTOS = {
     "psf_plan_destroy": (_c.c_int, [_P]),
     "psf_accumulate": (_c.c_int, [_P, _P, _c.c_int64, _P, _P, _P]),
     "psf_strehl": (_c.c_int, [_P, _P, _P, _c.c_int64, _P, _P, _P]),
+    "screen_generate": (_c.c_int, [_c.c_int32, _c.c_double, _c.c_double, _c.c_double,
+                                   _c.c_uint64, _c.c_uint64, _P, _P, _c.c_int64, _P]),
     "wfs_last_error": (_c.c_char_p, []),
 }
 

@@ -1,5 +1,6 @@
-"""Python front end of the PSF / Strehl module of libwfs (``psf_*`` in include/wfs.h).
-Argument marshalling only: the projection, fields, FFTs and sums run in the HIP kernels."""
+"""Python front end of the PSF / Strehl module and the phase-screen generator of libwfs
+(``psf_*``, ``screen_generate`` in include/wfs.h).  Argument marshalling only: the
+projection, fields, noise, filters, FFTs and sums run in the HIP kernels."""
 
 import ctypes
 
@@ -93,3 +94,18 @@ class PsfPlan:
                                      _ptr(b) if phase_var is not None else None,
                                      _stream(stream)), "psf_strehl")
         return a, b
+
+
+def screen_generate(n, pitch_m, r0_m, L0_m, seed, stream_id=0, out=None, stream=None):
+    """One periodic n x n von Karman phase screen on the GPU (``screen_generate``); returns a
+    float32 [n][n] tensor (radians at the wavelength r0 refers to)."""
+    n = int(n)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty(n, n, device=dev)
+    _need(out, "out", numel=n * n)
+    work = torch.empty(2 * n * n + 2 * n, device=dev)
+    L.check(L.lib().screen_generate(n, float(pitch_m), float(r0_m), float(L0_m), int(seed),
+                                    int(stream_id), _ptr(out), _ptr(work), work.numel(),
+                                    _stream(stream)), "screen_generate")
+    return out
