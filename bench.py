@@ -341,6 +341,33 @@ def bench_psf(torch, W, frames=20, lam=2.2e-6, N=2048):
                           "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM})
 
 
+def bench_screens(torch, W, reps=5):
+    """The ten 1024^2 von Karman layers of config 1 (0.04875 m pitch, r0 per layer, L0 25 m)
+    generated on the GPU straight into a layer buffer: one atmosphere = ten screen_generate
+    calls, captured in a HIP graph."""
+    cfg = synth.config1()
+    x = torch.zeros(cfg["layer_stride"], device="cuda")
+    turb = [(l, L) for l, L in enumerate(cfg["layers"]) if L["weight"] > 0]
+    views = [x[L["offset"]:L["offset"] + L["nx"] * L["ny"]].view(L["ny"], L["nx"])
+             for _, L in turb]
+
+    def atmosphere(i):
+        for (l, L), v in zip(turb, views):
+            W.screen_generate(L["nx"], L["pitch_m"], L["r0_m"], L["L0_m"], 1608 + i, l, out=v)
+
+    g = graph_of(torch, atmosphere, reps)
+    g.replay()
+    wall, gpu_ms = timed_replay(torch, g, reps)
+    n = turb[0][1]["nx"]
+    byts = len(turb) * (2 * n * n * 8 + n * n * 4)
+    return dict(workload="config1 atmosphere: %d von Karman screens %d^2, graph of %d "
+                         "atmospheres" % (len(turb), n, reps),
+                ms_per_atmosphere=gpu_ms, screens_per_s=len(turb) * 1e3 / gpu_ms,
+                roofline={"bound": "hbm", "algorithmic_bytes_per_atmosphere": byts,
+                          "achieved": byts / (gpu_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                          "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM})
+
+
 def bench_adjoint(torch, W, reps=20):
     cfg = synth.config3()
     x = torch.from_numpy(synth.make_batch(cfg, [cfg["guess_realisation"]])).cuda()
@@ -496,7 +523,7 @@ def main():
                          "schedule) and N plain copies of 256 MiB (the HBM counter "
                          "calibration), then exit")
     ap.add_argument("--only", choices=["psf", "calibration", "adjoint", "recon", "batched",
-                                       "closed_loop"],
+                                       "closed_loop", "screens"],
                     help="run one of the extra workloads alone and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -525,6 +552,7 @@ def main():
         return
     if args.only:  # one extra on its own (a short run for a profiler)
         fn = {"psf": bench_psf, "calibration": bench_calibration, "adjoint": bench_adjoint,
+              "screens": bench_screens,
               "recon": bench_recon, "batched": bench_batched,
               "closed_loop": bench_closed_loop}[args.only]
         print(json.dumps({args.only: fn(torch, W)}), flush=True)
@@ -644,6 +672,11 @@ def main():
             out["calibration"] = bench_calibration(torch, W)
         except Exception as e:
             out["calibration"] = {"error": repr(e)}
+        try:
+            log("[bench] screens ...")
+            out["screens"] = bench_screens(torch, W)
+        except Exception as e:
+            out["screens"] = {"error": repr(e)}
         try:
             log("[bench] PSF module ...")
             out["psf"] = bench_psf(torch, W)
