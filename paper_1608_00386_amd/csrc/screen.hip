@@ -124,7 +124,9 @@ int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_
     return scr_fail(WFS_EINVAL, "screen_generate: work must hold 2 n^2 + 2 n floats");
   int log2n = 0;
   while ((1 << log2n) < n) ++log2n;
-  const int cols = n >= 4096 ? 2 : std::min(16, kScrColPoints / n);
+  // columns per column-pass workgroup: enough workgroups to cover the 256 CUs (n / C >= 256
+  // where n allows), C (n + 1) + n points within the 160 KB of LDS
+  const int cols = n >= 4096 ? 2 : std::max(2, std::min(n / 256, kScrColPoints / n));
   hipError_t e;
   static std::once_flag lds_once;
   static hipError_t lds_err = hipSuccess;
