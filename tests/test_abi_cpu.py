@@ -156,3 +156,38 @@ def test_dm_calibration_config_keeps_actuator_order():
     assert any(s["photons"] > 0 for s in cfg["sensors"])  # the original is left alone
     with pytest.raises(ValueError):
         calib.dm_config(cfg, batch=3)
+
+
+def test_psf_and_screen_calls_reject_bad_arguments_without_a_device():
+    from paper_1608_00386_amd import _lib
+    L = _lib.lib()
+    c = ctypes
+    fake = c.c_void_p(4096)
+    ld = (_lib.LayerDesc * 1)(_lib.layer_desc(dict(offset=0, nx=64, ny=64, pitch_m=0.25,
+                                                   alt_m=0.0, vx_mps=0.0, vy_mps=0.0,
+                                                   weight=1.0, boundary=0)))
+    th = (c.c_double * 2)(0.0, 0.0)
+    lam = (c.c_double * 1)(1e-6)
+    h = c.c_void_p()
+
+    def plan(n_pup=32, nfft=64, stride=4096, D=8.0, obs=1.0, n_stars=1):
+        nf = (c.c_int32 * 1)(nfft)
+        return L.psf_plan(ld, 1, stride, th, n_stars, D, obs, n_pup, lam, nf, 1, 0.5e-6, 0.002,
+                          c.byref(h))
+
+    assert plan(nfft=48) == -1           # not a power of two
+    assert "power of two" in L.wfs_last_error().decode()
+    assert plan(nfft=16, n_pup=32) == -1  # smaller than the pupil
+    assert plan(nfft=8192) == -1
+    assert plan(stride=100) == -1         # layer outside the stride
+    assert plan(obs=9.0) == -1            # obstruction wider than the pupil
+    assert plan(n_stars=0) == -1
+    assert L.psf_accumulate(None, fake, 0, fake, None, None) == -1
+    assert L.psf_strehl(None, fake, None, 1, fake, None, None) == -1
+    assert L.psf_plan_destroy(None) == -1
+    W = 2 * 64 * 64 + 2 * 64
+    assert L.screen_generate(48, 0.1, 0.1, 25.0, 1, 0, fake, fake, W, None) == -1
+    assert L.screen_generate(64, 0.1, 0.1, 25.0, 1, 0, fake, fake, W - 1, None) == -1
+    assert "work" in L.wfs_last_error().decode()
+    assert L.screen_generate(64, -0.1, 0.1, 25.0, 1, 0, fake, fake, W, None) == -1
+    assert L.screen_generate(64, 0.1, 0.1, 25.0, 1, 0, None, fake, W, None) == -1
