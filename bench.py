@@ -19,6 +19,7 @@ import argparse
 import copy
 import glob
 import json
+import math
 import os
 import sys
 import time
@@ -331,6 +332,9 @@ def bench_psf(torch, W, frames=20, lam=2.2e-6, N=2048):
     # HBM bytes a two-pass transform cannot avoid: the row transforms written and read back
     # (n_pup x N complex per star) and the long-exposure image read and written (N^2 floats)
     byts = ns * (2 * n_pup * N * 8 + 2 * N * N * 4)
+    # FLOPs, FFT convention: 5 N log2 N per N-point transform (n_pup rows, N columns), and
+    # |F|^2, scale and accumulation (4 per image pixel)
+    flops = ns * ((n_pup + N) * 5 * N * math.log2(N) + 4 * N * N)
     return dict(workload="config4 layers + DMs, 9 test stars, 800^2 pupil padded to %d^2, "
                          "lambda %.2f um (pixel %.1f mas), graph of %d frames"
                          % (N, lam * 1e6, lam / (N * 39.0 / n_pup) / ARCSEC * 1e3, frames),
@@ -338,7 +342,10 @@ def bench_psf(torch, W, frames=20, lam=2.2e-6, N=2048):
                 star_psfs_per_s=ns * 1e3 / gpu_ms,
                 roofline={"bound": "hbm", "algorithmic_bytes_per_frame": byts,
                           "achieved": byts / (gpu_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
-                          "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM})
+                          "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM},
+                alu={"algorithmic_flop_per_frame": flops,
+                     "achieved": flops / (gpu_ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (gpu_ms * 1e-3) / PEAK_FP32_VALU})
 
 
 def bench_screens(torch, W, reps=5):
@@ -360,12 +367,16 @@ def bench_screens(torch, W, reps=5):
     wall, gpu_ms = timed_replay(torch, g, reps)
     n = turb[0][1]["nx"]
     byts = len(turb) * (2 * n * n * 8 + n * n * 4)
+    flops = len(turb) * (2 * n * 5 * n * math.log2(n) + 10 * n * n)  # transforms + filter
     return dict(workload="config1 atmosphere: %d von Karman screens %d^2, graph of %d "
                          "atmospheres" % (len(turb), n, reps),
                 ms_per_atmosphere=gpu_ms, screens_per_s=len(turb) * 1e3 / gpu_ms,
                 roofline={"bound": "hbm", "algorithmic_bytes_per_atmosphere": byts,
                           "achieved": byts / (gpu_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
-                          "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM})
+                          "unit": "GB/s", "frac": byts / (gpu_ms * 1e-3) / PEAK_HBM},
+                alu={"algorithmic_flop_per_atmosphere": flops,
+                     "achieved": flops / (gpu_ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / (gpu_ms * 1e-3) / PEAK_FP32_VALU})
 
 
 def bench_adjoint(torch, W, reps=20):
