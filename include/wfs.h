@@ -60,7 +60,7 @@ enum {
                                            (same bits as the footprint field)             */
 #define WFS_FLAG_FOOTPRINT (1u << 6)    /* staged footprint for single frames too (one launch
                                            per wfs_forward); ignored where a sensor cannot
-                                           stage its footprint                            */
+                                           stage its footprint or runs the FFT path       */
 
 /* `step` value meaning "read the step from the plan's device-resident counter". */
 #define WFS_STEP_DEVICE (-1)
@@ -171,9 +171,11 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
  *   (split), 2 = each wave stages its subaperture's layer footprint in LDS and projects it
  *   itself (one launch, no phase buffer).  frames: how wfs_forward_steps runs, 0 = one
  *   wfs_forward per frame, 1 = pipelined split frames, 2 = one footprint launch for all
- *   frames.  Fields 1 and 2 and frames 0-2 give the same bits; field 0 its own.  xcd_remap = 1
- *   when blocks are renumbered so neighbouring tasks share an XCD.  Any output pointer may be
- *   NULL.
+ *   frames (FFT-path sensors, which read the projected phase, then run frame by frame on
+ *   the plan's second stream beside it).  Fields 1 and 2 and frames 0-2 give the same bits;
+ *   field 0 its own.  Field 2 for single frames needs a plan without FFT-path sensors.
+ *   xcd_remap = 1 when blocks are renumbered so neighbouring tasks share an XCD.  Any output
+ *   pointer may be NULL.
  */
 int wfs_plan_schedule(wfs_plan_t plan, int32_t* field, int32_t* frames, int32_t* xcd_remap);
 

@@ -514,9 +514,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       } else {
         foot_ok = false;
       }
-    } else {
-      foot_ok = false;  // the FFT path reads the projected phase
-    }
+    }  // FFT-path sensors stage no footprint: they read the projected phase
   }
   P->hsen = ds;
   P->n_slopes = slope_off;
@@ -638,7 +636,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   P->lds_foot = otf_ns ? std::max(16, (otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, false,
                                                      foot_max_floats) + 15) & ~15)
                        : 0;
-  P->foot_ok = otf_ns && foot_ok && fft_ids.empty() && P->lds_foot * kWavesPerBlock <= 65536;
+  P->foot_ok = otf_ns && foot_ok && P->lds_foot * kWavesPerBlock <= 65536;
   P->lds_fused_otf = wave_lds(true, false);
   P->lds_split_otf = wave_lds(false, false);
   b.lds_per_wave = P->lds_split;
@@ -664,7 +662,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   if (flags & (WFS_FLAG_SPLIT | WFS_FLAG_FUSED)) P->foot_ok = 0;
   // single frames: the projection kernel first (one footprint launch per frame exposes the
   // window loads of every wave at once); frames in a row: one footprint launch
-  P->foot = (P->foot_ok && (flags & WFS_FLAG_FOOTPRINT)) ? 1 : 0;
+  P->foot = (P->foot_ok && P->fft_tasks == 0 && (flags & WFS_FLAG_FOOTPRINT)) ? 1 : 0;
   P->frames = P->foot_ok ? 2 : (P->split && P->d_phase ? 1 : 0);
   if (P->proj_lds_fft > 65536) {
     (void)hipFree(P->d_blob);
@@ -811,7 +809,36 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
     p.n_frames = n;
     p.lds_per_wave = P->lds_foot;
     p.lds_per_wave_otf = P->lds_foot;
-    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
+    if (p.fft_blocks == 0) return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
+    // FFT-path sensors read the projected phase: frame by frame on the side stream (their
+    // projection into the plan's phase buffer, then their launch), concurrently with the one
+    // footprint launch of every lag-domain frame on st
+    hipStream_t fs = P->side.stream ? P->side.stream : st;
+    if (fs != st) {
+      e = hipEventRecord(P->side.fork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(fs, P->side.fork, 0);
+    }
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+      FwdParams a = frame(k);
+      set_proj(a, P->proj_fft);
+      e = launch_project(a, P->d_phase, P->proj_lds_fft, fs);
+      if (e != hipSuccess) break;
+      a.phase_in = P->d_phase;
+      a.otf_from_phase = 1;
+      a.otf_blocks = 0;
+      a.proj_blocks = 0;
+      a.lds_per_wave = P->lds_split;
+      e = launch_forward(a, P->otf_ns ? P->otf_ns : 2, fs, nullptr);
+    }
+    if (e == hipSuccess) {
+      p.fft_blocks = 0;
+      e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, nullptr);
+    }
+    if (e == hipSuccess && fs != st) {
+      e = hipEventRecord(P->side.join, fs);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, P->side.join, 0);
+    }
+    return e;
   }
   if (!pipelined) {
     for (int k = 0; k < n && e == hipSuccess; ++k) e = launch_fwd_modes(P, frame(k), st);
@@ -1057,10 +1084,12 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   for (int mode = 0; mode < 6; ++mode) {
     const int remap = mode & 1, field = mode >> 1;
     if (field == 1 && (!P->d_phase || P->proj_lds > 65536)) continue;
-    if (field == 2 && !P->foot_ok) continue;
+    // single frames take the footprint field only without FFT-path sensors
+    const bool foot1 = P->foot_ok && P->fft_tasks == 0;
+    if (field == 2 && !foot1) continue;
     if ((P->flags & WFS_FLAG_FUSED) && field != 0) continue;
     if ((P->flags & WFS_FLAG_SPLIT) && field != 1) continue;
-    if ((P->flags & WFS_FLAG_FOOTPRINT) && P->foot_ok && field != 2) continue;
+    if ((P->flags & WFS_FLAG_FOOTPRINT) && foot1 && field != 2) continue;
     P->split = field == 1;
     P->foot = field == 2;
     FwdParams c = keep;

@@ -238,7 +238,7 @@ def test_forward_steps_after_tune_config2_equals_single_frames():
     xt = torch.from_numpy(x).cuda()
     plan.tune(xt, iters=2)
     sch = plan.schedule()
-    assert sch["field"] != "footprint" and sch["frames"] != "one_launch"  # FFT-path NGS
+    assert sch["field"] != "footprint"  # single frames: FFT-path NGS read the projected phase
     assert sch["field"] == "split" or sch["frames"] == "sequential"
     s, a = plan.forward_steps(xt, 11, 3)
     for k in range(3):
@@ -333,3 +333,19 @@ def test_side_stream_graph_replays_match_eager():
         assert torch.equal(out, ref) and torch.equal(out2, ref), rep
         plan.forward(xt, step=11, seed=1)  # eager work between the replays
         torch.cuda.synchronize()
+
+
+def test_mixed_plan_frames_in_one_footprint_launch_equal_single_frames():
+    """Config 2 untuned: the lag-domain LGS frames run as one staged-footprint launch while the
+    FFT-path NGS run frame by frame on the side stream; every frame equals the single-frame
+    call bit for bit, and the steps cross a device-step graph replay as well."""
+    torch, W = _gpu()
+    cfg = synth.config2(batch=2)
+    x = synth.make_batch(cfg, range(2))
+    plan = W.Plan(cfg, batch=2)
+    assert plan.schedule()["frames"] == "one_launch"
+    xt = torch.from_numpy(x).cuda()
+    s, a = plan.forward_steps(xt, 5, 4)
+    for k in range(4):
+        s1, a1 = plan.forward(xt, step=5 + k)
+        assert torch.equal(s[k], s1) and torch.equal(a[k], a1), k
