@@ -60,7 +60,8 @@ enum {
                                            (same bits as the footprint field)             */
 #define WFS_FLAG_FOOTPRINT (1u << 6)    /* staged footprint for single frames too (one launch
                                            per wfs_forward); ignored where a sensor cannot
-                                           stage its footprint or runs the FFT path       */
+                                           stage its footprint; with FFT-path sensors only
+                                           frames in a row take it (wfs_forward_steps)    */
 
 /* `step` value meaning "read the step from the plan's device-resident counter". */
 #define WFS_STEP_DEVICE (-1)

@@ -335,15 +335,18 @@ def test_side_stream_graph_replays_match_eager():
         torch.cuda.synchronize()
 
 
-def test_mixed_plan_frames_in_one_footprint_launch_equal_single_frames():
-    """Config 2 untuned: the lag-domain LGS frames run as one staged-footprint launch while the
-    FFT-path NGS run frame by frame on the side stream; every frame equals the single-frame
-    call bit for bit, and the steps cross a device-step graph replay as well."""
+@pytest.mark.parametrize("flags", ["footprint", "default"])
+def test_mixed_plan_frames_in_one_footprint_launch_equal_single_frames(flags):
+    """Config 2 with WFS_FLAG_FOOTPRINT: the lag-domain LGS frames run as one staged-footprint
+    launch while the FFT-path NGS run frame by frame on the side stream; every frame equals
+    the single-frame call bit for bit.  Without the flag such a plan keeps split frames."""
     torch, W = _gpu()
     cfg = synth.config2(batch=2)
     x = synth.make_batch(cfg, range(2))
-    plan = W.Plan(cfg, batch=2)
-    assert plan.schedule()["frames"] == "one_launch"
+    plan = W.Plan(cfg, batch=2, flags=W.WFS_FLAG_FOOTPRINT if flags == "footprint" else 0)
+    sch = plan.schedule()
+    assert sch["field"] == "split"
+    assert sch["frames"] == ("one_launch" if flags == "footprint" else "pipelined")
     xt = torch.from_numpy(x).cuda()
     s, a = plan.forward_steps(xt, 5, 4)
     for k in range(4):
