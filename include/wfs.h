@@ -324,7 +324,7 @@ int psf_strehl(psf_plan_t plan, const float* psf, const double* phase_var, int64
  *   counter (k_y n + k_x, 0, stream_id low, stream_id high) and key (seed low, seed high),
  *   u = ((w >> 8) + 1/2) 2^-24, a = sqrt(-2 ln u0) cos(2 pi u1), b = sqrt(-2 ln u0) sin(2 pi u1).
  *   Radians at the wavelength r0 refers to.  n: a power of two in [16, 4096].  screen: device
- *   [n][n] (written).  work: device, >= 2 n^2 + 2 n floats.  Asynchronous; deterministic.
+ *   [n][n] (written).  work: device, >= 2 n^2 floats.  Asynchronous; deterministic.
  *   No subharmonics: they would break the periodicity the layers' wrap-around relies on.
  */
 int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_t seed,

@@ -9,7 +9,8 @@
 // the seed, one block per Fourier sample (counter: sample index, stream id), Box-Muller on its
 // first two words.  The unnormalised inverse DFT is the forward one of the conjugate; it runs
 // as the PSF module's two passes: rows (noise, filter and an n-point FFT in LDS, written in
-// C-column tiles) and columns (FFT in LDS, real part out).
+// C-column tiles) and columns (FFT in LDS, real part out); each workgroup forms its own
+// twiddles in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +32,6 @@ constexpr int kScrColBlock = 1024;
 struct ScreenParams {
   float2* T;            // [n / C][n][C] row transforms
   float* out;           // [n][n]
-  const float2* tw;     // exp(-2 pi i m / n)
   int32_t n, log2n, cols;
   float c_psd;          // 0.023 r0^(-5/3)
   float inv_l02;        // L0^-2 (0: Kolmogorov)
@@ -39,13 +39,12 @@ struct ScreenParams {
   uint32_t seed_lo, seed_hi, sid_lo, sid_hi;
 };
 
-// exp(-2 pi i m / n), m < n, in double precision (rounded once to float).
-__global__ __launch_bounds__(kScrBlock) void screen_twiddle_kernel(float2* tw, int n) {
-  const int m = blockIdx.x * kScrBlock + threadIdx.x;
-  if (m < n) {
-    double sn, cs;
-    sincospi(-2.0 * (double)m / (double)n, &sn, &cs);
-    tw[m] = make_float2((float)cs, (float)sn);
+// exp(-2 pi i m / n) for m < n into LDS (FP32 sincospi: about one ulp).
+__device__ __forceinline__ void screen_twiddles(float2* tws, int n, int nthreads) {
+  for (int m = threadIdx.x; m < n; m += nthreads) {
+    float sn, cs;
+    sincospif(-2.0f * (float)m / (float)n, &sn, &cs);
+    tws[m] = make_float2(cs, sn);
   }
 }
 
@@ -72,8 +71,10 @@ __global__ __launch_bounds__(kScrBlock) void screen_rows_kernel(ScreenParams p) 
     // conjugate spectrum: the forward transform of conj(S) is conj of the inverse of S
     sh[kx] = make_float2(r * cs * amp, -(r * sn * amp));
   }
+  float2* tws = sh + n;  // the twiddles, after the row
+  screen_twiddles(tws, n, kScrBlock);
   __syncthreads();
-  lds_fft<kScrMaxN, kScrBlock>(sh, 1, n, n, p.log2n, p.tw);
+  lds_fft<kScrMaxN, kScrBlock>(sh, 1, n, n, p.log2n, tws);
   float2* o = p.T + (int64_t)ky * C;
   for (int x = tid; x < n; x += kScrBlock) {
     const int kt = x / C;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(kScrColBlock) void screen_cols_kernel(ScreenParams 
     const int c = i & (C - 1), y = i / C;
     sh[c * ld + y] = src[i];
   }
-  for (int i = tid; i < n; i += kScrColBlock) tws[i] = p.tw[i];
+  screen_twiddles(tws, n, kScrColBlock);
   __syncthreads();
   lds_fft<kScrColPoints, kScrColBlock>(sh, C, ld, n, p.log2n, tws);
   for (int i = tid; i < C * n; i += kScrColBlock) {
@@ -120,8 +121,8 @@ int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_
   if (!(pitch_m > 0) || !std::isfinite(pitch_m) || !(r0_m > 0) || !std::isfinite(r0_m) ||
       !(L0_m > 0))
     return scr_fail(WFS_EINVAL, "screen_generate: pitch, r0 and L0 must be > 0");
-  if (work_floats < 2 * (int64_t)n * n + 2 * (int64_t)n)
-    return scr_fail(WFS_EINVAL, "screen_generate: work must hold 2 n^2 + 2 n floats");
+  if (work_floats < 2 * (int64_t)n * n)
+    return scr_fail(WFS_EINVAL, "screen_generate: work must hold 2 n^2 floats");
   int log2n = 0;
   while ((1 << log2n) < n) ++log2n;
   // columns per column-pass workgroup: enough workgroups to cover the 256 CUs (n / C >= 256
@@ -136,13 +137,9 @@ int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_
   });
   if (lds_err != hipSuccess) return scr_fail(WFS_EDEVICE, hipGetErrorString(lds_err));
   hipStream_t st = (hipStream_t)stream;
-  float2* tw = reinterpret_cast<float2*>(work) + (int64_t)n * n;  // after the row transforms
-  screen_twiddle_kernel<<<(n + kScrBlock - 1) / kScrBlock, kScrBlock, 0, st>>>(tw, n);
-  if ((e = hipGetLastError()) != hipSuccess) return scr_fail(WFS_EDEVICE, hipGetErrorString(e));
   ScreenParams p{};
   p.T = reinterpret_cast<float2*>(work);
   p.out = screen;
-  p.tw = tw;
   p.n = n;
   p.log2n = log2n;
   p.cols = cols;
@@ -153,7 +150,7 @@ int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_
   p.seed_hi = (uint32_t)(seed >> 32);
   p.sid_lo = (uint32_t)stream_id;
   p.sid_hi = (uint32_t)(stream_id >> 32);
-  screen_rows_kernel<<<n, kScrBlock, (size_t)n * sizeof(float2), st>>>(p);
+  screen_rows_kernel<<<n, kScrBlock, 2 * (size_t)n * sizeof(float2), st>>>(p);
   if ((e = hipGetLastError()) != hipSuccess) return scr_fail(WFS_EDEVICE, hipGetErrorString(e));
   const size_t lds = ((size_t)cols * (n + 1) + n) * sizeof(float2);
   screen_cols_kernel<<<n / cols, kScrColBlock, lds, st>>>(p);

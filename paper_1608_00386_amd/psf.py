@@ -104,7 +104,7 @@ def screen_generate(n, pitch_m, r0_m, L0_m, seed, stream_id=0, out=None, stream=
     if out is None:
         out = torch.empty(n, n, device=dev)
     _need(out, "out", numel=n * n)
-    work = torch.empty(2 * n * n + 2 * n, device=dev)
+    work = torch.empty(2 * n * n, device=dev)
     L.check(L.lib().screen_generate(n, float(pitch_m), float(r0_m), float(L0_m), int(seed),
                                     int(stream_id), _ptr(out), _ptr(work), work.numel(),
                                     _stream(stream)), "screen_generate")

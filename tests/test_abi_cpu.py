@@ -185,7 +185,7 @@ def test_psf_and_screen_calls_reject_bad_arguments_without_a_device():
     assert L.psf_accumulate(None, fake, 0, fake, None, None) == -1
     assert L.psf_strehl(None, fake, None, 1, fake, None, None) == -1
     assert L.psf_plan_destroy(None) == -1
-    W = 2 * 64 * 64 + 2 * 64
+    W = 2 * 64 * 64
     assert L.screen_generate(48, 0.1, 0.1, 25.0, 1, 0, fake, fake, W, None) == -1
     assert L.screen_generate(64, 0.1, 0.1, 25.0, 1, 0, fake, fake, W - 1, None) == -1
     assert "work" in L.wfs_last_error().decode()
