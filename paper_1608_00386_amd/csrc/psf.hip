@@ -95,23 +95,48 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
   }
   __syncthreads();
   double s1 = 0.0, s2 = 0.0;
-  for (int x = tid; x < N; x += kPsfBlock) {
-    float2 e = make_float2(0.0f, 0.0f);
-    if (x < n && p.mask[(int64_t)y * n + x]) {
-      float phi = 0.0f;
-      for (int l = 0; l < p.n_layers; ++l) {
-        const RowLayer& r = rl[l];
-        const Tap cx = make_tap(fma(r.a, (double)x, r.b), r.n, r.inv_n, r.boundary, 1);
-        const Tap ry{r.r0, r.r1, r.w0, r.w1};
-        phi = fmaf(r.weight, bilinear(p.layers + r.offset, cx, ry), phi);
-      }
-      s1 += (double)phi;
-      s2 += (double)phi * (double)phi;
-      float sn, cs;
-      sincosf(p.kappa * phi, &sn, &cs);
-      e = make_float2(cs, sn);
+  // pupil pixels in blocks of kPix per thread: layers outer, pixels inner, so each layer's
+  // parameters are read once per block and its 4 kPix taps load back to back
+  constexpr int kPix = 4;
+  for (int x0 = 0; x0 < n; x0 += kPix * kPsfBlock) {
+    float phi[kPix];
+    bool lit[kPix];
+#pragma unroll
+    for (int j = 0; j < kPix; ++j) {
+      const int x = x0 + tid + j * kPsfBlock;
+      lit[j] = x < n && p.mask[(int64_t)y * n + x];
+      phi[j] = 0.0f;
     }
-    sh[x] = e;
+    for (int l = 0; l < p.n_layers; ++l) {
+      const RowLayer r = rl[l];
+      const Tap ry{r.r0, r.r1, r.w0, r.w1};
+      const float* g = p.layers + r.offset;
+#pragma unroll
+      for (int j = 0; j < kPix; ++j) {
+        if (lit[j]) {
+          const int x = x0 + tid + j * kPsfBlock;
+          const Tap cx = make_tap(fma(r.a, (double)x, r.b), r.n, r.inv_n, r.boundary, 1);
+          phi[j] = fmaf(r.weight, bilinear(g, cx, ry), phi[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPix; ++j) {
+      const int x = x0 + tid + j * kPsfBlock;
+      float2 e = make_float2(0.0f, 0.0f);
+      if (lit[j]) {
+        s1 += (double)phi[j];
+        s2 += (double)phi[j] * (double)phi[j];
+        float sn, cs;
+        sincosf(p.kappa * phi[j], &sn, &cs);
+        e = make_float2(cs, sn);
+      }
+      if (x < N) sh[x] = e;
+    }
+  }
+  for (int x = n + tid; x < N; x += kPsfBlock) {  // zero padding beyond the pupil
+    if (x >= ((n + kPix * kPsfBlock - 1) / (kPix * kPsfBlock)) * kPix * kPsfBlock)
+      sh[x] = make_float2(0.0f, 0.0f);
   }
   if (p.write_part) {  // fixed-order tree: deterministic row sums
     red[0][tid] = s1;
