@@ -664,9 +664,9 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   // window loads of every wave at once); frames in a row: one footprint launch
   P->foot = (P->foot_ok && P->fft_tasks == 0 && (flags & WFS_FLAG_FOOTPRINT)) ? 1 : 0;
   // with FFT-path sensors their per-frame chain on the side stream can outlast the one
-  // footprint launch (config 2 at 8 realisations: 0.81 against 0.57 ms per frame), so such
-  // plans take it by default only when asked (WFS_FLAG_FOOTPRINT) or when the tuner finds it
-  // faster
+  // footprint launch (six 80 x 80 LGS and three 2 x 2 NGS at 8 realisations: 0.81 against
+  // 0.57 ms per frame), so such plans take it by default only when asked
+  // (WFS_FLAG_FOOTPRINT) or when the tuner finds it faster
   P->frames = (P->foot_ok && (P->fft_tasks == 0 || (flags & WFS_FLAG_FOOTPRINT)))
                   ? 2
                   : (P->split && P->d_phase ? 1 : 0);
