@@ -305,6 +305,63 @@ def test_elongation_geometry():
             assert abs(K[i, 1, 0] - 1.0) < 1e-14
 
 
+def test_subap_centres_hand_computed():
+    """8 x 8 subapertures of 1 m (8 m pupil, 4 px each): the centre of subaperture (row a,
+    column b) is x = b + 1/2 - 4, y = a + 1/2 - 4 metres, worked out by hand for five named
+    subapertures (x follows the column, y the row; a swapped axis or a half-subaperture shift
+    changes at least one of them)."""
+    sensor = _ngs(8, 4, 16, 2, D=8.0)
+    geo = oracle.pupil_geometry(sensor)
+    c = oracle.subap_centres(sensor, geo)
+    where = {(int(a), int(b)): i for i, (a, b) in enumerate(geo["valid"])}
+    expect = {(3, 7): (3.5, -0.5), (0, 3): (-0.5, -3.5), (7, 4): (0.5, 3.5),
+              (4, 0): (-3.5, 0.5), (0, 2): (-1.5, -3.5)}
+    for ab, xy in expect.items():
+        assert ab in where, ab
+        np.testing.assert_allclose(c[where[ab]], xy, atol=1e-14)
+    # the corner subapertures lie outside the 8 m circle: not valid
+    assert (0, 0) not in where and (7, 7) not in where
+
+
+def _spot_variances(sensor):
+    """x and y second moments (FFT pixels^2) of the elongated, fftshifted spot of a flat
+    wavefront, per valid subaperture."""
+    cfg = _sys(sensor, [_layer(64, 0.25)])
+    tr = {}
+    oracle.sensor_slopes(np.zeros(cfg["layer_stride"]), cfg, 0, 0, 0, 0, noise=False, trace=tr)
+    S = np.fft.fftshift(tr["I_e"], axes=(1, 2))
+    N = S.shape[1]
+    x = np.arange(N) - (N - 1) / 2.0
+    tot = S.sum(axis=(1, 2))
+    vx = (S * x[None, None, :] ** 2).sum(axis=(1, 2)) / tot
+    vy = (S * x[None, :, None] ** 2).sum(axis=(1, 2)) / tot
+    where = {(int(a), int(b)): i for i, (a, b) in enumerate(tr["geo"]["valid"])}
+    return where, vx, vy
+
+
+def test_elongation_follows_the_launch_baseline():
+    """Sodium elongation stretches each spot along the line from the launch position to the
+    subaperture (Sec. 2.7 sodium layer, centre-launch reading).  With the launch at the pupil
+    centre a subaperture on the +x side of the pupil has the larger x variance and one on the
+    +y side the larger y variance; moving the launch onto a subaperture removes its
+    elongation (equal variances: the flat spot of a fully lit square subaperture is
+    symmetric) and turns its neighbour one row down (+y) into a y-elongated spot."""
+    sensor = _lgs(8, 4, 32, 4, D=8.0, fwhm=3e3)
+    where, vx, vy = _spot_variances(sensor)
+    for ab in ((3, 7), (4, 7), (3, 0)):      # on the x axis: elongated along x
+        i = where[ab]
+        assert vx[i] > 2.0 * vy[i], (ab, vx[i], vy[i])
+    for ab in ((0, 3), (7, 4)):              # on the y axis: elongated along y
+        i = where[ab]
+        assert vy[i] > 2.0 * vx[i], (ab, vx[i], vy[i])
+    sensor = dict(sensor, launch_x_m=3.5, launch_y_m=-0.5)  # launch at subaperture (3, 7)
+    where, vx, vy = _spot_variances(sensor)
+    i = where[(3, 7)]
+    assert abs(vx[i] - vy[i]) < 1e-9 * vx[i]
+    i = where[(4, 7)]                         # baseline (0, +1 m)
+    assert vy[i] > vx[i] + 1.0 and abs(vx[i] - vx[where[(3, 7)]]) < 1e-9 * vx[i]
+
+
 # ------------------------------------------------------------------------------------------
 # Projection geometry
 # ------------------------------------------------------------------------------------------
