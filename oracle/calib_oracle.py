@@ -21,10 +21,12 @@ from .wfs_oracle import forward
 def interaction_matrix(cfg, act_offset, n_act, amplitude, batch, step=0, seed=42, noise=False,
                        base=None):
     """Rows j = (s(base + a e_j) - s(base - a e_j)) / (2 a), j < n_act, where e_j is element
-    act_offset + j of one realisation's layer buffer.  The realisation and step numbering of a
-    batched calibration with ``batch`` realisations per call is kept (actuator j = c h + r,
-    h = batch / 2: push in realisation r, pull in realisation h + r, both at step + c), so
-    noisy calibrations draw the same noise as that schedule."""
+    act_offset + j of one realisation's layer buffer.  Every row is taken about the same
+    operating point: the layers (a base screen with wind included) are sampled at time step
+    ``step`` for every actuator.  The realisation and noise numbering of a batched
+    calibration with ``batch`` realisations per call is kept (actuator j = c h + r,
+    h = batch / 2: push in realisation r, pull in realisation h + r, noise drawn with step
+    counter step + c), so noisy calibrations draw the same noise as that schedule."""
     stride = int(cfg["layer_stride"])
     x0 = np.zeros(stride) if base is None else np.asarray(base, dtype=np.float64).copy()
     h = batch // 2
@@ -35,8 +37,9 @@ def interaction_matrix(cfg, act_offset, n_act, amplitude, batch, step=0, seed=42
         xp[act_offset + j] += amplitude
         xm = x0.copy()
         xm[act_offset + j] -= amplitude
-        sp, _ = forward(xp[None], cfg, step + c, seed, noise, realisations=[r])
-        sm, _ = forward(xm[None], cfg, step + c, seed, noise, realisations=[h + r])
+        sp, _ = forward(xp[None], cfg, step, seed, noise, realisations=[r], noise_step=step + c)
+        sm, _ = forward(xm[None], cfg, step, seed, noise, realisations=[h + r],
+                        noise_step=step + c)
         rows.append((sp[0] - sm[0]) / (2.0 * amplitude))
     return np.array(rows)
 

@@ -278,8 +278,11 @@ def centroid(B):
     return cx, cy, S
 
 
-def sensor_slopes(layer_buf, cfg, s_idx, step, seed, realisation, noise=True, trace=None):
-    """Slopes of one sensor for one realisation: [c_x over valid subaps || c_y], and sum B'."""
+def sensor_slopes(layer_buf, cfg, s_idx, step, seed, realisation, noise=True, trace=None,
+                  noise_step=None):
+    """Slopes of one sensor for one realisation: [c_x over valid subaps || c_y], and sum B'.
+    The noise is drawn with the step counter ``noise_step`` (default: ``step``, the frame's
+    own time step)."""
     sensor = cfg["sensors"][s_idx]
     geo = pupil_geometry(sensor)
     psi = project(layer_buf, cfg, sensor, step)
@@ -289,16 +292,18 @@ def sensor_slopes(layer_buf, cfg, s_idx, step, seed, realisation, noise=True, tr
     I_e = elongate(I, K)
     B = bin_spots(I_e, int(sensor["bin"]))
     if noise:
-        B = add_noise(B, sensor, realisation, s_idx, step, seed)
+        B = add_noise(B, sensor, realisation, s_idx, step if noise_step is None else noise_step,
+                      seed)
     cx, cy, S = centroid(B)
     if trace is not None:
         trace.update(psi=psi, E=E, F=F, I=I, K=K, I_e=I_e, B=B, geo=geo)
     return np.concatenate([cx, cy]), S
 
 
-def forward(layers, cfg, step, seed=42, noise=True, realisations=None):
+def forward(layers, cfg, step, seed=42, noise=True, realisations=None, noise_step=None):
     """Slopes [B][N_s] and sum-of-pixels aux [B][n_valid_total] of every sensor, sensors in
-    plan order, realisation-major.  ``layers`` is [B][layer_stride]."""
+    plan order, realisation-major.  ``layers`` is [B][layer_stride].  ``noise_step``: step
+    counter of the noise draws when it differs from the frame's time step."""
     layers = np.atleast_2d(np.asarray(layers, dtype=np.float64))
     if realisations is None:
         realisations = range(layers.shape[0])
@@ -306,7 +311,8 @@ def forward(layers, cfg, step, seed=42, noise=True, realisations=None):
     for bi, r in enumerate(realisations):
         s_r, a_r = [], []
         for s_idx in range(len(cfg["sensors"])):
-            s, S = sensor_slopes(layers[bi], cfg, s_idx, step, seed, r, noise)
+            s, S = sensor_slopes(layers[bi], cfg, s_idx, step, seed, r, noise,
+                                 noise_step=noise_step)
             s_r.append(s)
             a_r.append(S)
         slopes.append(np.concatenate(s_r))
@@ -379,12 +385,13 @@ def recon(R, S):
     return S @ R.T
 
 
-def closed_loop_step(layers, cfg, R, step, seed=42, noise=True):
+def closed_loop_step(layers, cfg, R, step, seed=42, noise=True, realisations=None):
     """One integrator step: slopes of the residual phase (DM grids enter the projection with
     weight -1), C = R s, and the DM actuators a <- a + g C (rows beyond the actuator count are
-    computed and dropped).  Returns (new layers, slopes)."""
+    computed and dropped).  ``realisations`` numbers the rows of ``layers`` for the noise
+    (default 0 .. B-1).  Returns (new layers, slopes)."""
     layers = np.atleast_2d(np.asarray(layers, dtype=np.float64)).copy()
-    s, _ = forward(layers, cfg, step, seed, noise)
+    s, _ = forward(layers, cfg, step, seed, noise, realisations=realisations)
     C = recon(R, s)
     n_act = sum(L["nx"] * L["ny"] for L in cfg["layers"] if L["weight"] < 0)
     o = cfg["dm_offset"]

@@ -25,14 +25,15 @@ def _lgs(n_sa, n_sub, N, b, D, obs=0.0, tx=0.0, ty=0.0):
     return s
 
 
-def _system(turbulence=False):
+def _system(turbulence=False, wind=(0.0, 0.0)):
     """An NGS and an off-axis LGS (8 m pupil, 4 x 4 subapertures of 4 x 4 pixels) seeing a 7 x 7
     zero-boundary DM grid of pitch 2 m at the pupil (wider than the pupil: its corner actuators
-    lie outside every beam), and optionally a periodic turbulence screen at 3 km."""
+    lie outside every beam), and optionally a periodic turbulence screen at 3 km moving with
+    the wind (vx, vy) in m/s."""
     layers = []
     if turbulence:
-        layers.append(dict(nx=48, ny=48, pitch_m=0.5, alt_m=3000.0, vx_mps=0.0, vy_mps=0.0,
-                           weight=1.0, boundary=0))
+        layers.append(dict(nx=48, ny=48, pitch_m=0.5, alt_m=3000.0, vx_mps=wind[0],
+                           vy_mps=wind[1], weight=1.0, boundary=0))
     layers.append(dict(nx=7, ny=7, pitch_m=2.0, alt_m=0.0, vx_mps=0.0, vy_mps=0.0,
                        weight=-1.0, boundary=1))
     sensors = [_ngs(4, 4, 8, 2, D=8.0, obs=1.0),
@@ -151,3 +152,26 @@ def test_closed_loop_with_the_calibrated_reconstructor_converges():
     fit = s0[0] - im.T @ (R @ s0[0])
     assert np.linalg.norm(s_end) < 0.5 * np.linalg.norm(s0)
     assert abs(np.linalg.norm(s_end) - np.linalg.norm(fit)) <= 0.05 * np.linalg.norm(s0)
+
+
+def test_rows_share_one_operating_point_on_a_moving_screen():
+    """Sec. 2.5: the modes are pushed through the system at one operating point.  On a base
+    screen that moves with the wind, every row is taken with the screen at the calibration's
+    time step, whichever call of the batched schedule holds the actuator: the matrix does not
+    depend on the number of actuators per call, and equals the adjoint linearisation at that
+    step."""
+    cfg, a0, n_act = _system(turbulence=True, wind=(35.0, -20.0))
+    base = np.random.default_rng(3).standard_normal(cfg["layer_stride"]) * 0.3
+    base[a0:] = 0.0
+    step = 5
+    im2 = oracle.interaction_matrix(cfg, a0, n_act, 1e-4, batch=2, step=step, base=base)
+    im_all = oracle.interaction_matrix(cfg, a0, n_act, 1e-4, batch=2 * n_act, step=step,
+                                       base=base)
+    np.testing.assert_array_equal(im2, im_all)
+    g = np.random.default_rng(12).standard_normal((1, im2.shape[1]))
+    adj = oracle.adjoint(base[None], cfg, step, g)[0, a0:a0 + n_act]
+    np.testing.assert_allclose(im2 @ g[0], adj, rtol=0, atol=1e-6 * np.abs(adj).max())
+    # the screen does move between steps: another step gives other rows
+    j = 3 * 7 + 2  # an actuator near the centre, seen by both sensors
+    im_late = oracle.interaction_matrix(cfg, a0 + j, 1, 1e-4, batch=2, step=step + 3, base=base)
+    assert np.abs(im_late[0] - im2[j]).max() > 1e-3 * np.abs(im2[j]).max()
