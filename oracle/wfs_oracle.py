@@ -10,9 +10,12 @@ adaptive optics system") describes the chain in prose only:
   * Sec. 2.7  X/Y slopes computed by the wavefront-sensor modules from the residual phase
               (open loop minus DM), slopes times the control matrix giving differential
               coefficients added to the mirror, a pure integrator, the sodium layer;
-  * Sec. 1    six LGS feeding as many Shack-Hartmann sensors, three NGS.
+  * Sec. 1    six LGS feeding as many Shack-Hartmann sensors, three NGS;
+  * Sec. 2.3  extra aberrations, among them an extra tip and tilt per NGS sensor;
+  * Sec. 2.7  also the temporal evolution of the sodium layer.
 Everything inside the Shack-Hartmann model (pupil sampling rule, spot formation by a
-zero-padded FFT with a half-pixel centring ramp, Gaussian sodium elongation, binning, photon
+zero-padded FFT with a half-pixel centring ramp, Gaussian or multi-peak time-varying sodium
+elongation, per-sensor tip-tilt offsets, binning, photon
 and read noise, centre of gravity) is one reading of that prose; each function below states
 the reading it implements.  Arrays are row-major [y][x]; x runs along columns.
 
@@ -182,8 +185,22 @@ def spots(E, sensor):
     return F, I
 
 
-def elongation_kernel(sensor, geo):
-    """Gaussian sodium-profile transfer function per valid subaperture ([nv][N][N] real).
+def na_profile_at(cfg, step):
+    """Sodium profile of the frame at time step ``step``: entry step mod T of the plan's table
+    cfg["na_profile"] (T entries, each a list of peaks (dh, fwhm, weight)), or None when the
+    configuration has no table (each LGS then keeps its own single Gaussian).
+
+    Reading of "the sodium layer temporal evolution" (Sec. 2.7): the profile is a time series
+    sampled once per frame and repeated with period T; a peak dh metres above the LGS focus
+    altitude H, of width fwhm, carries the fraction weight / sum(weights) of the return."""
+    table = cfg.get("na_profile")
+    if not table:
+        return None
+    return table[int(step) % len(table)]
+
+
+def elongation_kernel(sensor, geo, profile=None):
+    """Sodium-profile transfer function per valid subaperture ([nv][N][N]).
 
     Reading of the paper's "sodium layer" (Sec. 2.7): a Gaussian profile of FWHM na_fwhm at
     the LGS altitude H seen from a subaperture at baseline b (centre minus launch position)
@@ -191,6 +208,13 @@ def elongation_kernel(sensor, geo):
     i.e. sigma_px = that / (lambda / (N dx)) FFT pixels.  Its transfer function is
     K[ky, kx] = exp(-2 pi^2 sigma_px^2 ((kx~ e_x + ky~ e_y) / N)^2), kx~ the signed frequency
     (k for k < N/2, k - N otherwise).  No elongation (K = 1) for NGS or na_fwhm = 0.
+
+    With a multi-peak ``profile`` (list of (dh, fwhm, weight), see na_profile_at) instead of
+    the sensor's single Gaussian: peak j is seen at the angle |b| dh_j / H^2 from the focus
+    along e (further from the launch for dh > 0) with the width |b| sigma_j / H^2, so
+    K = sum_j w_j exp(-2 pi^2 sigma_px,j^2 u^2) exp(-2 pi i mu_px,j u), u = (kx~ e_x +
+    ky~ e_y) / N, w_j the normalised weights and mu_px,j the shift in FFT pixels (complex,
+    Hermitian: the spot stays real and moves by mu along e).
     """
     N = int(sensor["n_fft"])
     nv = len(geo["valid"])
@@ -201,20 +225,45 @@ def elongation_kernel(sensor, geo):
     bx = c[:, 0] - sensor["launch_x_m"]
     by = c[:, 1] - sensor["launch_y_m"]
     blen = np.hypot(bx, by)
-    sig_h = sensor["na_fwhm_m"] * FWHM_TO_SIGMA
     p_fft = sensor["lambda_m"] / (N * geo["dx"])
-    sig_px = blen * sig_h / (H * H) / p_fft
     with np.errstate(invalid="ignore", divide="ignore"):
         ex = np.where(blen > 0, bx / blen, 0.0)
         ey = np.where(blen > 0, by / blen, 0.0)
     k = np.arange(N)
     ks = np.where(k < N // 2, k, k - N).astype(np.float64)
     proj = (ks[None, None, :] * ex[:, None, None] + ks[None, :, None] * ey[:, None, None]) / N
-    return np.exp(-2.0 * math.pi ** 2 * sig_px[:, None, None] ** 2 * proj ** 2)
+    if profile is None:
+        sig_h = sensor["na_fwhm_m"] * FWHM_TO_SIGMA
+        sig_px = blen * sig_h / (H * H) / p_fft
+        return np.exp(-2.0 * math.pi ** 2 * sig_px[:, None, None] ** 2 * proj ** 2)
+    w = np.array([float(pk[2]) for pk in profile])
+    w = w / w.sum()
+    K = np.zeros((nv, N, N), dtype=np.complex128)
+    for (dh, fwhm, _), wj in zip(profile, w):
+        sig_px = blen * (float(fwhm) * FWHM_TO_SIGMA) / (H * H) / p_fft
+        mu_px = blen * float(dh) / (H * H) / p_fft
+        K += wj * np.exp(-2.0 * math.pi ** 2 * sig_px[:, None, None] ** 2 * proj ** 2
+                         - 2j * math.pi * mu_px[:, None, None] * proj)
+    return K
+
+
+def tilt_phase(sensor, geo):
+    """Extra tip-tilt of one sensor, [n_pup][n_pup] radians at its wavelength.
+
+    Reading of the NGS WFS mispositioning modelled as an extra tip and tilt aberration
+    (Sec. 2.3): a sensor offset by the angles (tilt_x, tilt_y) on the sky sees the phase
+    2 pi (tilt_x x + tilt_y y) / lambda at the pupil coordinates (x, y) of its pixel centres,
+    added to the projected phase (zero when the sensor has no such keys)."""
+    tx = float(sensor.get("tilt_x_rad", 0.0))
+    ty = float(sensor.get("tilt_y_rad", 0.0))
+    n_pup, dx = geo["n_pup"], geo["dx"]
+    xc = (np.arange(n_pup) + 0.5 - n_pup / 2.0) * dx
+    return 2.0 * math.pi * (tx * xc[None, :] + ty * xc[:, None]) / float(sensor["lambda_m"])
 
 
 def elongate(I, K):
-    """Circular convolution with the sodium profile: I_e = Re IDFT2(DFT2(I) K)."""
+    """Circular convolution with the sodium profile: I_e = Re IDFT2(DFT2(I) K).  (With
+    conj(K) it is the adjoint map: the correlation with the same profile.)"""
     return np.real(np.fft.ifft2(np.fft.fft2(I, axes=(1, 2)) * K, axes=(1, 2)))
 
 
@@ -285,10 +334,10 @@ def sensor_slopes(layer_buf, cfg, s_idx, step, seed, realisation, noise=True, tr
     own time step)."""
     sensor = cfg["sensors"][s_idx]
     geo = pupil_geometry(sensor)
-    psi = project(layer_buf, cfg, sensor, step)
+    psi = project(layer_buf, cfg, sensor, step) + tilt_phase(sensor, geo)
     E = subap_fields(psi, geo, sensor)
     F, I = spots(E, sensor)
-    K = elongation_kernel(sensor, geo)
+    K = elongation_kernel(sensor, geo, na_profile_at(cfg, step))
     I_e = elongate(I, K)
     B = bin_spots(I_e, int(sensor["bin"]))
     if noise:
@@ -343,7 +392,7 @@ def _sensor_adjoint(layer_buf, cfg, s_idx, step, g_slopes, out):
     g_B *= ok[:, None, None]
     g_S = np.repeat(np.repeat(g_B, b, axis=1), b, axis=2)  # adjoint of the block sum
     g_Ie = np.fft.ifftshift(g_S, axes=(1, 2))  # adjoint of fftshift
-    g_I = elongate(g_Ie, K)  # K real and even: the convolution is self-adjoint
+    g_I = elongate(g_Ie, np.conj(K))  # adjoint of the convolution: the correlation
     c_I = flux(sensor) / (N * N * n * n)
     G = (N * N) * np.fft.ifft2(g_I * F, axes=(1, 2))  # D^H (g_I . F)
     g_sub = 2.0 * c_I * np.imag(np.conj(E) * G)[:, :n, :n]
