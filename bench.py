@@ -91,7 +91,8 @@ def graph_of(torch, fn, n):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
+    # captured on the warm stream: recon_apply's workspace belongs to the stream it runs on
+    with torch.cuda.graph(g, stream=s):
         for i in range(n):
             fn(i)
     torch.cuda.synchronize()

@@ -15,9 +15,9 @@
  *   - All data buffers are DEVICE pointers owned by the caller (float32, row-major).
  *   - Every call that takes a `stream` (a hipStream_t; NULL = the default stream) is
  *     asynchronous on it and never synchronises the device, except wfs_plan, wfs_plan_destroy
- *     and wfs_plan_tune (and wfs_tlse).  No call allocates device memory except wfs_plan, recon_apply
- *     (first use on a device, or a larger problem than seen before) and wfs_adjoint (first
- *     use of a plan).
+ *     and wfs_plan_tune (and wfs_tlse).  No call allocates device memory except wfs_plan,
+ *     recon_apply (first use on a stream, or a larger problem than that stream has seen;
+ *     never while the stream is capturing a graph) and wfs_adjoint (first use of a plan).
  *   - Arguments are validated on the host before anything is launched: a bad argument returns
  *     WFS_EINVAL and launches nothing.  A failed HIP call returns WFS_EDEVICE.  The message of
  *     the last failure on the calling thread is returned by wfs_last_error().
@@ -233,7 +233,11 @@ int wfs_plan_tune(wfs_plan_t plan, const float* layers, int32_t iters, double* b
  *   R: device [M][N] row-major.  S: device [B][N].  C: device, row b at C + b*ldc
  *   (ldc >= M).  beta = 0 ignores the old C.  A pure integrator a += g R s is
  *   alpha = g, beta = 1 on the DM actuator rows.  B = 1 runs a streaming GEMV; B >= 2 a
- *   split-K matrix-core (MFMA) GEMM.  Deterministic.
+ *   split-K matrix-core (MFMA) GEMM.  Deterministic.  The split partial sums go to a
+ *   library-owned buffer of the calling stream (kept for the life of the process, so graphs
+ *   captured with it stay valid); a call that would have to grow that buffer while the stream
+ *   is capturing returns WFS_EINVAL (run it once outside the capture first).  Calls on one
+ *   stream are ordered; calls on different streams never share a buffer.
  */
 int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B, float* C,
                 int64_t ldc, float alpha, float beta, void* stream);
@@ -248,8 +252,10 @@ int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
  *   one wfs_forward of a batch whose realisation r < h holds actuator j0 + r at +amplitude and
  *   realisation h + r the same actuator at -amplitude, on top of `base` (device
  *   [layer_stride], one realisation: e.g. an on-sky screen; NULL = flat); then row j of `im`
- *   is (s+ - s-) / (2 amplitude).  Chunk c runs at step `step` + c, so noise (sensors with
- *   photons > 0) differs between chunks; static grids do not move.  im: device
+ *   is (s+ - s-) / (2 amplitude).  Every chunk samples the layers at time step `step`, so
+ *   all rows share one operating point even when the base screen moves with the wind; chunk c
+ *   draws its noise (sensors with photons > 0) with step counter `step` + c, so noise differs
+ *   between chunks.  im: device
  *   [n_act][ld_im] (ld_im >= n_slopes): row j = d slopes / d actuator j, i.e. the
  *   interaction matrix transposed.  ref_slopes: device [n_slopes], realisation 0 of an
  *   unpoked batch at `step` (NULL = not wanted).  work: device, at least the number of floats

@@ -7,13 +7,14 @@
 //   B >= 2, 16-byte aligned, N%4==0: split-K GEMM on the FP32 matrix cores
 //                                    (v_mfma_f32_16x16x4f32, one 16-row x 16-realisation tile
 //                                    per MFMA, 2 row tiles per wavefront)
-// Both write per-split partial sums to a library-owned workspace; a second kernel adds the
-// splits in a fixed order and applies alpha/beta, so results are deterministic.
+// Both write per-split partial sums to a workspace; a second kernel adds the splits in a fixed
+// order and applies alpha/beta, so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/wfs.h"
 
@@ -228,65 +229,97 @@ __global__ __launch_bounds__(kRB) void recon_reduce_kernel(const float* __restri
 }
 
 // ---------------------------------------------------------------------------------------
-// workspace: one growable buffer per device, kept for the life of the process
+// launch shape: every (row group, split) wave of a call runs in ONE round of the device's
+// resident wave slots, so no wave of a second round streams its chunk after the others end
 // ---------------------------------------------------------------------------------------
-struct Workspace {
-  float* ptr = nullptr;
-  size_t bytes = 0;
-};
-static std::mutex g_ws_mu;
-static Workspace g_ws[64];
+static std::mutex g_occ_mu;
+static int g_slots[64][3];  // per device: resident waves of the MFMA, GEMV and unaligned kernels
 
-static hipError_t workspace(size_t bytes, float** out) {
+static hipError_t resident_waves(int which, int* out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  Workspace& w = g_ws[dev];
-  if (w.bytes < bytes) {
-    if (w.ptr) {
-      e = hipDeviceSynchronize();
-      if (e != hipSuccess) return e;
-      (void)hipFree(w.ptr);
-      w.ptr = nullptr;
-      w.bytes = 0;
-    }
-    e = hipMalloc((void**)&w.ptr, bytes);
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  if (g_slots[dev][which] == 0) {
+    int cus = 0, blocks = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    w.bytes = bytes;
+    const void* k = which == 0   ? reinterpret_cast<const void*>(recon_mfma_kernel<2>)
+                    : which == 1 ? reinterpret_cast<const void*>(recon_valu_kernel<2, true>)
+                                 : reinterpret_cast<const void*>(recon_valu_kernel<2, false>);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kRB, 0);
+    if (e != hipSuccess) return e;
+    g_slots[dev][which] = std::max(1, cus * std::max(1, blocks) * (kRB / 64));
   }
-  *out = w.ptr;
+  *out = g_slots[dev][which];
   return hipSuccess;
 }
 
-static int choose_splits(int row_groups, int N, int align, int* chunk) {
-  const int target_waves = 256 * 32;  // ~8 waves per SIMD
-  int splits = std::max(1, std::min((target_waves + row_groups - 1) / row_groups, N / 256));
-  int c = (N + splits - 1) / splits;
+// Splits of the N columns (chunks of a multiple of `align`) for `row_groups` waves per split:
+// as many as one round of `slots` resident waves holds, at most N/256, and at most
+// `max_splits` (the workspace a caller can offer).
+static int choose_splits(int row_groups, int N, int align, int slots, int64_t max_splits,
+                         int* chunk) {
+  int64_t want = std::max<int64_t>(1, slots / row_groups);
+  want = std::min<int64_t>(want, std::max(1, N / 256));
+  want = std::max<int64_t>(1, std::min<int64_t>(want, max_splits));
+  int c = (int)((N + want - 1) / want);
   c = (c + align - 1) / align * align;
-  splits = (N + c - 1) / c;
   *chunk = c;
-  return splits;
+  return (N + c - 1) / c;  // <= want
 }
 
+struct ReconShape {
+  int mfma;        // 1: matrix-core GEMM in tiles of 16 realisations; 0: one GEMV per realisation
+  int aligned;     // 16-byte aligned R and S, N % 4 == 0
+  int row_groups;
+  int slots;
+  int tile_b;      // realisations per partial-sum tile (16, or 1 for the GEMV)
+};
+
+static hipError_t recon_shape(const float* R, int M, int N, const float* S, int B,
+                              ReconShape* sh) {
+  sh->aligned = (N % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)S % 16 == 0);
+  sh->mfma = B >= 2 && sh->aligned;
+  sh->row_groups = sh->mfma ? (M + 31) / 32 : (M + 1) / 2;
+  sh->tile_b = sh->mfma ? std::min(16, B) : 1;
+  return resident_waves(sh->mfma ? 0 : (sh->aligned ? 1 : 2), &sh->slots);
+}
+
+// Floats of partial sums a call wants (its split count unconstrained by the workspace).
+hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B,
+                             int64_t* floats) {
+  ReconShape sh;
+  hipError_t e = recon_shape(R, M, N, S, B, &sh);
+  if (e != hipSuccess) return e;
+  int chunk;
+  const int splits = choose_splits(sh.row_groups, N, sh.mfma ? 32 : (sh.aligned ? 256 : 64),
+                                   sh.slots, INT32_MAX, &chunk);
+  *floats = (int64_t)splits * sh.tile_b * M;
+  return hipSuccess;
+}
+
+// C = alpha R S^T + beta C with the split partial sums in ws (ws_floats >= M * min(B, 16));
+// the split count shrinks to what ws holds.
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
-                        int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma) {
-  const bool aligned = (N % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)S % 16 == 0);
-  *used_mfma = 0;
-  if (B >= 2 && aligned) {
+                        int64_t ldc, float alpha, float beta, float* ws, int64_t ws_floats,
+                        hipStream_t st, int* used_mfma) {
+  ReconShape sh;
+  hipError_t e = recon_shape(R, M, N, S, B, &sh);
+  if (e != hipSuccess) return e;
+  *used_mfma = sh.mfma;
+  const int64_t max_splits = ws_floats / ((int64_t)sh.tile_b * M);
+  if (max_splits < 1) return hipErrorInvalidValue;
+  if (sh.mfma) {
     constexpr int TR = 2;
-    const int row_groups = (M + 16 * TR - 1) / (16 * TR);
     int chunk;
-    const int splits = choose_splits(row_groups, N, 32, &chunk);
+    const int splits = choose_splits(sh.row_groups, N, 32, sh.slots, max_splits, &chunk);
     for (int b0 = 0; b0 < B; b0 += 16) {
       const int bc = std::min(16, B - b0);
-      float* ws;
-      hipError_t e = workspace(sizeof(float) * (size_t)splits * bc * M, &ws);
-      if (e != hipSuccess) return e;
-      const int waves = row_groups * splits;
+      const int waves = sh.row_groups * splits;
       hipLaunchKernelGGL(recon_mfma_kernel<TR>, dim3((waves + 3) / 4), dim3(kRB), 0, st, R, M,
-                         N, S + (int64_t)b0 * N, bc, 0, chunk, splits, row_groups, ws);
+                         N, S + (int64_t)b0 * N, bc, 0, chunk, splits, sh.row_groups, ws);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
       const int64_t n = (int64_t)M * bc;
@@ -295,24 +328,20 @@ hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, flo
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    *used_mfma = 1;
     return hipSuccess;
   }
   constexpr int RW = 2;
-  const int row_groups = (M + RW - 1) / RW;
   int chunk;
-  const int splits = choose_splits(row_groups, N, aligned ? 256 : 64, &chunk);
+  const int splits =
+      choose_splits(sh.row_groups, N, sh.aligned ? 256 : 64, sh.slots, max_splits, &chunk);
   for (int b = 0; b < B; ++b) {
-    float* ws;
-    hipError_t e = workspace(sizeof(float) * (size_t)splits * M, &ws);
-    if (e != hipSuccess) return e;
-    const int waves = row_groups * splits;
-    if (aligned)
+    const int waves = sh.row_groups * splits;
+    if (sh.aligned)
       hipLaunchKernelGGL((recon_valu_kernel<RW, true>), dim3((waves + 3) / 4), dim3(kRB), 0, st,
-                         R, M, N, S, b, chunk, splits, row_groups, ws);
+                         R, M, N, S, b, chunk, splits, sh.row_groups, ws);
     else
       hipLaunchKernelGGL((recon_valu_kernel<RW, false>), dim3((waves + 3) / 4), dim3(kRB), 0,
-                         st, R, M, N, S, b, chunk, splits, row_groups, ws);
+                         st, R, M, N, S, b, chunk, splits, sh.row_groups, ws);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(recon_reduce_kernel, dim3((M + kRB - 1) / kRB), dim3(kRB), 0, st, ws, M,
@@ -320,6 +349,56 @@ hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, flo
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------
+// recon_apply's workspace: one buffer per (device, stream), so calls on different streams
+// never share partial sums.  A buffer is never freed while the process lives (a captured
+// graph may still hold it): a larger problem allocates a larger buffer and keeps the old one.
+// No buffer is allocated while the stream is capturing.
+// ---------------------------------------------------------------------------------------
+struct StreamWork {
+  int dev;
+  hipStream_t stream;
+  float* ptr;
+  int64_t floats;
+};
+static std::mutex g_ws_mu;
+static std::vector<StreamWork> g_ws;       // current buffer of each (device, stream)
+static std::vector<float*> g_ws_retired;   // outgrown buffers, kept for captured graphs
+
+hipError_t recon_stream_work(hipStream_t st, int64_t floats, float** out, bool* capturing) {
+  *capturing = false;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  StreamWork* w = nullptr;
+  for (auto& x : g_ws)
+    if (x.dev == dev && x.stream == st) w = &x;
+  if (w && w->floats >= floats) {
+    *out = w->ptr;
+    return hipSuccess;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusNone) {
+    *capturing = true;
+    return hipErrorStreamCaptureUnsupported;
+  }
+  float* p = nullptr;
+  e = hipMalloc((void**)&p, sizeof(float) * (size_t)floats);
+  if (e != hipSuccess) return e;
+  if (w) {
+    g_ws_retired.push_back(w->ptr);
+    w->ptr = p;
+    w->floats = floats;
+  } else {
+    g_ws.push_back(StreamWork{dev, st, p, floats});
+  }
+  *out = p;
   return hipSuccess;
 }
 

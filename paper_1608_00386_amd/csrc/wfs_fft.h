@@ -265,7 +265,7 @@ __device__ void fft_subap_m(const FwdParams& p, const DevSensor& S, const DevSub
     float b1 = q1 < np2 ? Bimg[q1] : 0.0f;
     if (noisy) {
       const uint4 ctr = make_uint4((uint32_t)pr, (uint32_t)v, ((uint32_t)b << 8) | (uint32_t)sid,
-                                   (uint32_t)step);
+                                   (uint32_t)(step + p.noise_dstep));
       add_noise_pair(b0, b1, philox4x32_10(ctr, p.seed_lo, p.seed_hi), S.read_noise);
       if (q1 >= np2) b1 = 0.0f;
     }

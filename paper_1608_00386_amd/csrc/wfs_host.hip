@@ -26,8 +26,12 @@ hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
 hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* grad,
                                  const int32_t* blk_start, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
+hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B,
+                             int64_t* floats);
+hipError_t recon_stream_work(hipStream_t st, int64_t floats, float** out, bool* capturing);
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
-                        int64_t ldc, float alpha, float beta, hipStream_t st, int* used_mfma);
+                        int64_t ldc, float alpha, float beta, float* ws, int64_t ws_floats,
+                        hipStream_t st, int* used_mfma);
 hipError_t calib_poke(float* layers, const float* base, int64_t stride, int32_t h, int64_t act0,
                       int32_t n_chunk, float amp, hipStream_t st);
 hipError_t calib_diff(const float* slopes, int32_t h, int32_t n_slopes, int32_t n_chunk,
@@ -1163,8 +1167,22 @@ int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
   if ((int64_t)M * N > (1LL << 40)) return fail(WFS_EINVAL, "recon_apply: R too large");
   if (!std::isfinite(alpha) || !std::isfinite(beta))
     return fail(WFS_EINVAL, "recon_apply: non-finite alpha or beta");
+  hipStream_t st = (hipStream_t)stream;
+  int64_t floats = 0;
+  hipError_t e = recon_work_floats(R, M, N, S, B, &floats);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply");
+  float* ws = nullptr;
+  bool capturing = false;
+  e = recon_stream_work(st, floats, &ws, &capturing);
+  if (capturing)
+    return fail(WFS_EINVAL,
+                "recon_apply: the stream is capturing a graph and its workspace must grow to "
+                "%lld floats: call recon_apply once with this size (or larger) on this stream "
+                "before the capture",
+                (long long)floats);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply: workspace");
   int mfma = 0;
-  hipError_t e = recon_launch(R, M, N, S, B, C, ldc, alpha, beta, (hipStream_t)stream, &mfma);
+  e = recon_launch(R, M, N, S, B, C, ldc, alpha, beta, ws, floats, st, &mfma);
   if (e != hipSuccess) return hip_fail(e, "recon_apply");
   return WFS_OK;
 }
@@ -1212,7 +1230,8 @@ int wfs_calibrate(wfs_plan_t P, const float* base, int64_t act_offset, int32_t n
     return fail(WFS_EINVAL, "wfs_calibrate: step must be an explicit step >= 0");
   const int32_t h = P->batch / 2;
   const int64_t chunks = ((int64_t)n_act + h - 1) / h;
-  if (step > INT64_MAX - chunks) return fail(WFS_EINVAL, "wfs_calibrate: step overflow");
+  if (chunks > INT32_MAX || step > INT64_MAX - chunks)
+    return fail(WFS_EINVAL, "wfs_calibrate: step overflow");
   int64_t o_s = 0, o_a = 0;
   const int64_t need = calib_floats(P, &o_s, &o_a);
   if (work_floats < need)
@@ -1241,8 +1260,11 @@ int wfs_calibrate(wfs_plan_t P, const float* base, int64_t act_offset, int32_t n
     if ((e = calib_poke(wl, base, P->layer_stride, h, act_offset + j0, nc, amplitude, st)) !=
         hipSuccess)
       return hip_fail(e, "wfs_calibrate: poke");
-    rc = wfs_forward(P, wl, step + c, seed, ws, wa, stream);
-    if (rc) return rc;
+    // every chunk sees the layers at the calibration step; only its noise draws move on
+    FwdParams p = call_params(P, wl, step, seed, ws, wa);
+    p.noise_dstep = (int32_t)c;
+    if ((e = launch_fwd_modes(P, p, st)) != hipSuccess)
+      return hip_fail(e, "wfs_calibrate: forward");
     if ((e = calib_diff(ws, h, P->n_slopes, nc, amplitude, im + (int64_t)j0 * ld_im, ld_im,
                         st)) != hipSuccess)
       return hip_fail(e, "wfs_calibrate: difference");

@@ -113,6 +113,7 @@ struct FwdParams {
   int32_t batch;
   uint32_t seed_lo, seed_hi;
   int32_t noise_on;         // 0 in the adjoint's recompute
+  int32_t noise_dstep;      // noise counter step = time step + noise_dstep (calibration chunks)
   float* slopes;
   int32_t n_slopes;
   float* aux;

@@ -828,7 +828,8 @@ __device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm, in
   const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix, false,
                                    FIELD == kFieldFoot ? S.foot_floats : 0);
   otf_spot<NS, FIELD>(p, S, sb, sid, b, step, wsm, lo);
-  const Cog c = cog_sums(p, S, sid, b, v, step, reinterpret_cast<const float*>(wsm + lo.b_off));
+  const Cog c = cog_sums(p, S, sid, b, v, step + p.noise_dstep,
+                         reinterpret_cast<const float*>(wsm + lo.b_off));
   write_slopes(p, S, b, v, c, frame);
   wave_sync();
 }

@@ -43,6 +43,13 @@ def _case(name):
         base = np.random.default_rng(3).standard_normal(cfg["layer_stride"]) * 0.3
         base[a0:] = 0.0
         return dict(cfg, batch=6), a0, n, base.astype(np.float32), False
+    if name == "ngs_lgs_dm7_onsky_wind_noisy":
+        # a base screen moving with the wind and noisy sensors: every chunk sees the screen
+        # at the calibration step and draws its own noise
+        cfg, a0, n = _system(turbulence=True, wind=(35.0, -20.0))
+        base = np.random.default_rng(3).standard_normal(cfg["layer_stride"]) * 0.3
+        base[a0:] = 0.0
+        return _noisy(dict(cfg, batch=6)), a0, n, base.astype(np.float32), True
     if name == "two_ngs_dm11":
         ccfg, n = calib.dm_config(dm_case(), batch=16)
         return ccfg, 0, n, None, False
@@ -50,7 +57,7 @@ def _case(name):
 
 
 @pytest.mark.parametrize("name", ["ngs_lgs_dm7", "ngs_lgs_dm7_noisy", "ngs_lgs_dm7_onsky",
-                                  "two_ngs_dm11"])
+                                  "ngs_lgs_dm7_onsky_wind_noisy", "two_ngs_dm11"])
 def test_calibrate_matches_oracle(name):
     torch, W = _gpu()
     cfg, a0, n, base, noise = _case(name)

@@ -71,6 +71,57 @@ def test_recon_full_size_sampled_rows(B):
     _recon_check(R, S, np.zeros((B, M), np.float32), 1.0, 0.0, got, rows=rows, rel=1e-4)
 
 
+def test_recon_streams_and_graphs_keep_their_own_workspace():
+    """Calls on two streams at once use separate partial-sum buffers (each result equals the
+    call made alone); a graph captured on a stream still replays correctly after a larger
+    problem on that stream has outgrown its buffer (the old buffer stays alive); and a capture
+    that would need a new buffer is refused with an error instead of allocating."""
+    torch, W = _gpu()
+    rng = np.random.default_rng(5)
+    M, N = 700, 20000
+    Ra = torch.from_numpy(rng.standard_normal((M, N)).astype(np.float32)).cuda()
+    Rb = torch.from_numpy(rng.standard_normal((M, N)).astype(np.float32)).cuda()
+    Sa = torch.from_numpy(rng.standard_normal((8, N)).astype(np.float32)).cuda()
+    Sb = torch.from_numpy(rng.standard_normal((8, N)).astype(np.float32)).cuda()
+    ref_a = W.recon_apply(Ra, Sa)
+    ref_b = W.recon_apply(Rb, Sb)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for s in (s1, s2):
+        s.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ca = W.recon_apply(Ra, Sa, stream=s1)
+        with torch.cuda.stream(s2):
+            cb = W.recon_apply(Rb, Sb, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(ca, ref_a) and torch.equal(cb, ref_b)
+    # a graph on s1, then a larger problem on s1 (new buffer), then replays
+    out = torch.zeros(8, M, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s1):
+        W.recon_apply(Ra, Sa, out, stream=s1)
+    Mb = 5000
+    Rbig = torch.from_numpy(rng.standard_normal((Mb, N)).astype(np.float32)).cuda()
+    with torch.cuda.stream(s1):
+        big = W.recon_apply(Rbig, Sa, stream=s1)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_a), rep
+    _recon_check(Rbig.cpu().numpy(), Sa.cpu().numpy(), np.zeros((8, Mb), np.float32), 1.0, 0.0,
+                 big.cpu().numpy().astype(np.float64), rows=np.arange(0, Mb, 97))
+    # capture on a stream whose buffer is too small: refused before any launch
+    s3 = torch.cuda.Stream()
+    g2 = torch.cuda.CUDAGraph()
+    with pytest.raises(RuntimeError, match="capturing"):
+        with torch.cuda.graph(g2, stream=s3):
+            W.recon_apply(Ra, Sa, stream=s3)
+    torch.cuda.synchronize()
+
+
 def _adjoint_case(name, seed=1):
     cfg = CASES[name]()
     for s in cfg["sensors"]:
