@@ -243,6 +243,21 @@ int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
                 int64_t ldc, float alpha, float beta, void* stream);
 
 /*
+ * recon_apply_noalloc -- recon_apply for callers that cannot allocate device memory (code
+ *   under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ *   arguments, operation, layouts and error codes as recon_apply, same kernels; it never
+ *   allocates, frees or synchronises.  The split partial sums go to a fixed library array of
+ *   2^22 floats (16 MiB) on each GPU, held until the process ends; the split count shrinks to
+ *   what it holds, so results may differ from recon_apply's by rounding order only.  Returns
+ *   WFS_EINVAL when one split does not fit: M * min(B, 16) > 2^22 for B >= 2 (aligned
+ *   operands), M > 2^22 otherwise.  Every call on one GPU shares the array: calls that overlap
+ *   in time on one GPU (different streams, or threads) race and give wrong results; order
+ *   them on one stream.  The caller owns R, S and C as for recon_apply.
+ */
+int recon_apply_noalloc(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
+                        float* C, int64_t ldc, float alpha, float beta, void* stream);
+
+/*
  * wfs_calibrate -- interaction-matrix calibration (Sec. 2.5: the chosen modes are pushed
  *   through the sensor model and their slopes recorded, optionally with noise or with a
  *   turbulence screen present, together with the reference slopes).  The modes are single

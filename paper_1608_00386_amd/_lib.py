@@ -91,6 +91,8 @@ _PROTOS = {
     "wfs_plan_tune": (_c.c_int, [_P, _P, _c.c_int32, _c.POINTER(_c.c_double), _P]),
     "recon_apply": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _P, _c.c_int32, _P, _c.c_int64,
                                _c.c_float, _c.c_float, _P]),
+    "recon_apply_noalloc": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _P, _c.c_int32, _P,
+                                       _c.c_int64, _c.c_float, _c.c_float, _P]),
     "wfs_calibrate_work": (_c.c_int, [_P, _c.POINTER(_c.c_int64)]),
     "wfs_calibrate": (_c.c_int, [_P, _P, _c.c_int64, _c.c_int32, _c.c_float, _c.c_int64,
                                  _c.c_uint64, _P, _c.c_int64, _P, _P, _c.c_int64, _P]),

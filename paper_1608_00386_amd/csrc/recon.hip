@@ -402,4 +402,44 @@ hipError_t recon_stream_work(hipStream_t st, int64_t floats, float** out, bool* 
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------------------
+// Fixed workspace of recon_apply_noalloc: a file-scope device array (each GPU the library runs
+// on holds its own copy until the process ends).  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get its device address, fetched once per device with
+// hipGetSymbolAddress on the first call there.  Every call on one GPU shares it.
+// ---------------------------------------------------------------------------------------
+constexpr int64_t kStaticWorkFloats = int64_t(1) << 22;  // 16 MiB of partial sums
+static __device__ __align__(256) float scratch[kStaticWorkFloats];
+static std::mutex g_static_mu;
+static float* g_static_ptr[64];
+
+int64_t recon_static_work_floats() { return kStaticWorkFloats; }
+
+// Floats of partial sums one split of a call needs (M rows x the realisations of one tile).
+hipError_t recon_min_work_floats(const float* R, int M, int N, const float* S, int B,
+                                 int64_t* floats) {
+  ReconShape sh;
+  hipError_t e = recon_shape(R, M, N, S, B, &sh);
+  if (e != hipSuccess) return e;
+  *floats = (int64_t)sh.tile_b * M;
+  return hipSuccess;
+}
+
+hipError_t recon_static_work(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_static_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_static_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace wfs

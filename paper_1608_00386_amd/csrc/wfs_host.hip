@@ -29,6 +29,10 @@ int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B,
                              int64_t* floats);
 hipError_t recon_stream_work(hipStream_t st, int64_t floats, float** out, bool* capturing);
+int64_t recon_static_work_floats();
+hipError_t recon_min_work_floats(const float* R, int M, int N, const float* S, int B,
+                                 int64_t* floats);
+hipError_t recon_static_work(float** out);
 hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, float* C,
                         int64_t ldc, float alpha, float beta, float* ws, int64_t ws_floats,
                         hipStream_t st, int* used_mfma);
@@ -1184,6 +1188,36 @@ int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
   int mfma = 0;
   e = recon_launch(R, M, N, S, B, C, ldc, alpha, beta, ws, floats, st, &mfma);
   if (e != hipSuccess) return hip_fail(e, "recon_apply");
+  return WFS_OK;
+}
+
+int recon_apply_noalloc(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
+                        float* C, int64_t ldc, float alpha, float beta, void* stream) {
+  if (!R || !S || !C) return fail(WFS_EINVAL, "recon_apply_noalloc: null R, S or C");
+  if (M < 1 || N < 1 || B < 1)
+    return fail(WFS_EINVAL, "recon_apply_noalloc: M=%d N=%d B=%d must be >= 1", M, N, B);
+  if (ldc < M)
+    return fail(WFS_EINVAL, "recon_apply_noalloc: ldc=%lld < M=%d", (long long)ldc, M);
+  if ((int64_t)M * N > (1LL << 40)) return fail(WFS_EINVAL, "recon_apply_noalloc: R too large");
+  if (!std::isfinite(alpha) || !std::isfinite(beta))
+    return fail(WFS_EINVAL, "recon_apply_noalloc: non-finite alpha or beta");
+  int64_t need = 0;
+  hipError_t e = recon_min_work_floats(R, M, N, S, B, &need);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply_noalloc");
+  const int64_t cap = recon_static_work_floats();
+  if (need > cap)
+    return fail(WFS_EINVAL,
+                "recon_apply_noalloc: M=%d rows x %d realisations per tile need %lld floats of "
+                "partial sums, above the fixed workspace of %lld floats (M * min(B, 16) <= "
+                "%lld)",
+                M, (int)(need / M), (long long)need, (long long)cap,
+                (long long)cap);
+  float* ws = nullptr;
+  e = recon_static_work(&ws);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply_noalloc: workspace address");
+  int mfma = 0;
+  e = recon_launch(R, M, N, S, B, C, ldc, alpha, beta, ws, cap, (hipStream_t)stream, &mfma);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply_noalloc");
   return WFS_OK;
 }
 

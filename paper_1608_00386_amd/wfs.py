@@ -228,8 +228,10 @@ class Plan:
         return best.value
 
 
-def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None):
-    """C[b] = alpha R S[b] + beta C[b]; R [M][N], S [B][N]; C [B][ldc] (default ldc = M)."""
+def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None, noalloc=False):
+    """C[b] = alpha R S[b] + beta C[b]; R [M][N], S [B][N]; C [B][ldc] (default ldc = M).
+    ``noalloc``: call ``recon_apply_noalloc`` (partial sums in the library's fixed array; the
+    caller then passes C, since allocating it here would defeat the purpose)."""
     _need(R, "R")
     _need(S, "S")
     if R.dim() != 2 or S.dim() != 2 or S.shape[1] != R.shape[1]:
@@ -237,6 +239,8 @@ def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None):
     M, N = R.shape
     B = S.shape[0]
     if C is None:
+        if noalloc:
+            raise ValueError("recon_apply(noalloc=True) needs the output C")
         C = torch.zeros(B, M, device=R.device)
         ldc = M
     if not isinstance(C, torch.Tensor) or C.dtype != torch.float32 or not C.is_cuda:
@@ -247,8 +251,9 @@ def recon_apply(R, S, C=None, alpha=1.0, beta=0.0, ldc=None, stream=None):
         ldc = C.stride(0)
     if C.stride(0) != ldc or ldc < M:
         raise ValueError(f"C row stride {C.stride(0)} must equal ldc={ldc} >= M={M}")
-    L.check(L.lib().recon_apply(_ptr(R), int(M), int(N), _ptr(S), int(B), _ptr(C), int(ldc),
-                                float(alpha), float(beta), _stream(stream)), "recon_apply")
+    fn = "recon_apply_noalloc" if noalloc else "recon_apply"
+    L.check(getattr(L.lib(), fn)(_ptr(R), int(M), int(N), _ptr(S), int(B), _ptr(C), int(ldc),
+                                 float(alpha), float(beta), _stream(stream)), fn)
     return C
 
 
