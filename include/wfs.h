@@ -14,10 +14,11 @@
  * Conventions shared by every call
  *   - All data buffers are DEVICE pointers owned by the caller (float32, row-major).
  *   - Every call that takes a `stream` (a hipStream_t; NULL = the default stream) is
- *     asynchronous on it and never synchronises the device, except wfs_plan, wfs_plan_destroy
- *     and wfs_plan_tune (and wfs_tlse).  No call allocates device memory except wfs_plan,
- *     recon_apply (first use on a stream, or a larger problem than that stream has seen;
- *     never while the stream is capturing a graph) and wfs_adjoint (first use of a plan).
+ *     asynchronous on it and never synchronises the device, except wfs_plan, wfs_plan_destroy,
+ *     wfs_plan_na_profile and wfs_plan_tune (and wfs_tlse).  No call allocates device memory
+ *     except wfs_plan, wfs_plan_na_profile, recon_apply (first use on a stream, or a larger
+ *     problem than that stream has seen; never while the stream is capturing a graph) and
+ *     wfs_adjoint (first use of a plan).
  *   - Arguments are validated on the host before anything is launched: a bad argument returns
  *     WFS_EINVAL and launches nothing.  A failed HIP call returns WFS_EDEVICE.  The message of
  *     the last failure on the calling thread is returned by wfs_last_error().
@@ -96,6 +97,11 @@ typedef struct {
   double photons;                  /* photons per fully lit subaperture per frame;
                                       0 = unit flux and no noise                           */
   double read_noise_e;             /* read noise (electrons rms), used when photons > 0    */
+  double tilt_x_rad, tilt_y_rad;   /* extra tip-tilt of this sensor (Sec. 2.3: an NGS WFS
+                                      mispositioned by these sky angles): the phase
+                                      2 pi (tilt_x x + tilt_y y) / lambda_m at the pupil
+                                      pixel centres (x, y) is added to the projected phase;
+                                      0 = none                                            */
 } wfs_sensor_desc;
 
 /*
@@ -120,6 +126,25 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
 int wfs_plan_info(wfs_plan_t plan, int32_t* n_slopes, int32_t* n_valid_total,
                   int32_t* n_valid_per_sensor, double* pix_scale_rad);
 
+/*
+ * wfs_plan_na_profile -- time-varying, multi-peak sodium profile of the plan's elongated LGS
+ *   sensors (Sec. 2.7: the temporal evolution of the sodium layer).  table: host
+ *   [n_entries][n_peaks][3] doubles (dh_m, fwhm_m, weight) per peak; the frame at time step k
+ *   uses entry k mod n_entries.  A peak dh metres above the LGS altitude H with Gaussian width
+ *   fwhm (0 allowed: a thin peak) carries the fraction weight / (sum of the entry's weights)
+ *   of the return; a subaperture at baseline b from the launch sees it shifted by
+ *   |b| dh / H^2 and widened by |b| sigma / H^2 (radians) along b / |b|, so its transfer
+ *   function is sum_j w_j exp(-2 pi^2 sigma_j^2 u^2) exp(-2 pi i mu_j u) in FFT pixels.  The
+ *   profile replaces the single Gaussian of na_fwhm_m on every sensor with na_fwhm_m > 0 and
+ *   a finite source altitude; other sensors are unaffected.  n_entries = 0 (table NULL)
+ *   restores the single Gaussians.  Limits: 1 <= n_peaks <= 8, n_entries <= 2^20; weights
+ *   >= 0 with a positive sum per entry, fwhm >= 0, all finite (WFS_EINVAL otherwise).
+ *   Synchronises the device; allocates the device copy (a table that fits the plan's current
+ *   buffer reuses it; a captured graph reads whatever table is current when it replays).
+ */
+int wfs_plan_na_profile(wfs_plan_t plan, int32_t n_entries, int32_t n_peaks,
+                        const double* table);
+
 /* wfs_plan_path -- which path each sensor runs: 0 = lag-domain (OTF), 1 = FFT. */
 int wfs_plan_path(wfs_plan_t plan, int32_t* path_per_sensor);
 
@@ -129,9 +154,11 @@ int wfs_plan_destroy(wfs_plan_t plan);
 /*
  * wfs_forward -- slopes of every sensor for every realisation (Sec. 2.2 + Sec. 2.7):
  *   projection of the layers along each guide-star direction (cone factor for the LGS,
- *   frozen-flow shift v*t, periodic/zero boundary), field A exp(i phase) with a half-pixel
- *   centring ramp on each valid n_sub x n_sub subaperture zero-padded to n_fft, spot
- *   |DFT|^2 scaled to `photons`, Gaussian sodium elongation along the launch baseline,
+ *   frozen-flow shift v*t, periodic/zero boundary), the sensor's tip-tilt offset added,
+ *   field A exp(i phase) with a half-pixel centring ramp on each valid n_sub x n_sub
+ *   subaperture zero-padded to n_fft, spot |DFT|^2 scaled to `photons`, sodium elongation
+ *   along the launch baseline (the sensor's Gaussian, or the plan's sodium-profile entry for
+ *   this step, wfs_plan_na_profile),
  *   fftshift and bin x bin binning, Gaussian photon + read noise (Philox4x32-10 keyed by
  *   seed, counters from realisation, sensor, subaperture, pixel pair and step) when the
  *   sensor has photons > 0, and centre of gravity in binned pixels (0 when the flux <= 0).

@@ -56,6 +56,8 @@ class SensorDesc(ctypes.Structure):
         ("launch_y_m", ctypes.c_double),
         ("photons", ctypes.c_double),
         ("read_noise_e", ctypes.c_double),
+        ("tilt_x_rad", ctypes.c_double),
+        ("tilt_y_rad", ctypes.c_double),
     ]
 
 
@@ -76,6 +78,7 @@ _PROTOS = {
     "wfs_plan_info": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
                                  _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double)]),
     "wfs_plan_path": (_c.c_int, [_P, _c.POINTER(_c.c_int32)]),
+    "wfs_plan_na_profile": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_double)]),
     "wfs_plan_destroy": (_c.c_int, [_P]),
     "wfs_forward": (_c.c_int, [_P, _P, _c.c_int64, _c.c_uint64, _P, _P, _P]),
     "wfs_project": (_c.c_int, [_P, _P, _c.c_int64, _P, _P]),
@@ -150,4 +153,19 @@ def sensor_desc(S):
                       float(S["pupil_d_m"]), float(S["obs_d_m"]), int(S["n_sa"]),
                       int(S["n_sub"]), int(S["n_fft"]), int(S["bin"]), float(S["valid_frac"]),
                       float(S["na_fwhm_m"]), float(S["launch_x_m"]), float(S["launch_y_m"]),
-                      float(S["photons"]), float(S["read_noise_e"]))
+                      float(S["photons"]), float(S["read_noise_e"]),
+                      float(S.get("tilt_x_rad", 0.0)), float(S.get("tilt_y_rad", 0.0)))
+
+
+def na_profile_table(profile):
+    """A sodium-profile time series (list of entries, each a list of (dh_m, fwhm_m, weight)
+    peaks) as wfs_plan_na_profile's flat [n_entries][n_peaks][3] doubles; entries with fewer
+    peaks are padded with zero-weight peaks.  Returns (n_entries, n_peaks, ctypes array)."""
+    n_e = len(profile)
+    n_p = max(len(e) for e in profile)
+    flat = []
+    for e in profile:
+        pk = [tuple(map(float, q)) for q in e] + [(0.0, 0.0, 0.0)] * (n_p - len(e))
+        for q in pk:
+            flat.extend(q)
+    return n_e, n_p, (ctypes.c_double * len(flat))(*flat)

@@ -118,6 +118,7 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   wave_sync();
   // U[k] = c Kel(k) s(kx) s(ky) ghat[k mod n_pix] on all (2 NS - 1)^2 lags
   constexpr int NL = 2 * NS - 1;
+  const NaEntry el = na_entry(p, step);
   float2* U = reinterpret_cast<float2*>(wsm + la.u_off);
   const float2* stab = reinterpret_cast<const float2*>(wsm + lo.stab_off);
   for (int t2 = lane; t2 < NL * NL; t2 += kWave) {
@@ -130,9 +131,10 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
     const float2 g = GH[Ky * np + Kx];
     const float2 sx = stab[ix], sy = stab[iy];
     const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
-    const float kel = __expf(-sb.alpha * proj * proj) * S.flux_c;
-    const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
-    const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
+    const float2 k = elong_tf(sb, el, proj, S.flux_c);
+    const float sr = sx.x * sy.x - sx.y * sy.y, si = sx.x * sy.y + sx.y * sy.x;
+    const float tr = sr * k.x - si * k.y;
+    const float ti = sr * k.y + si * k.x;
     U[t2] = make_float2(tr * g.x - ti * g.y, tr * g.y + ti * g.x);
   }
   // taps again (the forward scratch region is free now); the gather mode needs none

@@ -156,7 +156,7 @@ __device__ void fft_subap_m(const FwdParams& p, const DevSensor& S, const DevSub
   for (int q = tid; q < n * n; q += kBlock) {
     const int y = q / n, x = q - y * n;
     const uint8_t amp = p.mask[S.mask_off + (sb.a * n + y) * S.n_pup + sb.b * n + x];
-    float t = fmaf(ph[q], 0.15915494309189535f, -(float)(x + y) * S.ramp);
+    float t = fmaf(ph[q], 0.15915494309189535f, -fmaf((float)x, S.ramp_x, (float)y * S.ramp_y));
     t -= rintf(t);
     turns[q] = amp ? t : __builtin_inff();
   }

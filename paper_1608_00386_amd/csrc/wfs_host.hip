@@ -133,6 +133,9 @@ struct wfs_plan_s {
   int frames = 0;
   int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
   SideStream side{};         // FFT-path blocks run here concurrently (plans with both paths)
+  float4* d_na = nullptr;    // sodium-profile table (wfs_plan_na_profile), capacity na_cap
+  int64_t na_cap = 0;
+  std::vector<float4*> na_retired;  // outgrown tables: graphs captured earlier may hold them
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
@@ -187,6 +190,7 @@ static SensorGeom sensor_geometry(const wfs_sensor_desc& s) {
         d.alpha = (float)(2.0 * M_PI * M_PI * sig_px * sig_px / ((double)s.n_fft * s.n_fft));
         d.ex = (float)(bx / bl);
         d.ey = (float)(by / bl);
+        d.gam = (float)(bl / (H * H * p_fft * (double)s.n_fft));
       }
       g.subs.push_back(d);
     }
@@ -244,6 +248,8 @@ static int validate(const wfs_layer_desc* layers, int32_t n_layers, int64_t laye
         !finite_d(S.theta_x_rad) || !finite_d(S.theta_y_rad) || !finite_d(S.launch_x_m) ||
         !finite_d(S.launch_y_m))
       return fail(WFS_EINVAL, "sensor %d: photons/noise/elongation/direction", s);
+    if (!finite_d(S.tilt_x_rad) || !finite_d(S.tilt_y_rad))
+      return fail(WFS_EINVAL, "sensor %d: non-finite tip-tilt offset", s);
     if (finite_d(S.src_alt_m))
       for (int l = 0; l < n_layers; ++l)
         if (!(layers[l].alt_m < S.src_alt_m))
@@ -362,7 +368,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     const double fph = S.photons > 0 ? S.photons : 1.0;
     d.flux_c = (float)(fph / ((double)S.n_fft * S.n_fft * (double)S.n_sub * S.n_sub));
     d.read_noise = (float)S.read_noise_e;
-    d.ramp = (float)(0.5 / S.n_fft);
+    d.ramp_x = (float)(0.5 / S.n_fft - S.tilt_x_rad * g.dx / S.lambda_m);
+    d.ramp_y = (float)(0.5 / S.n_fft - S.tilt_y_rad * g.dx / S.lambda_m);
     // projection blocks: (group of project_rows() pupil rows, strip of project_strip()
     // columns) holding at least one pixel of a valid subaperture; packed row0 | strip << 16
     d.proj_rows = project_rows();
@@ -726,6 +733,8 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (P->d_blob) (void)hipFree(P->d_blob);
   if (P->d_phase) (void)hipFree(P->d_phase);
   if (P->d_gimg) (void)hipFree(P->d_gimg);
+  if (P->d_na) (void)hipFree(P->d_na);
+  for (float4* q : P->na_retired) (void)hipFree(q);
   if (P->side.join) (void)hipEventDestroy(P->side.join);
   if (P->side.fork) (void)hipEventDestroy(P->side.fork);
   if (P->side.stream) (void)hipStreamDestroy(P->side.stream);
@@ -741,6 +750,63 @@ static int check_device(wfs_plan_t P, const char* who) {
   if (dev != P->device)
     return fail(WFS_EINVAL, "%s: current device %d is not the plan's device %d", who, dev,
                 P->device);
+  return WFS_OK;
+}
+
+int wfs_plan_na_profile(wfs_plan_t P, int32_t n_entries, int32_t n_peaks, const double* table) {
+  if (!P) return fail(WFS_EINVAL, "wfs_plan_na_profile: null plan");
+  if (n_entries == 0) {  // back to each sensor's single Gaussian
+    P->base.na_entries = 0;
+    P->base.na_peaks = 0;
+    return WFS_OK;
+  }
+  if (n_entries < 0 || n_entries > (1 << 20))
+    return fail(WFS_EINVAL, "wfs_plan_na_profile: n_entries=%d outside [0, 2^20]", n_entries);
+  if (n_peaks < 1 || n_peaks > kMaxNaPeaks)
+    return fail(WFS_EINVAL, "wfs_plan_na_profile: n_peaks=%d outside [1, %d]", n_peaks,
+                kMaxNaPeaks);
+  if (!table) return fail(WFS_EINVAL, "wfs_plan_na_profile: null table");
+  const double to_sigma = 1.0 / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+  std::vector<float4> h((size_t)n_entries * n_peaks);
+  for (int k = 0; k < n_entries; ++k) {
+    const double* e = table + (size_t)k * n_peaks * 3;
+    double wsum = 0.0;
+    for (int j = 0; j < n_peaks; ++j) {
+      const double dh = e[3 * j], fw = e[3 * j + 1], w = e[3 * j + 2];
+      if (!finite_d(dh) || !finite_d(fw) || !finite_d(w) || fw < 0 || w < 0)
+        return fail(WFS_EINVAL,
+                    "wfs_plan_na_profile: entry %d peak %d: dh, fwhm, weight must be finite, "
+                    "fwhm >= 0 and weight >= 0", k, j);
+      wsum += w;
+    }
+    if (!(wsum > 0))
+      return fail(WFS_EINVAL, "wfs_plan_na_profile: entry %d has no positive weight", k);
+    for (int j = 0; j < n_peaks; ++j) {
+      const double sig = e[3 * j + 1] * to_sigma;
+      h[(size_t)k * n_peaks + j] = make_float4((float)(2.0 * M_PI * M_PI * sig * sig),
+                                               (float)e[3 * j], (float)(e[3 * j + 2] / wsum),
+                                               0.0f);
+    }
+  }
+  int rc = check_device(P, "wfs_plan_na_profile");
+  if (rc) return rc;
+  // no launch may still read the table being replaced
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "wfs_plan_na_profile: synchronise");
+  const int64_t need = (int64_t)h.size();
+  if (need > P->na_cap) {
+    float4* q = nullptr;
+    e = hipMalloc((void**)&q, sizeof(float4) * (size_t)need);
+    if (e != hipSuccess) return fail(WFS_ENOMEM, "wfs_plan_na_profile: %lld peaks", (long long)need);
+    if (P->d_na) P->na_retired.push_back(P->d_na);
+    P->d_na = q;
+    P->na_cap = need;
+  }
+  e = hipMemcpy(P->d_na, h.data(), sizeof(float4) * h.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "wfs_plan_na_profile: upload");
+  P->base.na_tab = P->d_na;
+  P->base.na_entries = n_entries;
+  P->base.na_peaks = n_peaks;
   return WFS_OK;
 }
 

@@ -43,7 +43,9 @@ struct DevSensor {
   float kappa;       // lambda_ref / lambda
   float flux_c;      // F_ph / (n_fft^2 n_sub^2)
   float read_noise;  // electrons rms
-  float ramp;        // 1 / (2 n_fft): half-pixel centring ramp, turns per pixel index
+  float ramp_x;      // turns per pixel column subtracted from the field phase: the half-pixel
+                     // centring ramp 1 / (2 n_fft) less the sensor's tip, tilt_x dx / lambda
+                     // (its constant part over a subaperture does not change the spot)
   int32_t stab_off;  // first entry of this sensor's lag-phase table s(k), k = -(n_sub-1)..
   int32_t wtab_off;  // first entry of this sensor's n_pix-point twiddle table
   float inv_npix;    // 1 / n_pix
@@ -54,7 +56,7 @@ struct DevSensor {
   int32_t pupil_off;  // offset of this sensor's [n_pup][n_pup] image in a pupil-frame buffer
   int32_t foot_cols_off;  // first entry of this sensor's footprint-column table
   int32_t foot_floats;    // footprint floats of one subaperture, all layers
-  int32_t pad3;
+  float ramp_y;           // the same per pixel row: 1 / (2 n_fft) - tilt_y dx / lambda
 };
 
 // Staged-footprint field: the layer pixels one subaperture's bilinear stencils can touch,
@@ -82,8 +84,12 @@ struct DevSubap {
   float alpha;    // 2 pi^2 sigma_px^2 / n_fft^2 (0: no elongation)
   float ex, ey;   // unit elongation direction
   int32_t v;      // index among the sensor's valid subapertures
-  int32_t pad0, pad1;
+  float gam;      // sodium-profile scale |b| / (H^2 p_fft n_fft): a peak dh metres above the
+                  // focus shifts by gam dh per unit lag along e (0: no elongation)
+  int32_t pad1;
 };
+
+constexpr int kMaxNaPeaks = 8;  // peaks per entry of a sodium-profile table
 
 // Flat list of sensors served by one launch (one lag-domain template instance plus the FFT
 // path); task t of realisation b is subaperture (t - start[k]) of sensor ids[k].
@@ -114,6 +120,10 @@ struct FwdParams {
   uint32_t seed_lo, seed_hi;
   int32_t noise_on;         // 0 in the adjoint's recompute
   int32_t noise_dstep;      // noise counter step = time step + noise_dstep (calibration chunks)
+  // sodium profile: [na_entries][na_peaks] peaks (2 pi^2 sigma_h^2, dh, normalised weight, 0);
+  // the frame at step k uses entry k mod na_entries; na_entries = 0: single Gaussians
+  const float4* na_tab;
+  int32_t na_entries, na_peaks;
   float* slopes;
   int32_t n_slopes;
   float* aux;

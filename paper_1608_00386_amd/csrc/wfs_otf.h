@@ -132,6 +132,54 @@ __device__ __forceinline__ Tap tap_of(const DevLayer& L, const DevAffine& A, boo
   return make_tap(v, L.ny, L.inv_ny, L.boundary, L.nx);
 }
 
+// Sodium-profile entry of the frame at time step `step` (wave-uniform): its first peak and the
+// peak count, or no peaks when the plan has no profile table (single Gaussians).
+struct NaEntry {
+  const float4* pk;
+  int n;
+};
+
+__device__ __forceinline__ NaEntry na_entry(const FwdParams& p, int64_t step) {
+  NaEntry e;
+  e.n = 0;
+  e.pk = nullptr;
+  if (p.na_entries > 0) {
+    const int64_t k = step % (int64_t)p.na_entries;
+    e.pk = p.na_tab + (k < 0 ? k + p.na_entries : k) * p.na_peaks;
+    e.n = p.na_peaks;
+  }
+  return e;
+}
+
+// Sodium transfer function at the lag whose projection on the elongation direction is `proj`
+// (lag units), times `scale`: the subaperture's single Gaussian exp(-alpha proj^2), or, with
+// a profile entry, sum_j w_j exp(-2 pi^2 sigma_j^2 t^2) e^{-2 pi i dh_j t}, t = gam proj
+// (peak j widened by gam sigma_j and shifted by gam dh_j FFT pixels per unit lag, Sec. 2.7).
+__device__ __forceinline__ float2 elong_tf(const DevSubap& sb, const NaEntry& el, float proj,
+                                           float scale) {
+  if (el.n == 0 || sb.gam == 0.0f)
+    return make_float2(__expf(-sb.alpha * proj * proj) * scale, 0.0f);
+  const float t = sb.gam * proj;
+  float kr = 0.0f, ki = 0.0f;
+  for (int j = 0; j < el.n; ++j) {
+    const float4 q = el.pk[j];  // (2 pi^2 sigma_h^2, dh, w, 0)
+    const float m = q.z * __expf(-q.x * t * t);
+    float turns = q.y * t;
+    turns -= rintf(turns);
+    float sn, cs;
+    sincos_rev(turns, &sn, &cs);
+    kr = fmaf(m, cs, kr);
+    ki = fmaf(-m, sn, ki);
+  }
+  return make_float2(kr * scale, ki * scale);
+}
+
+// Phase in turns subtracted at local pixel (row r, column c) of a subaperture: the half-pixel
+// centring ramp and the sensor's tip-tilt (both linear in the pixel index).
+__device__ __forceinline__ float field_ramp(const DevSensor& S, int r, int c) {
+  return fmaf((float)c, S.ramp_x, (float)r * S.ramp_y);
+}
+
 // Where the lag-domain field stage gets the phase (a compile-time choice, so that each kernel
 // only holds the registers of its own path).
 constexpr int kFieldGather = 0;  // bilinear stencils straight from the layers, per pixel
@@ -367,7 +415,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       if (q < NPIX) {
         const int r = q / NS, c = q - r * NS;
         const uint8_t amp = p.mask[S.mask_off + (sb.a * NS + r) * S.n_pup + sb.b * NS + c];
-        float turns = fmaf(ph[i], 0.15915494309189535f, -(float)(r + c) * S.ramp);
+        float turns = fmaf(ph[i], 0.15915494309189535f, -field_ramp(S, r, c));
         turns -= rintf(turns);
         float sn, cs;
         sincos_rev(turns, &sn, &cs);
@@ -385,7 +433,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       if (q < NPIX) {
         const int r = q / NS, c = q - r * NS;
         const uint8_t amp = p.mask[S.mask_off + (sb.a * NS + r) * S.n_pup + sb.b * NS + c];
-        float turns = fmaf(ph[q], 0.15915494309189535f, -(float)(r + c) * S.ramp);
+        float turns = fmaf(ph[q], 0.15915494309189535f, -field_ramp(S, r, c));
         turns -= rintf(turns);
         float sn, cs;
         sincos_rev(turns, &sn, &cs);
@@ -467,7 +515,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       const int q = lane + i * kWave;
       // phase in turns, reduced to [-1/2, 1/2] before the sincos
       float turns =
-          fmaf(psi[i], S.kappa * 0.15915494309189535f, -(float)(pr[i] + pc[i]) * S.ramp);
+          fmaf(psi[i], S.kappa * 0.15915494309189535f, -field_ramp(S, pr[i], pc[i]));
       turns -= rintf(turns);
       float sn, cs;
       sincos_rev(turns, &sn, &cs);
@@ -481,8 +529,9 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
 // partial-row region, kChunk columns per job), times the elongation and binning factors:
 // AW[dy][dx] (+)= w_dy Kel(dx, dy) s(dx) s(dy) sum_r part, lane per lag (dy, dx).
 template <int NS, int IX0, int W>
-__device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& sb, char* wsm,
-                                           const OtfLds& lo, int j0) {
+__device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& sb,
+                                           const NaEntry& el, char* wsm, const OtfLds& lo,
+                                           int j0) {
   constexpr int NL = Otf<NS>::kLags;
   const int lane = lane_id();
   const float2* part = reinterpret_cast<const float2*>(wsm + lo.part_off);
@@ -493,9 +542,10 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
     const int dx = ix - (NS - 1);
     const float2 sx = stab[ix], sy = stab[dy + NS - 1];
     const float proj = fmaf((float)dx, sb.ex, (float)dy * sb.ey);
-    const float kel = __expf(-sb.alpha * proj * proj) * (dy == 0 ? 1.0f : 2.0f);
-    const float tr = (sx.x * sy.x - sx.y * sy.y) * kel;
-    const float ti = (sx.x * sy.y + sx.y * sy.x) * kel;
+    const float2 k = elong_tf(sb, el, proj, dy == 0 ? 1.0f : 2.0f);
+    const float sr = sx.x * sy.x - sx.y * sy.y, si = sx.x * sy.y + sx.y * sy.x;
+    const float tr = sr * k.x - si * k.y;
+    const float ti = sr * k.y + si * k.x;
     return make_float2(a.x * tr - a.y * ti, a.x * ti + a.y * tr);
   };
   if constexpr (Otf<NS>::kRounds == 1) {
@@ -564,7 +614,8 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
 // row per job, at the same number of multiply-adds.
 template <int NS, int IX0, int W>
 __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap& sb,
-                                              char* wsm, const OtfLds& lo, int j0) {
+                                              const NaEntry& el, char* wsm, const OtfLds& lo,
+                                              int j0) {
   const int lane = lane_id();
   const float2* E = reinterpret_cast<const float2*>(wsm + lo.e_off);
   float2* part = reinterpret_cast<float2*>(wsm + lo.part_off);
@@ -603,16 +654,17 @@ __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap
     for (int k = 0; k < W; ++k) part[lane * Otf<NS>::kChunk + k] = acc[k];
   }
   wave_sync();
-  otf_lagsum<NS, IX0, W>(S, sb, wsm, lo, j0);
+  otf_lagsum<NS, IX0, W>(S, sb, el, wsm, lo, j0);
 }
 
 template <int NS, int IX0 = 0>
 __device__ __forceinline__ void otf_corr_round(const DevSensor& S, const DevSubap& sb,
-                                               char* wsm, const OtfLds& lo, int j0) {
+                                               const NaEntry& el, char* wsm, const OtfLds& lo,
+                                               int j0) {
   constexpr int NL = Otf<NS>::kLags, CW = Otf<NS>::kChunk;
   constexpr int W = IX0 + CW <= NL ? CW : NL - IX0;
-  otf_corr_part<NS, IX0, W>(S, sb, wsm, lo, j0);
-  if constexpr (IX0 + W < NL) otf_corr_round<NS, IX0 + W>(S, sb, wsm, lo, j0);
+  otf_corr_part<NS, IX0, W>(S, sb, el, wsm, lo, j0);
+  if constexpr (IX0 + W < NL) otf_corr_round<NS, IX0 + W>(S, sb, el, wsm, lo, j0);
 }
 
 // Fold modulo n_pix: P[Ky][Kx] = sum over lags (dy, dx) = (Ky, Kx) mod n_pix of AW, lane per K.
@@ -811,9 +863,10 @@ __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
                                          const DevSubap& sb, int sid, int b, int64_t step,
                                          char* wsm, const OtfLds& lo) {
   otf_field<NS, FIELD>(p, S, sb, sid, b, (double)step, wsm, lo);
+  const NaEntry el = na_entry(p, step);
 #pragma unroll
   for (int rd = 0; rd < Otf<NS>::kRounds; ++rd)
-    otf_corr_round<NS>(S, sb, wsm, lo, rd * Otf<NS>::kJobsPerRound);
+    otf_corr_round<NS>(S, sb, el, wsm, lo, rd * Otf<NS>::kJobsPerRound);
   otf_fold<NS>(S, wsm, lo);
   otf_image(p, S, wsm, lo);
 }

@@ -40,7 +40,8 @@ class Plan:
     """A set of Shack-Hartmann sensors looking through a set of layers (``wfs_plan``).
 
     ``cfg`` is a dict with ``layers`` and ``sensors`` (the fields of wfs_layer_desc and
-    wfs_sensor_desc), ``layer_stride``, ``batch``, ``lambda_ref_m`` and ``dt_s``.
+    wfs_sensor_desc), ``layer_stride``, ``batch``, ``lambda_ref_m`` and ``dt_s``; an optional
+    ``na_profile`` (sodium-profile time series) goes to ``wfs_plan_na_profile``.
     """
 
     def __init__(self, cfg, flags=0, batch=None):
@@ -69,6 +70,18 @@ class Plan:
         L.check(self._lib.wfs_plan_path(h, paths), "wfs_plan_path")
         self.paths = list(paths)
         self.device = torch.cuda.current_device()
+        if cfg.get("na_profile"):
+            self.set_na_profile(cfg["na_profile"])
+
+    def set_na_profile(self, profile):
+        """Time-varying multi-peak sodium profile: a list of entries (frame k uses entry
+        k mod len), each a list of (dh_m, fwhm_m, weight) peaks; None or [] restores the
+        sensors' single Gaussians (``wfs_plan_na_profile``; synchronises the device)."""
+        if not profile:
+            L.check(self._lib.wfs_plan_na_profile(self._h, 0, 0, None), "wfs_plan_na_profile")
+            return
+        n_e, n_p, tab = L.na_profile_table(profile)
+        L.check(self._lib.wfs_plan_na_profile(self._h, n_e, n_p, tab), "wfs_plan_na_profile")
 
     # -- lifetime -------------------------------------------------------------------------
     def close(self):

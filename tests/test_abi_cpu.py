@@ -37,12 +37,35 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared_functions()) == set(_lib._PROTOS)
 
 
-def test_struct_layouts_match_header_sizes():
+def test_struct_layouts_match_header_sizes(tmp_path):
+    """The ctypes descriptors have the C compiler's size and field offsets for include/wfs.h."""
+    import shutil
+    import subprocess
     from paper_1608_00386_amd import _lib
     # int64 + 2*int32 + 4*double + float + int32 = 56 bytes
     assert ctypes.sizeof(_lib.LayerDesc) == 56
-    # 6 doubles + 4 int32 + 6 doubles = 112 bytes
-    assert ctypes.sizeof(_lib.SensorDesc) == 112
+    # 6 doubles + 4 int32 + 8 doubles = 128 bytes
+    assert ctypes.sizeof(_lib.SensorDesc) == 128
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = []
+    for ct, cname in ((_lib.LayerDesc, "wfs_layer_desc"), (_lib.SensorDesc, "wfs_sensor_desc")):
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"wfs.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for ct, cname in ((_lib.LayerDesc, "wfs_layer_desc"), (_lib.SensorDesc, "wfs_sensor_desc")):
+        assert int(got[cname]) == ctypes.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(ct, f).offset, (cname, f)
 
 
 def _plan_rc(cfg, batch=1, flags=0, mutate=None):
@@ -77,6 +100,7 @@ def _set(which, key, value):
     (_set("sensor", "obs_d_m", 40.0), "obstruction"),
     (_set("sensor", "valid_frac", 0.0), "valid_frac"),
     (_set("sensor", "src_alt_m", 10e3), "LGS altitude"),
+    (_set("sensor", "tilt_y_rad", math.inf), "tip-tilt"),
     (_set("layer", "boundary", 3), "boundary"),
     (_set("layer", "pitch_m", 0.0), "geometry"),
     (_set("layer", "nx", 1), "grid"),
@@ -109,6 +133,15 @@ def test_calls_reject_null_handles_without_a_device():
     assert L.wfs_plan_footprint(None, 0, None, None) == -1
     assert L.recon_apply(None, 1, 1, None, 1, None, 1, 1.0, 0.0, None) == -1
     assert "null" in L.wfs_last_error().decode()
+    assert L.wfs_plan_na_profile(None, 1, 1, None) == -1
+    assert "null plan" in L.wfs_last_error().decode()
+
+
+def test_na_profile_table_pads_entries_with_zero_weight_peaks():
+    from paper_1608_00386_amd import _lib
+    n_e, n_p, tab = _lib.na_profile_table([[(100.0, 2e3, 1.0)], [(0.0, 1e3, 2.0), (5e3, 0.0, 1.0)]])
+    assert (n_e, n_p) == (2, 2)
+    assert list(tab) == [100.0, 2e3, 1.0, 0.0, 0.0, 0.0, 0.0, 1e3, 2.0, 5e3, 0.0, 1.0]
 
 
 def test_recon_rejects_bad_shapes_without_a_device():
