@@ -208,6 +208,16 @@ def bench_batched(torch, W, steps=20, batch=8):
     n_lgs = sum(1 for s in cfg["sensors"] if np.isfinite(s["src_alt_m"]))
     lgs_subaps = sum(nv for s, nv in zip(cfg["sensors"], plan.n_valid) if np.isfinite(s["src_alt_m"]))
     flops = plan_flops(cfg, plan, batch)
+    # the projection of every sensor and realisation on its own: a graph of wfs_project
+    # launches; algorithmic bytes = the compulsory union over sensors of the layer pixels the
+    # stencils touch (per realisation) + the phase written
+    phase = plan.project(x, step=0)
+    gp = graph_of(torch, lambda i: plan.project(x, step=i, out=phase), 20)
+    gp.replay()
+    _, proj_ms = timed_replay(torch, gp, 20)
+    del gp, phase
+    foot, n_phase = plan.footprint(0)
+    proj_bytes = 4.0 * (foot + n_phase) * batch
     return dict(workload="config2: 6 LGS 80x80 + 3 NGS 2x2 (64 px, N=128), 8 realisations, "
                          "10 layers 1024^2, noise on, %d steps in one wfs_forward_steps graph "
                          "(pipelined as tuned)" % steps,
@@ -218,6 +228,11 @@ def bench_batched(torch, W, steps=20, batch=8):
                 lgs_subaps_per_step=lgs_subaps * batch,
                 achieved_tflops=flops / (gpu_ms * 1e-3) / 1e12,
                 frac_fp32_valu=flops / (gpu_ms * 1e-3) / PEAK_FP32_VALU,
+                projection={"kernel": "wfs_project_kernel", "kernel_ms": proj_ms,
+                            "algorithmic_bytes_per_step": proj_bytes,
+                            "achieved": proj_bytes / (proj_ms * 1e-3) / 1e9,
+                            "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                            "frac": proj_bytes / (proj_ms * 1e-3) / PEAK_HBM},
                 schedule=plan.schedule(), paths=plan.paths)
 
 
@@ -431,6 +446,55 @@ def cpu_baseline(frames=40):
                       f"1 thread, {dt:.1f} s"}
 
 
+def cpu_baseline_configs():
+    """The FP64 oracle on the other workloads, one thread (numpy's FFT is single-threaded):
+    config 2 as one (realisation, step) of its 6 LGS + 3 NGS with noise, extrapolated to a
+    step of 8 realisations and to the 100-step run; the config-3 loss and its gradient (6 LGS,
+    ten 1024^2 layers); the config-4 reconstructor as a numpy FP64 matmul of 8 slope vectors
+    (BLAS thread count stated)."""
+    import oracle
+    out = {}
+    cfg2 = synth.config2(batch=1)
+    x2 = synth.make_batch(cfg2, [0]).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.forward(x2, cfg2, 0, realisations=[0])
+    dt = time.perf_counter() - t0
+    out["config2"] = {"value": 1.0 / (dt * 8), "unit": "steps/s", "cores": 1, "kind": "oracle",
+                      "extrapolated": True,
+                      "sample": f"one (realisation, step) of 6 LGS + 3 NGS in {dt:.2f} s; a step of "
+                                f"8 realisations = 8x, the 100-step run = {800 * dt:.0f} s "
+                                "(extrapolated)"}
+    cfg3 = synth.config3()
+    x3 = synth.make_batch(cfg3, [cfg3["guess_realisation"]]).astype(np.float64)
+    target = synth.random_field((1, oracle.n_slopes(cfg3)), seed=7).astype(np.float64)
+    t0 = time.perf_counter()
+    s3, _ = oracle.forward(x3, cfg3, 0, noise=False)
+    oracle.adjoint(x3, cfg3, 0, 2.0 * (s3 - target))
+    dt = time.perf_counter() - t0
+    out["config3"] = {"value": 1.0 / dt, "unit": "loss+gradient evaluations/s", "cores": 1,
+                      "kind": "oracle",
+                      "sample": f"one loss + gradient over 6 LGS and ten 1024^2 layers, {dt:.2f} s"}
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
+        blas_threads = blas[0] if blas else None
+    except Exception:
+        blas_threads = None
+    M, N = synth.configs.N_ACT_ROWS, 55608
+    R = synth.make_reconstructor(M, N).astype(np.float64)
+    S = synth.random_field((8, N), seed=11).astype(np.float64)
+    oracle.recon(R[:64], S)  # warm BLAS
+    t0 = time.perf_counter()
+    oracle.recon(R, S)
+    dt = time.perf_counter() - t0
+    del R
+    out["config4_recon"] = {"value": 1.0 / dt, "unit": "recon_apply/s", "cores": blas_threads,
+                            "kind": "oracle",
+                            "sample": f"C = S R^T, R 5400 x 55608 FP64, 8 slope vectors, numpy "
+                                      f"matmul with {blas_threads} BLAS threads, {dt * 1e3:.0f} ms"}
+    return out
+
+
 _POOL_X = None
 
 
@@ -543,7 +607,7 @@ def main():
               "multi-GPU sharding is a design note, not a launched path.", file=sys.stderr)
         sys.exit(2)
 
-    cpu = cpu_pool = None
+    cpu = cpu_pool = cpu_cfgs = None
     if not args.quick and not args.no_cpu and args.profile_frames == 0:
         # the oracle baselines run first: the pool forks before anything touches the GPU
         log("[bench] cpu baseline (oracle, 1 thread) ...")
@@ -553,6 +617,11 @@ def main():
             cpu_pool = cpu_baseline_pool()
         except Exception as e:  # report, do not hide
             cpu_pool = {"error": repr(e)}
+        log("[bench] cpu baseline (oracle) of configs 2-4 ...")
+        try:
+            cpu_cfgs = cpu_baseline_configs()
+        except Exception as e:
+            cpu_cfgs = {"error": repr(e)}
 
     import torch
     import paper_1608_00386_amd as W
@@ -578,9 +647,10 @@ def main():
     frames_per_s = args.steps / r1["wall"]
     spot_flops = plan_flops(cfg1, r1["plan"])
     flops = spot_flops
-    # dominant kernel: the spot launch, charged with the spot stage's FLOPs, plus the
-    # projection's when its waves project their own pixels (staged footprint); a separate
-    # projection kernel's bytes are reported under "projection".
+    # dominant kernel: the spot launch, charged with the spot stage's algorithmic FLOPs only
+    # (96,020 per LGS subaperture); when its waves also project their own pixels (staged
+    # footprint) that work is reported beside it (projection_flop_per_frame), not added; a
+    # separate projection kernel's bytes are reported under "projection".
     #   one launch (staged footprint): the K frames are one dispatch; per frame, the replayed
     #     graph's time divided by K;
     #   pipelined (split): one launch per frame that forms the spots of step k and projects
@@ -609,8 +679,7 @@ def main():
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = "wfs_forward_kernel<10, gather> (per-pixel gather)"
         traffic_key = "wfs_forward_kernel<10, 0, false, false>"
-    if field == "footprint" or frames == "one_launch":
-        flops += proj_flops(cfg1, r1["plan"])  # the spot waves also project their pixels
+    in_wave_proj = field == "footprint" or frames == "one_launch"
     achieved = flops / (kern_ms * 1e-3)
     foot, n_phase = r1["plan"].footprint(0)
     proj_bytes = 4.0 * (foot + n_phase)  # each layer pixel read once, each phase pixel written
@@ -638,6 +707,8 @@ def main():
                      "kernel": kern_name,
                      "kernel_ms": kern_ms,
                      "algorithmic_flop_per_frame": flops,
+                     "projection_flop_per_frame": proj_flops(cfg1, r1["plan"]),
+                     "projection_in_launch": in_wave_proj,
                      "frames_per_launch": args.steps if frames == "one_launch" else 1,
                      "spots_only_kernel_ms": r1["spots_ms"],
                      "spots_only_frac": spot_flops / (r1["spots_ms"] * 1e-3) / PEAK_FP32_VALU,
@@ -697,6 +768,7 @@ def main():
         if cpu is not None:
             out["cpu_baseline"] = cpu
             out["cpu_baseline_all_cores"] = cpu_pool
+            out["cpu_baseline_other_configs"] = cpu_cfgs
     print(json.dumps(out), flush=True)
 
 

@@ -202,10 +202,24 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
  *   frames (FFT-path sensors, which read the projected phase, then run frame by frame on
  *   the plan's second stream beside it).  Fields 1 and 2 and frames 0-2 give the same bits;
  *   field 0 its own.  Field 2 for single frames needs a plan without FFT-path sensors.
- *   xcd_remap = 1 when blocks are renumbered so neighbouring tasks share an XCD.  Any output
- *   pointer may be NULL.
+ *   xcd_remap = 1 when blocks are renumbered so neighbouring tasks share an XCD.
+ *   fft_launch (plans with both paths, fields 0 and 1): 0 = the FFT-path blocks run as a
+ *   launch of their own on the plan's second stream, concurrently; 1 = they are blocks of
+ *   the same launch as the lag-domain blocks (and, pipelined, the next step's projection:
+ *   one launch per step).  All choices give the same bits.  Any output pointer may be NULL.
  */
-int wfs_plan_schedule(wfs_plan_t plan, int32_t* field, int32_t* frames, int32_t* xcd_remap);
+int wfs_plan_schedule(wfs_plan_t plan, int32_t* field, int32_t* frames, int32_t* xcd_remap,
+                      int32_t* fft_launch);
+
+/*
+ * wfs_plan_set_schedule -- pin a launch schedule (values as wfs_plan_schedule reports them;
+ *   -1 keeps a choice).  WFS_EUNSUPPORTED when the plan cannot run it: field 1 or frames 1
+ *   without a phase buffer, field 2 or frames 2 where a lag-domain sensor cannot stage its
+ *   footprint, field 2 for single frames with FFT-path sensors, frames 1 or 2 with field 0.
+ *   Host only; no device work.
+ */
+int wfs_plan_set_schedule(wfs_plan_t plan, int32_t field, int32_t frames, int32_t xcd_remap,
+                          int32_t fft_launch);
 
 /*
  * wfs_plan_footprint -- algorithmic read footprint of the projection at time step `step`:

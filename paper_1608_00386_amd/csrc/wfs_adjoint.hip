@@ -11,7 +11,10 @@
 // stencil weights (subaperture fields recomputed).  Two ways to form it:
 //   gather (default): g_psi (kappa applied) goes to a phase-layout buffer, then one thread per
 //     layer pixel sums, sensor by sensor, the stencil weights of the pupil pixels whose
-//     forward taps touch it (the same FP64 taps as the forward) -- bitwise deterministic;
+//     forward taps touch it (the same FP64 taps as the forward) -- bitwise deterministic.
+//     Layers whose pupil and layer pitches are within about a factor of two read those
+//     pupil pixels from per-step lists (one small kernel per call builds them, the gather
+//     then needs no FP64 and no searches); the others search their candidates per tile;
 //   atomic scatter: each pupil pixel adds its four weighted taps with FP32 atomics.
 #include "wfs_otf.h"
 
@@ -416,13 +419,219 @@ __global__ __launch_bounds__(kBlock) void wfs_adjoint_gather_kernel(GatherParams
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Table-driven gather (layers whose inverse stencil lists are short: pupil and layer pitches
+// within a factor of about two, one periodic image per layer pixel).
+//
+// Taps kernel, thread per (segment, layer index i): the pupil indices whose forward taps (the
+// same FP64 coordinate and make_tap as the projection, bit for bit) touch i, in increasing
+// order, with the weight i has in their stencil.  Candidates: for every periodic image m, the
+// indices whose coordinate lies in [i - 1 + m n, i + 1 + m n), with a margin of one index.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void wfs_adjoint_taps_kernel(GatherTabParams g) {
+  const FwdParams& p = g.f;
+  const AdjSeg sg = g.segs[blockIdx.y];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= sg.n) return;
+  const DevLayer L = p.lay[sg.l];
+  const DevAffine A = p.aff[(int64_t)sg.s * p.n_layers + sg.l];
+  const int npup = p.sen[sg.s].n_pup;
+  const double stepd = (double)current_step(p);
+  const bool ax = sg.axis == 0;
+  const double a = ax ? A.ax : A.ay, b0 = ax ? A.bx0 : A.by0, db = ax ? A.dbx : A.dby;
+  const double inv_a = ax ? A.inv_ax : A.inv_ay;
+  const int32_t n = ax ? L.nx : L.ny;
+  const double inv_n = ax ? L.inv_nx : L.inv_ny;
+  const double b = b0 + stepd * db;
+  int m_lo, m_hi;
+  image_range(a, b, n, inv_n, npup, i, i, L.boundary, m_lo, m_hi);
+  int2 out[kAdjKI];
+#pragma unroll
+  for (int k = 0; k < kAdjKI; ++k) out[k] = make_int2(-1, 0);
+  int cnt = 0;
+  for (int m = m_lo; m <= m_hi; ++m) {
+    int lo, hi;
+    const double base = (double)i + (double)m * (double)n;
+    cand_range(inv_a, b, base, base, npup, lo, hi);
+    for (int c = lo; c <= hi; ++c) {
+      const double w = fma(a, (double)c, b0) + stepd * db;
+      const Tap t = make_tap(w, n, inv_n, L.boundary, 1);
+      const float wt = (t.i0 == i ? t.w0 : 0.0f) + (t.i1 == i ? t.w1 : 0.0f);
+      if (wt != 0.0f && cnt < kAdjKI) {
+#pragma unroll
+        for (int k = 0; k < kAdjKI; ++k)
+          if (k == cnt) out[k] = make_int2(c, __float_as_int(wt));
+        ++cnt;
+      }
+    }
+  }
+  int2* dst = g.tab + sg.off + (int64_t)i * kAdjKI;
+#pragma unroll
+  for (int k = 0; k < kAdjKI; ++k) dst[k] = out[k];
+}
+
+// Gather kernel for tabled layers (one periodic image per layer pixel: for every sensor the
+// pupil rows touching a run of layer rows are consecutive, and so are the pupil columns of
+// one layer column).  Block = (realisation, tabled layer, 64 x 64 tile); wave = 64 layer
+// columns (one per lane) x kG2R rows, accumulated in the wave's own LDS rows (the waves never
+// wait for each other).  For every sensor in order, each pupil row r whose taps reach the
+// wave's rows is reduced along the lane's column list,
+//     T = sum_j wc_j g[r][cf + j],
+// and added to the (at most two) layer rows of its forward row tap with that tap's weights
+// (the same FP64 coordinate and make_tap as the projection).  Fixed order of every sum:
+// bitwise deterministic.
+constexpr int kG2R = 16;
+constexpr int kG2TH = kG2R * kWavesPerBlock;
+constexpr int kG2MaxPR = 64;  // pupil rows per sensor and wave (above: direct per-row lists)
+constexpr int kG2Chunk = 8;   // pupil rows whose loads are in flight together
+
+__global__ __launch_bounds__(kBlock) void wfs_adjoint_gather_tab_kernel(GatherTabParams g) {
+  __shared__ float acc_s[kWavesPerBlock][kG2R][kWave];
+  __shared__ float4 rtap_s[kWavesPerBlock][kG2MaxPR];  // (row - y0 of tap 0, of tap 1, w0, w1)
+  const FwdParams& p = g.f;
+  const int nl = p.n_layers;
+  const int per_real = g.blk_start[nl];
+  const int b = blockIdx.x / per_real;
+  const int rb = blockIdx.x - b * per_real;
+  int l = 0;
+  while (l + 1 < nl && rb >= g.blk_start[l + 1]) ++l;  // block-uniform
+  const DevLayer L = cload(p.lay, l);
+  const int tiles_x = (L.nx + kWave - 1) / kWave;
+  const int tile = rb - g.blk_start[l];
+  const int tyi = tile / tiles_x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int x = (tile - tyi * tiles_x) * kWave + lane;
+  const int y0 = tyi * kG2TH + wave * kG2R;
+  const int nrows = min(kG2R, L.ny - y0);  // wave-uniform, may be <= 0
+  if (nrows <= 0) return;                  // no block-wide barrier below
+  const bool xin = x < L.nx;
+  float* acc = &acc_s[wave][0][0];
+  float4* rtap = rtap_s[wave];
+#pragma unroll
+  for (int yy = 0; yy < kG2R; ++yy) acc[yy * kWave + lane] = 0.0f;
+  const float* gb = g.gpsi + (int64_t)b * p.pupil_per_real;
+  const double stepd = (double)current_step(p);
+  const int xl = xin ? x : 0;
+  // the lane's column list of a sensor: consecutive pupil columns from its first entry, with
+  // their weights (0 past the list's end); the next sensor's list is loaded while this one's
+  // rows are summed
+  int2 ce[kAdjKI];
+  {
+    const int2* e0 = g.tab + g.tab_off[l] + (int64_t)xl * kAdjKI;
+#pragma unroll
+    for (int k = 0; k < kAdjKI; ++k) ce[k] = e0[k];
+  }
+  for (int s = 0; s < p.n_sensors; ++s) {
+    float wc[kAdjKI];
+    int cf = 0, ncol = 0;
+#pragma unroll
+    for (int k = 0; k < kAdjKI; ++k) {
+      const bool ok = xin && ce[k].x >= 0;
+      if (k == 0) cf = ok ? ce[k].x : 0;
+      wc[k] = ok ? __int_as_float(ce[k].y) : 0.0f;
+      if (__builtin_amdgcn_ballot_w64(ok) != 0) ncol = k + 1;  // wave-uniform
+    }
+    if (s + 1 < p.n_sensors) {
+      const int2* e1 = g.tab + g.tab_off[(int64_t)(s + 1) * nl + l] + (int64_t)xl * kAdjKI;
+#pragma unroll
+      for (int k = 0; k < kAdjKI; ++k) ce[k] = e1[k];
+    }
+    const DevSensor S = cload(p.sen, s);
+    const DevAffine A = cload(p.aff, (int64_t)s * nl + l);
+    const float* gs = gb + S.pupil_off;
+    const int npup = S.n_pup;
+    // pupil rows whose taps can reach the wave's rows, every periodic image (FP64, the
+    // candidate rule of the taps kernel: one index of slack on each side)
+    const double by = A.by0 + stepd * A.dby;
+    int m_lo, m_hi;
+    image_range(A.ay, by, L.ny, L.inv_ny, npup, y0, y0 + nrows - 1, L.boundary, m_lo, m_hi);
+    int r_lo = 0x7FFFFFFF, r_hi = -1;
+    for (int m = m_lo; m <= m_hi; ++m) {
+      int lo, hi;
+      const double base = (double)m * (double)L.ny;
+      cand_range(A.inv_ay, by, base + y0, base + y0 + nrows - 1, npup, lo, hi);
+      if (lo <= hi) {
+        r_lo = min(r_lo, lo);
+        r_hi = max(r_hi, hi);
+      }
+    }
+    if (r_hi < r_lo || ncol == 0) continue;  // wave-uniform: no contribution
+    const int nr = r_hi - r_lo + 1;
+    if (nr <= kG2MaxPR) {
+      // forward row taps of those pupil rows, relative to y0
+      if (lane < nr) {
+        const double v = fma(A.ay, (double)(r_lo + lane), A.by0) + stepd * A.dby;
+        const Tap t = make_tap(v, L.ny, L.inv_ny, L.boundary, 1);
+        rtap[lane] = make_float4(__int_as_float(t.i0 - y0), __int_as_float(t.i1 - y0), t.w0,
+                                 t.w1);
+      }
+      wave_sync();
+      int cq[kAdjKI];
+#pragma unroll
+      for (int q = 0; q < kAdjKI; ++q) cq[q] = min(cf + q, npup - 1);
+      const float* gr0 = gs + (int64_t)r_lo * npup;
+      // chunks of kG2Chunk pupil rows: every load of a chunk in flight before its sums
+      for (int j0 = 0; j0 < nr; j0 += kG2Chunk) {
+        float v[kG2Chunk][kAdjKI];
+#pragma unroll
+        for (int jj = 0; jj < kG2Chunk; ++jj) {
+          const float* gr = gr0 + (int64_t)min(j0 + jj, nr - 1) * npup;
+#pragma unroll
+          for (int q = 0; q < kAdjKI; ++q) v[jj][q] = q < ncol ? gr[cq[q]] : 0.0f;
+        }
+#pragma unroll
+        for (int jj = 0; jj < kG2Chunk; ++jj) {
+          if (j0 + jj >= nr) break;
+          float t = 0.0f;
+#pragma unroll
+          for (int q = 0; q < kAdjKI; ++q)
+            if (q < ncol) t = fmaf(wc[q], v[jj][q], t);
+          const float4 tp = rtap[j0 + jj];  // wave-uniform (broadcast)
+          const int r0 = __builtin_amdgcn_readfirstlane(__float_as_int(tp.x));
+          const int r1 = __builtin_amdgcn_readfirstlane(__float_as_int(tp.y));
+          if (r0 >= 0 && r0 < nrows)
+            acc[r0 * kWave + lane] = fmaf(tp.z, t, acc[r0 * kWave + lane]);
+          if (r1 >= 0 && r1 < nrows)
+            acc[r1 * kWave + lane] = fmaf(tp.w, t, acc[r1 * kWave + lane]);
+        }
+      }
+      wave_sync();  // the next sensor rewrites the taps
+    } else {
+      // the wave's rows take pupil rows from two periodic images: each layer row walks its
+      // own list
+      const int2* rows = g.tab + g.tab_off[(int64_t)s * nl + l] + (int64_t)L.nx * kAdjKI;
+      for (int yy = 0; yy < nrows; ++yy) {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kAdjKI; ++k) {
+          const int2 e = rows[(int64_t)(y0 + yy) * kAdjKI + k];
+          if (e.x < 0) break;
+          const float* gr = gs + (int64_t)e.x * npup;
+          float t = 0.0f;
+#pragma unroll
+          for (int q = 0; q < kAdjKI; ++q)
+            if (q < ncol) t = fmaf(wc[q], gr[min(cf + q, npup - 1)], t);
+          a = fmaf(__int_as_float(e.y), t, a);
+        }
+        acc[yy * kWave + lane] += a;
+      }
+    }
+  }
+  if (xin) {
+    float* out = g.grad + (int64_t)b * p.layer_stride + L.offset + x;
+    for (int yy = 0; yy < nrows; ++yy)
+      out[(int64_t)(y0 + yy) * L.nx] = acc[yy * kWave + lane] * L.weight;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void zero_kernel(float* x, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) x[i] = 0.0f;
 }
 
 template <int NS>
-static hipError_t launch_adj(AdjParams a, hipStream_t st) {
+static hipError_t launch_adj(AdjParams a, bool clear_grad, hipStream_t st) {
   // atomic mode accumulates into the gradient; gather mode into the phase-gradient images
   float* z = a.gpsi ? a.gpsi : a.grad_layers;
   const int64_t n = a.gpsi ? a.f.pupil_per_real * a.f.batch : a.f.layer_stride * a.f.batch;
@@ -430,7 +639,9 @@ static hipError_t launch_adj(AdjParams a, hipStream_t st) {
   hipLaunchKernelGGL(zero_kernel, dim3(zb > 0 ? zb : 1), dim3(kBlock), 0, st, z, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (a.gpsi) {  // the gather writes every grid pixel; clear the rest of the gradient buffer
+  // the gather writes every grid pixel; the rest of the gradient buffer (gaps between the
+  // grids inside the stride) is cleared only when there is such a gap
+  if (a.gpsi && clear_grad) {
     const int64_t ng = a.f.layer_stride * a.f.batch;
     const int zg = (int)std::min<int64_t>((ng + kBlock - 1) / kBlock, 8192);
     hipLaunchKernelGGL(zero_kernel, dim3(zg > 0 ? zg : 1), dim3(kBlock), 0, st, a.grad_layers,
@@ -469,19 +680,46 @@ hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* g
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st) {
+hipError_t launch_adjoint_gather_tab(const FwdParams& f, const float* gpsi, float* grad,
+                                     int2* tab, const AdjSeg* segs, int n_segs, int max_n,
+                                     const int64_t* tab_off, const int32_t* blk_start,
+                                     hipStream_t st) {
+  if (n_segs == 0) return hipSuccess;
+  GatherTabParams g;
+  g.f = f;
+  g.gpsi = gpsi;
+  g.grad = grad;
+  g.tab = tab;
+  g.segs = segs;
+  g.tab_off = tab_off;
+  for (int l = 0; l <= f.n_layers; ++l) g.blk_start[l] = blk_start[l];
+  hipLaunchKernelGGL(wfs_adjoint_taps_kernel, dim3((max_n + kBlock - 1) / kBlock, n_segs),
+                     dim3(kBlock), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (int64_t)blk_start[f.n_layers] * f.batch;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wfs_adjoint_gather_tab_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                     g);
+  return hipGetLastError();
+}
+
+int adj_tab_rows() { return kG2TH; }
+
+hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, hipStream_t st) {
   switch (ns) {
-    case 2: return launch_adj<2>(a, st);
-    case 3: return launch_adj<3>(a, st);
-    case 4: return launch_adj<4>(a, st);
-    case 5: return launch_adj<5>(a, st);
-    case 6: return launch_adj<6>(a, st);
-    case 7: return launch_adj<7>(a, st);
-    case 8: return launch_adj<8>(a, st);
-    case 9: return launch_adj<9>(a, st);
-    case 10: return launch_adj<10>(a, st);
-    case 11: return launch_adj<11>(a, st);
-    case 12: return launch_adj<12>(a, st);
+    case 2: return launch_adj<2>(a, clear_grad, st);
+    case 3: return launch_adj<3>(a, clear_grad, st);
+    case 4: return launch_adj<4>(a, clear_grad, st);
+    case 5: return launch_adj<5>(a, clear_grad, st);
+    case 6: return launch_adj<6>(a, clear_grad, st);
+    case 7: return launch_adj<7>(a, clear_grad, st);
+    case 8: return launch_adj<8>(a, clear_grad, st);
+    case 9: return launch_adj<9>(a, clear_grad, st);
+    case 10: return launch_adj<10>(a, clear_grad, st);
+    case 11: return launch_adj<11>(a, clear_grad, st);
+    case 12: return launch_adj<12>(a, clear_grad, st);
     default: return hipErrorInvalidValue;
   }
 }

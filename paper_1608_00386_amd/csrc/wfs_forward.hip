@@ -47,14 +47,14 @@ static hipError_t launch_forward_ns(const FwdParams& p, int ns, hipStream_t st) 
   }
 }
 
-// FFT-path and lag-domain subapertures go in two launches on the same stream: the FFT path's
-// registers and LDS would otherwise set the occupancy of every lag-domain wavefront.
-// The FFT-path blocks (large fields, one workgroup each, 48 KB of LDS) and the lag-domain
-// blocks go to separate launches, so that the lag-domain waves keep their own occupancy; with
-// a side stream the FFT-path launch runs concurrently (fork after everything already queued
-// on st, join before anything queued after this call).
+// FFT-path and lag-domain subapertures: by default in two launches, since the FFT path's
+// registers and LDS would otherwise set the occupancy of every lag-domain wavefront.  The
+// FFT-path blocks (large fields, one workgroup each, 48 KB of LDS) and the lag-domain blocks
+// go to separate launches, so that the lag-domain waves keep their own occupancy; with a side
+// stream the FFT-path launch runs concurrently (fork after everything already queued on st,
+// join before anything queued after this call).  With fft_inline they share one launch.
 hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const SideStream* side) {
-  if (p.fft_blocks == 0 || (p.otf_blocks == 0 && p.proj_blocks == 0))
+  if (p.fft_inline || p.fft_blocks == 0 || (p.otf_blocks == 0 && p.proj_blocks == 0))
     return launch_forward_ns(p, ns, st);
   FwdParams a = p;
   a.otf_blocks = 0;

@@ -22,9 +22,14 @@ int project_lds_bytes(int n_layers);
 int project_strip();
 int project_rows();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
-hipError_t launch_adjoint(const AdjParams& a, int ns, hipStream_t st);
+hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, hipStream_t st);
 hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* grad,
                                  const int32_t* blk_start, hipStream_t st);
+hipError_t launch_adjoint_gather_tab(const FwdParams& f, const float* gpsi, float* grad,
+                                     int2* tab, const AdjSeg* segs, int n_segs, int max_n,
+                                     const int64_t* tab_off, const int32_t* blk_start,
+                                     hipStream_t st);
+int adj_tab_rows();
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B,
                              int64_t* floats);
@@ -117,6 +122,15 @@ struct wfs_plan_s {
   int64_t otf_tasks = 0, fft_tasks = 0;
   int adj_lds_per_wave = 0;
   std::vector<int32_t> gather_blk;  // adjoint gather: first tile of each layer (+ total)
+  // table-driven adjoint gather (layers whose inverse stencil lists are short): first tile of
+  // each such layer (+ total), the segments of the list tables, and the tables themselves
+  std::vector<int32_t> gather_tab_blk;
+  int adj_nseg = 0, adj_maxn = 0;
+  int64_t adj_ent = 0;
+  const AdjSeg* d_adj_segs = nullptr;
+  const int64_t* d_adj_tab_off = nullptr;
+  int2* d_adj_tab = nullptr;  // allocated on the first gather call, with d_gimg
+  bool adj_clear_grad = true;  // the layer grids leave gaps inside the stride
   int lds_split = 0, lds_fused = 0;  // LDS bytes per lag-domain wave, per schedule
   int lds_split_otf = 0, lds_fused_otf = 0;  // same, in a launch without FFT-path blocks
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
@@ -531,6 +545,62 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       }
     }  // FFT-path sensors stage no footprint: they read the projected phase
   }
+  // Adjoint gather by tables: a layer qualifies when, for every sensor and axis, the pupil
+  // footprint meets each layer index in one periodic image only and at most kAdjKI pupil
+  // indices touch it: floor(2 / a) + 1 (the coordinates a c + b in a window of two layer
+  // pixels), one more for the rounding of the FP64 coordinates.
+  std::vector<uint8_t> adj_tabled(n_layers, 1);
+  std::vector<AdjSeg> adj_segs;
+  std::vector<int64_t> adj_tab_off((size_t)n_sensors * n_layers, -1);
+  for (int l = 0; l < n_layers; ++l) {
+    const wfs_layer_desc& L = layers[l];
+    for (int s = 0; s < n_sensors && adj_tabled[l]; ++s)
+      for (int axis = 0; axis < 2; ++axis) {
+        const DevAffine& A = aff[(size_t)s * n_layers + l];
+        const double a = axis ? A.ay : A.ax;
+        const int n = axis ? L.ny : L.nx;
+        // one periodic image per layer pixel (the gather takes the pupil rows and columns
+        // of a run of layer pixels as consecutive)
+        const double images =
+            L.boundary ? 1.0 : std::floor((a * (ds[s].n_pup - 1) + 2.0) / n) + 1.0;
+        const double need = std::floor(2.0 / a) + 2.0;
+        if (!(a > 0) || images != 1.0 || !(need <= kAdjKI)) adj_tabled[l] = 0;
+      }
+  }
+  int64_t adj_ent = 0;
+  for (int l = 0; l < n_layers; ++l) {
+    if (!adj_tabled[l]) continue;
+    for (int s = 0; s < n_sensors; ++s) {
+      adj_tab_off[(size_t)s * n_layers + l] = adj_ent;
+      adj_segs.push_back(AdjSeg{adj_ent, layers[l].nx, s, l, 0});
+      adj_ent += (int64_t)layers[l].nx * kAdjKI;
+      adj_segs.push_back(AdjSeg{adj_ent, layers[l].ny, s, l, 1});
+      adj_ent += (int64_t)layers[l].ny * kAdjKI;
+      P->adj_maxn = std::max(P->adj_maxn, std::max(layers[l].nx, layers[l].ny));
+    }
+  }
+  P->adj_ent = adj_ent;
+  P->adj_nseg = (int)adj_segs.size();
+  if (adj_segs.size() > 65535) {  // one grid row per segment
+    std::fill(adj_tabled.begin(), adj_tabled.end(), 0);
+    adj_segs.clear();
+    std::fill(adj_tab_off.begin(), adj_tab_off.end(), -1);
+    P->adj_nseg = 0;
+    P->adj_ent = 0;
+  }
+  {  // do the grids cover the stride without gaps (then the gather writes every float)?
+    std::vector<std::pair<int64_t, int64_t>> ext;
+    for (int l = 0; l < n_layers; ++l)
+      ext.emplace_back(layers[l].offset, layers[l].offset + (int64_t)layers[l].nx * layers[l].ny);
+    std::sort(ext.begin(), ext.end());
+    int64_t end = 0;
+    bool gap = false;
+    for (const auto& e2 : ext) {
+      if (e2.first > end) gap = true;
+      end = std::max(end, e2.second);
+    }
+    P->adj_clear_grad = gap || end < layer_stride;
+  }
   P->hsen = ds;
   P->n_slopes = slope_off;
   P->n_valid_total = aux_off;
@@ -563,6 +633,9 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   const size_t o_pfft = push_table(blob, desc_fft);
   std::vector<int64_t> step0(1, 0);
   const size_t o_step = push_table(blob, step0);
+  if (adj_segs.empty()) adj_segs.push_back(AdjSeg{});
+  const size_t o_adjseg = push_table(blob, adj_segs);
+  const size_t o_adjoff = push_table(blob, adj_tab_off);
   blob.resize((blob.size() + 255) & ~size_t(255));
 
   hipError_t e = hipGetDevice(&P->device);
@@ -594,6 +667,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   P->proj_fft.desc = reinterpret_cast<const int2*>(P->d_blob + o_pfft);
   P->proj_fft.per_real = (int32_t)desc_fft.size();
   P->d_step = reinterpret_cast<int64_t*>(P->d_blob + o_step);
+  P->d_adj_segs = reinterpret_cast<const AdjSeg*>(P->d_blob + o_adjseg);
+  P->d_adj_tab_off = reinterpret_cast<const int64_t*>(P->d_blob + o_adjoff);
   b.step_dev = P->d_step;
   b.layer_stride = layer_stride;
   b.n_layers = n_layers;
@@ -613,13 +688,19 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.pupil_per_real = P->pupil_per_real;
   b.phase_in = nullptr;
   {
-    int64_t acc = 0;
+    int64_t acc = 0, acc_tab = 0;
+    const int th = adj_tab_rows();
     for (int l = 0; l < n_layers; ++l) {
       P->gather_blk.push_back((int32_t)acc);
-      // adjoint gather tiles of 64 x 16 layer pixels
-      acc += (int64_t)((layers[l].nx + 63) / 64) * ((layers[l].ny + 15) / 16);
+      P->gather_tab_blk.push_back((int32_t)acc_tab);
+      // adjoint gather tiles: 64 x th layer pixels for tabled layers, 64 x 16 for the others
+      if (adj_tabled[l])
+        acc_tab += (int64_t)((layers[l].nx + 63) / 64) * ((layers[l].ny + th - 1) / th);
+      else
+        acc += (int64_t)((layers[l].nx + 63) / 64) * ((layers[l].ny + 15) / 16);
     }
     P->gather_blk.push_back((int32_t)acc);
+    P->gather_tab_blk.push_back((int32_t)acc_tab);
   }
   P->otf_tasks = (int64_t)b.otf.per_real * batch;
   P->fft_tasks = (int64_t)b.fft.per_real * batch;
@@ -734,6 +815,7 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (P->d_phase) (void)hipFree(P->d_phase);
   if (P->d_gimg) (void)hipFree(P->d_gimg);
   if (P->d_na) (void)hipFree(P->d_na);
+  if (P->d_adj_tab) (void)hipFree(P->d_adj_tab);
   for (float4* q : P->na_retired) (void)hipFree(q);
   if (P->side.join) (void)hipEventDestroy(P->side.join);
   if (P->side.fork) (void)hipEventDestroy(P->side.fork);
@@ -977,12 +1059,47 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
   return WFS_OK;
 }
 
-int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xcd_remap) {
+int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xcd_remap,
+                      int32_t* fft_launch) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_schedule: null plan");
   const bool split = P->split && P->d_phase;
   if (field) *field = P->foot ? 2 : (split ? 1 : 0);
   if (frames) *frames = P->frames;
   if (xcd_remap) *xcd_remap = P->base.xcd_remap;
+  if (fft_launch) *fft_launch = P->base.fft_inline;
+  return WFS_OK;
+}
+
+int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t xcd_remap,
+                          int32_t fft_launch) {
+  if (!P) return fail(WFS_EINVAL, "wfs_plan_set_schedule: null plan");
+  if (field < -1 || field > 2 || frames < -1 || frames > 2 || xcd_remap < -1 ||
+      xcd_remap > 1 || fft_launch < -1 || fft_launch > 1)
+    return fail(WFS_EINVAL, "wfs_plan_set_schedule: field=%d frames=%d xcd_remap=%d "
+                "fft_launch=%d out of range", field, frames, xcd_remap, fft_launch);
+  const int cur_field = P->foot ? 2 : ((P->split && P->d_phase) ? 1 : 0);
+  const int f = field < 0 ? cur_field : field;
+  const int fr = frames < 0 ? P->frames : frames;
+  const bool phase_ok = P->d_phase && P->proj_lds <= 65536;
+  if (f == 1 && !phase_ok)
+    return fail(WFS_EUNSUPPORTED, "wfs_plan_set_schedule: no phase buffer for the split field");
+  if (f == 2 && !(P->foot_ok && P->fft_tasks == 0))
+    return fail(WFS_EUNSUPPORTED,
+                "wfs_plan_set_schedule: a sensor cannot take the footprint field for single "
+                "frames");
+  if (fr == 1 && !phase_ok)
+    return fail(WFS_EUNSUPPORTED, "wfs_plan_set_schedule: no phase buffer for pipelined frames");
+  if (fr == 2 && !P->foot_ok)
+    return fail(WFS_EUNSUPPORTED,
+                "wfs_plan_set_schedule: a lag-domain sensor cannot stage its footprint");
+  if (fr != 0 && f == 0)
+    return fail(WFS_EUNSUPPORTED,
+                "wfs_plan_set_schedule: frames in a row need the split or footprint field");
+  P->split = f == 1 ? 1 : (f == 0 ? 0 : P->split);
+  P->foot = f == 2;
+  P->frames = fr;
+  if (xcd_remap >= 0) P->base.xcd_remap = xcd_remap;
+  if (fft_launch >= 0) P->base.fft_inline = fft_launch;
   return WFS_OK;
 }
 
@@ -1099,13 +1216,20 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   // gather mode (default): phase gradients into the second phase buffer, then the layer
   // gather; atomic mode: each pupil pixel scatters its taps
   const bool gather = !(P->flags & WFS_FLAG_ADJOINT_ATOMIC) &&
-                      P->pupil_per_real < (1LL << 31) - 1;
+                      P->pupil_per_real < (1LL << 30);  // 32-bit byte offsets in the images
   if (gather && !P->d_gimg) {  // phase-gradient images, allocated on the first gather call
     hipError_t ea = hipMalloc((void**)&P->d_gimg,
                               sizeof(float) * (size_t)P->pupil_per_real * P->batch);
     if (ea != hipSuccess) {
       P->d_gimg = nullptr;
       return hip_fail(ea, "wfs_adjoint: phase-gradient images");
+    }
+  }
+  if (gather && P->adj_ent > 0 && !P->d_adj_tab) {  // and the gather's stencil lists
+    hipError_t ea = hipMalloc((void**)&P->d_adj_tab, sizeof(int2) * (size_t)P->adj_ent);
+    if (ea != hipSuccess) {
+      P->d_adj_tab = nullptr;
+      return hip_fail(ea, "wfs_adjoint: stencil lists");
     }
   }
   a.gpsi = gather ? P->d_gimg : nullptr;
@@ -1118,9 +1242,13 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
     a.f.phase_in = P->d_phase;
     a.f.otf_from_phase = 1;
   }
-  e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream);
+  e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, P->adj_clear_grad, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: launch");
   if (gather) {
+    e = launch_adjoint_gather_tab(a.f, P->d_gimg, grad_layers, P->d_adj_tab, P->d_adj_segs,
+                                  P->adj_nseg, P->adj_maxn, P->d_adj_tab_off,
+                                  P->gather_tab_blk.data(), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: tabled gather launch");
     e = launch_adjoint_gather(a.f, P->d_gimg, grad_layers, P->gather_blk.data(),
                               (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: gather launch");

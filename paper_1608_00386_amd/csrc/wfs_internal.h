@@ -135,6 +135,7 @@ struct FwdParams {
   int32_t lds_per_wave;     // bytes (lag-domain waves, or a quarter of an FFT workgroup)
   int32_t lds_per_wave_otf; // bytes when the launch holds no FFT-path blocks
   int32_t otf_from_phase;   // lag-domain field source: 0 gather, 1 phase_in (split), 2 footprint
+  int32_t fft_inline;       // host side: FFT-path blocks in the same launch as the others
   TaskTable otf;
   TaskTable fft;
   // projection blocks of one realisation: (first pupil row | column strip << 16, sensor)
@@ -170,6 +171,28 @@ struct AdjParams {
   const float* fwd_aux;     // or null
   float* grad_layers;       // [B][layer_stride]
   float* gpsi;              // gather mode: [B][pupil_per_real] phase-gradient images, or null
+};
+
+// Table-driven gather of the layer gradient.  For a (sensor, layer, axis) whose inverse
+// stencil lists fit kAdjKI entries, entry k of layer index i is (pupil index, weight) of the
+// k-th pupil index whose forward taps touch i (increasing pupil index; pupil index -1 ends a
+// shorter list).  One segment per (sensor, layer, axis) of such layers: its first entry, its
+// layer size and who it is.
+constexpr int kAdjKI = 4;
+struct AdjSeg {
+  int64_t off;
+  int32_t n, s, l, axis;
+};
+
+struct GatherTabParams {
+  FwdParams f;
+  const float* gpsi;         // [B][pupil_per_real] pupil-frame images, kappa applied
+  float* grad;               // [B][layer_stride]
+  int2* tab;                 // the lists (written by the taps kernel for the call's step)
+  const AdjSeg* segs;
+  const int64_t* tab_off;    // [n_sensors][n_layers]: first entry of the column lists of
+                             // (s, l), the row lists follow nx * kAdjKI later; -1: not tabled
+  int32_t blk_start[kMaxLayers + 1];  // first block of each layer within a realisation
 };
 
 // Gather of the layer gradient from the phase gradients: thread per layer pixel.

@@ -352,3 +352,44 @@ def test_mixed_plan_frames_in_one_footprint_launch_equal_single_frames(flags):
     for k in range(4):
         s1, a1 = plan.forward(xt, step=5 + k)
         assert torch.equal(s[k], s1) and torch.equal(a[k], a1), k
+
+
+@pytest.mark.parametrize("name", ["mixed_lgs_ngs_batch2", "config2_batch2"])
+def test_pinned_schedules_give_the_same_bits(name):
+    """wfs_plan_set_schedule: the FFT-path blocks on the side stream or in the same launch as
+    the lag-domain blocks (and, pipelined, the next step's projection: one launch per step),
+    frames one after the other or pipelined, either block order: the slopes are bit for bit
+    those of the split single frame; impossible schedules are refused."""
+    torch, W = _gpu()
+    if name == "config2_batch2":
+        cfg, B = synth.config2(batch=2), 2
+        x = synth.make_batch(cfg, range(B))
+    else:
+        cfg = CASES[name]()
+        x = layers_for(cfg)
+        B = x.shape[0]
+    xt = torch.from_numpy(x).cuda()
+    plan = W.Plan(cfg, batch=B)
+    plan.set_schedule(field="split", frames="sequential", xcd_remap=1, fft_launch="side_stream")
+    n, k0 = 3, 6
+    ref = [plan.forward(xt, step=k0 + k, seed=4) for k in range(n)]
+    ref = [(s.clone(), a.clone()) for s, a in ref]
+    for fft_launch in ("side_stream", "same_launch"):
+        for frames in ("sequential", "pipelined"):
+            for remap in (0, 1):
+                plan.set_schedule(field="split", frames=frames, xcd_remap=remap,
+                                  fft_launch=fft_launch)
+                sch = plan.schedule()
+                assert (sch["frames"], sch["fft_launch"]) == (frames, fft_launch)
+                s, a = plan.forward_steps(xt, k0, n, seed=4)
+                for k in range(n):
+                    assert torch.equal(s[k], ref[k][0]) and torch.equal(a[k], ref[k][1]), \
+                        (fft_launch, frames, remap, k)
+                s1, a1 = plan.forward(xt, step=k0, seed=4)
+                assert torch.equal(s1, ref[0][0]) and torch.equal(a1, ref[0][1])
+    with pytest.raises(W.WfsError) as e:
+        plan.set_schedule(field="footprint")  # FFT-path sensors read the projected phase
+    assert e.value.code == -4
+    with pytest.raises(W.WfsError) as e:
+        plan.set_schedule(field="gather", frames="pipelined")
+    assert e.value.code == -4

@@ -187,6 +187,29 @@ def test_adjoint_small_periodic_grid_wraps():
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
 
 
+@pytest.mark.parametrize("n,D", [(128, 12.5), (64, 6.0)])
+def test_adjoint_coarse_pupil_two_periodic_images(n, D):
+    """A pupil 2.5 times as coarse as the layer (2.5 layer pixels per pupil pixel) whose
+    footprint wraps about twice around a small periodic screen: most layer pixels take taps
+    from two periodic images, which the gather finds by searching each tile's candidates."""
+    torch, W = _gpu()
+    from wfs_cases import ngs_case
+    cfg = ngs_case(10 if n == 128 else 8, 10 if n == 128 else 6, 20 if n == 128 else 12, 2,
+                   D=D, layers=2, n=n, pitch=0.05)
+    for s in cfg["sensors"]:
+        s["photons"] = 0.0
+    x = layers_for(cfg, scale=0.5)
+    g = synth.random_field((1, oracle.n_slopes(cfg)), seed=8)
+    plan = W.Plan(cfg)
+    out = plan.adjoint(torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda(), step=3)
+    ref = oracle.adjoint(x.astype(np.float64), cfg, 3, g.astype(np.float64))
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
+    assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max()
+    o2 = plan.adjoint(torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda(), step=3)
+    assert torch.equal(out, o2)
+
+
 def test_autograd_function_uses_the_adjoint():
     torch, W = _gpu()
     cfg, x, _ = _adjoint_case("lgs_n5_N10_b2_2sens_batch3")
