@@ -259,11 +259,14 @@ int wfs_set_step(wfs_plan_t plan, int64_t step, void* stream);
 int wfs_advance_step(wfs_plan_t plan, int64_t delta, void* stream);
 
 /*
- * wfs_plan_tune -- time the launch schedules (block order, split or fused projection where
- *   both apply) on `layers` and keep the fastest in the plan; under the split schedule also
- *   time max(2, iters) frames pipelined against one after the other and keep the faster for
- *   wfs_forward_steps.  Synchronises; writes scratch slopes internally.  iters: timed launches
- *   per candidate.  On return *best_us holds the best time per forward call (may be NULL).
+ * wfs_plan_tune -- time every launch schedule the plan can run (field, frame schedule, block
+ *   order and, with both paths, where the FFT-path blocks run) on max(2, iters) frames in a
+ *   row from `layers` and keep the fastest; only schedules whose single frames and frames in
+ *   a row give the same bits are candidates.  Then, where the split and footprint fields both
+ *   fit the kept frame schedule (they share their bits), single frames take the faster.
+ *   Honours WFS_FLAG_FUSED / SPLIT / FOOTPRINT.  Synchronises; writes scratch slopes
+ *   internally.  On return *best_us holds the time per wfs_forward call of the kept schedule
+ *   (may be NULL).
  */
 int wfs_plan_tune(wfs_plan_t plan, const float* layers, int32_t iters, double* best_us,
                   void* stream);

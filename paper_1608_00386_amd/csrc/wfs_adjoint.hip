@@ -571,7 +571,8 @@ __global__ __launch_bounds__(kBlock) void wfs_adjoint_gather_tab_kernel(GatherTa
 #pragma unroll
       for (int q = 0; q < kAdjKI; ++q) cq[q] = min(cf + q, npup - 1);
       const float* gr0 = gs + (int64_t)r_lo * npup;
-      // chunks of kG2Chunk pupil rows: every load of a chunk in flight before its sums
+      // chunks of kG2Chunk pupil rows: every load of a chunk in flight before its sums (double
+      // buffering the chunks measured slower: the registers cost more occupancy than it hid)
       for (int j0 = 0; j0 < nr; j0 += kG2Chunk) {
         float v[kG2Chunk][kAdjKI];
 #pragma unroll

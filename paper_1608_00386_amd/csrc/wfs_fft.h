@@ -114,17 +114,18 @@ inline bool fft_supported_impl(int n_sub, int n_fft, int bin) {
 }
 
 // LDS of one FFT workgroup (bytes):
-//   turns [n][n] float | G [n][M] float2 | fin: spot [N][N] (Q = 1) or b row partials
-//   [Q][n_pix][n_pix] | binned image [n_pix][n_pix] (Q = 1) | block reduction [16]
+//   G [n][M] float2 | fin: spot [N][N] (Q = 1) or b row partials [Q][n_pix][n_pix] |
+//   binned image [n_pix][n_pix] (Q = 1) | block reduction [16]
+// (32 KB for a 64-pixel field in a 128-point transform: a workgroup's share per wave stays
+// near a lag-domain wave's, so both kinds of block can share a launch)
 struct FftLds {
-  int turns_off, g_off, fin_off, bq_off, red_off, total;
+  int g_off, fin_off, bq_off, red_off, total;
 };
 
 __host__ __device__ inline FftLds fft_lds_layout(int n_sub, int n_fft, int n_pix) {
   const int M = n_fft >= 32 ? 32 : n_fft, Q = n_fft / M;
   FftLds o;
-  o.turns_off = 0;
-  o.g_off = (n_sub * n_sub * 4 + 15) & ~15;
+  o.g_off = 0;
   o.fin_off = o.g_off + ((n_sub * M * 8 + 15) & ~15);
   o.bq_off = o.fin_off + (((Q == 1) ? n_fft * n_fft * 4 : Q * n_pix * n_pix * 4) + 15) / 16 * 16;
   o.red_off = o.bq_off + (((Q == 1) ? n_pix * n_pix * 4 : 0) + 15) / 16 * 16;
@@ -146,21 +147,14 @@ __device__ void fft_subap_m(const FwdParams& p, const DevSensor& S, const DevSub
   const int n = S.n_sub, N = S.n_fft, Q = N / M, np = S.n_pix;
   const int nx1 = (n + M - 1) / M;  // input chunks per axis (1 or 2)
   const FftLds lo = fft_lds_layout(n, N, np);
-  float* turns = reinterpret_cast<float*>(smem + lo.turns_off);
   float2* G = reinterpret_cast<float2*>(smem + lo.g_off);
   float* fin = reinterpret_cast<float*>(smem + lo.fin_off);
   float* red = reinterpret_cast<float*>(smem + lo.red_off);  // 3 x 4 floats
 
-  // field phase in turns (kappa psi / 2 pi - (x + y) / 2N), dark pixels as +inf
+  // field phase in turns (kappa psi / 2 pi - the centring ramp and tip-tilt), read by each row
+  // thread straight from the phase buffer; dark pixels contribute nothing
   const float* ph = p.phase_in + (int64_t)b * p.phase_per_real + S.phase_off + (int64_t)v * n * n;
-  for (int q = tid; q < n * n; q += kBlock) {
-    const int y = q / n, x = q - y * n;
-    const uint8_t amp = p.mask[S.mask_off + (sb.a * n + y) * S.n_pup + sb.b * n + x];
-    float t = fmaf(ph[q], 0.15915494309189535f, -fmaf((float)x, S.ramp_x, (float)y * S.ramp_y));
-    t -= rintf(t);
-    turns[q] = amp ? t : __builtin_inff();
-  }
-  __syncthreads();
+  const uint8_t* mrow0 = p.mask + S.mask_off + (sb.a * n) * S.n_pup + sb.b * n;
 
   // Q = b: thread (k2x, k1y) owns the partial bins fin[k1y][(k2y + M/2) % M][(k2x + M/2) % M]
   // for every k2y and accumulates them over the x chunks (no other thread touches them)
@@ -177,8 +171,10 @@ __device__ void fft_subap_m(const FwdParams& p, const DevSensor& S, const DevSub
         for (int x1 = 0; x1 < nx1; ++x1) {
           const int x = x2 + M * x1;
           if (x < n) {
-            const float t = turns[y * n + x];
-            if (t != __builtin_inff()) {
+            float t = fmaf(ph[y * n + x], 0.15915494309189535f,
+                           -fmaf((float)x, S.ramp_x, (float)y * S.ramp_y));
+            t -= rintf(t);
+            if (mrow0[y * S.n_pup + x]) {
               // e^{2 pi i t} W_Q^{x1 k1x} W_N^{x2 k1x}: one rotation in turns
               const float rot = t - (float)(x1 * k1x) / (float)Q - (float)(x2 * k1x) / (float)N;
               float sn, cs;

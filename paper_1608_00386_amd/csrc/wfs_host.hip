@@ -1285,62 +1285,80 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   };
   const FwdParams keep = P->base;
   const int keep_split = P->split, keep_foot = P->foot, keep_frames = P->frames;
-  FwdParams best = keep;
+  // candidates (field, frames, block order, FFT-path blocks in the lag-domain launch), timed on
+  // nf frames in a row (the stepping loop the plan serves); only schedules whose single frames
+  // and frames in a row give the same bits: the gather field steps frame by frame, the split
+  // and footprint fields share their bits with pipelined and one-launch frames
+  struct Cand {
+    int field, frames, remap, inl;
+  };
+  std::vector<Cand> cands;
+  const bool has_fft = P->fft_tasks > 0, mixed = P->fft_tasks > 0 && P->otf_tasks > 0;
+  const bool phase_ok = P->d_phase && P->proj_lds <= 65536;
+  const bool foot1 = P->foot_ok && !has_fft;  // footprint field for single frames
+  const uint32_t fl = P->flags;
+  for (int remap = 0; remap < 2; ++remap)
+    for (int inl = 0; inl < (mixed ? 2 : 1); ++inl) {
+      if (!(fl & (WFS_FLAG_SPLIT | WFS_FLAG_FOOTPRINT))) cands.push_back({0, 0, remap, inl});
+      if (phase_ok && !(fl & WFS_FLAG_FUSED)) {
+        if (!((fl & WFS_FLAG_FOOTPRINT) && foot1)) {
+          cands.push_back({1, 0, remap, inl});
+          cands.push_back({1, 1, remap, inl});
+        }
+      }
+      if (inl == 0 && P->foot_ok && !(fl & (WFS_FLAG_FUSED | WFS_FLAG_SPLIT)) &&
+          (foot1 || phase_ok))
+        cands.push_back({foot1 ? 2 : 1, 2, remap, 0});
+    }
+  auto apply = [&](const Cand& c) {
+    P->base = keep;
+    P->base.xcd_remap = c.remap;
+    P->base.fft_inline = c.inl;
+    P->split = c.field == 1;
+    P->foot = c.field == 2;
+    P->frames = c.frames;
+  };
   double best_t = 1e30;
-  int best_field = P->foot ? 2 : (P->split ? 1 : 0);
-  // single frames: field source (gather, split, staged footprint) x block order
-  for (int mode = 0; mode < 6; ++mode) {
-    const int remap = mode & 1, field = mode >> 1;
-    if (field == 1 && (!P->d_phase || P->proj_lds > 65536)) continue;
-    // single frames take the footprint field only without FFT-path sensors
-    const bool foot1 = P->foot_ok && P->fft_tasks == 0;
-    if (field == 2 && !foot1) continue;
-    if ((P->flags & WFS_FLAG_FUSED) && field != 0) continue;
-    if ((P->flags & WFS_FLAG_SPLIT) && field != 1) continue;
-    if ((P->flags & WFS_FLAG_FOOTPRINT) && foot1 && field != 2) continue;
-    P->split = field == 1;
-    P->foot = field == 2;
-    FwdParams c = keep;
-    c.xcd_remap = remap;
-    P->base = c;
-    FwdParams p = call_params(P, layers, 0, 1, slopes, aux);
-    e = launch_fwd_modes(P, p, st);  // warm-up
+  int best_i = -1;
+  for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+    apply(cands[i]);
+    e = run_steps(P, layers, 0, nf, 1, slopes, aux, P->frames, st);  // warm-up
     if (e != hipSuccess) break;
     (void)hipEventRecord(e0, st);
-    for (int it = 0; it < iters; ++it) e = launch_fwd_modes(P, p, st);
+    e = run_steps(P, layers, 0, nf, 1, slopes, aux, P->frames, st);
     (void)hipEventRecord(e1, st);
-    const double us = 1000.0 * elapsed_ms() / iters;
-    if (e == hipSuccess && us < best_t) {
-      best_t = us;
-      best = c;
-      best_field = field;
+    const double ms = elapsed_ms();
+    if (e == hipSuccess && ms < best_t) {
+      best_t = ms;
+      best_i = (int)i;
     }
-    if (e != hipSuccess) break;
   }
-  P->base = best;
-  P->split = best_field == 1 ? 1 : keep_split;
-  P->foot = best_field == 2;
-  if (best_field == 0) P->split = 0;
-  P->frames = 0;
-  if (e == hipSuccess && best_field != 0) {
-    // frames in a row: one wfs_forward after the other, pipelined split frames, one
-    // footprint launch (the same bits whichever runs)
-    double tbest = 1e30;
-    for (int fr = 0; fr < 3 && e == hipSuccess; ++fr) {
-      if (fr == 1 && !(P->d_phase && P->proj_lds <= 65536)) continue;
-      if (fr == 2 && !P->foot_ok) continue;
-      e = run_steps(P, layers, 0, nf, 1, slopes, aux, fr, st);  // warm-up
-      if (e != hipSuccess) break;
+  double single_us = 0.0;
+  if (e == hipSuccess && best_i >= 0) {
+    Cand c = cands[best_i];
+    apply(c);
+    // single frames of the chosen schedule: the split and footprint fields share their bits,
+    // keep the faster for one wfs_forward
+    auto time_single = [&]() {
+      FwdParams q = call_params(P, layers, 0, 1, slopes, aux);
+      hipError_t r = launch_fwd_modes(P, q, st);
       (void)hipEventRecord(e0, st);
-      e = run_steps(P, layers, 0, nf, 1, slopes, aux, fr, st);
+      for (int it = 0; it < iters && r == hipSuccess; ++it) r = launch_fwd_modes(P, q, st);
       (void)hipEventRecord(e1, st);
-      const double ms = elapsed_ms();
-      if (e == hipSuccess && ms < tbest) {
-        tbest = ms;
-        P->frames = fr;
-      }
+      e = r;
+      return 1000.0 * elapsed_ms() / iters;
+    };
+    single_us = time_single();
+    if (e == hipSuccess && c.frames != 0 && foot1 && phase_ok && !(fl & WFS_FLAG_SPLIT)) {
+      Cand other = c;
+      other.field = c.field == 2 ? 1 : 2;
+      apply(other);
+      const double us2 = time_single();
+      if (e == hipSuccess && us2 < single_us) single_us = us2;
+      else apply(c);
     }
   }
+  if (e == hipSuccess && best_i < 0) e = hipErrorInvalidValue;  // no schedule could run
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(slopes);
@@ -1352,7 +1370,7 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
     P->frames = keep_frames;
     return hip_fail(e, "wfs_plan_tune: launch");
   }
-  if (best_us) *best_us = best_t;
+  if (best_us) *best_us = single_us;
   return WFS_OK;
 }
 

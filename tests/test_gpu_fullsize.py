@@ -52,10 +52,15 @@ def test_batched_config_step_matches_oracle():
     err = _slope_errors(s[rows], want, tol)
     assert err.max() <= 1.0, f"config-2 slopes: {err.max():.3g} of the bar"
     np.testing.assert_allclose(a[rows], aux, rtol=2e-5, atol=1e-3)
-    # the tuned schedule gives the same bits
+    # the tuned schedule gives the same bits when it keeps a field that shares them (split or
+    # footprint); the per-pixel gather has its own bits, held to the same bar
     plan.tune(xt, iters=2)
     s2, _ = plan.forward(xt, step=step, seed=42)
-    assert np.array_equal(s2.cpu().numpy(), s)
+    s2 = s2.cpu().numpy()
+    if plan.schedule()["field"] != "gather":
+        assert np.array_equal(s2, s)
+    else:
+        assert _slope_errors(s2[rows], want, tol).max() <= 1.0
 
 
 @pytest.mark.parametrize("saved", [False, True])
