@@ -276,8 +276,9 @@ int wfs_plan_tune(wfs_plan_t plan, const float* layers, int32_t iters, double* b
  *   C[b][i] = alpha * sum_j R[i][j] S[b][j] + beta * C[b][i],  i < M, j < N, b < B.
  *   R: device [M][N] row-major.  S: device [B][N].  C: device, row b at C + b*ldc
  *   (ldc >= M).  beta = 0 ignores the old C.  A pure integrator a += g R s is
- *   alpha = g, beta = 1 on the DM actuator rows.  B = 1 runs a streaming GEMV; B >= 2 a
- *   split-K matrix-core (MFMA) GEMM.  Deterministic.  The split partial sums go to a
+ *   alpha = g, beta = 1 on the DM actuator rows.  B = 1 runs a streaming GEMV, 2 <= B <= 8
+ *   the same stream with every realisation at once (16-byte aligned R and S, N % 4 == 0),
+ *   larger batches a split-K matrix-core (MFMA) GEMM.  Deterministic.  The split partial sums go to a
  *   library-owned buffer of the calling stream (kept for the life of the process, so graphs
  *   captured with it stay valid); a call that would have to grow that buffer while the stream
  *   is capturing returns WFS_EINVAL (run it once outside the capture first).  Calls on one
@@ -293,8 +294,8 @@ int recon_apply(const float* R, int32_t M, int32_t N, const float* S, int32_t B,
  *   allocates, frees or synchronises.  The split partial sums go to a fixed library array of
  *   2^22 floats (16 MiB) on each GPU, held until the process ends; the split count shrinks to
  *   what it holds, so results may differ from recon_apply's by rounding order only.  Returns
- *   WFS_EINVAL when one split does not fit: M * min(B, 16) > 2^22 for B >= 2 (aligned
- *   operands), M > 2^22 otherwise.  Every call on one GPU shares the array: calls that overlap
+ *   WFS_EINVAL when one split does not fit: M * B > 2^22 for 2 <= B <= 8 and
+ *   M * min(B, 16) > 2^22 for larger B (aligned operands), M > 2^22 otherwise.  Every call on one GPU shares the array: calls that overlap
  *   in time on one GPU (different streams, or threads) race and give wrong results; order
  *   them on one stream.  The caller owns R, S and C as for recon_apply.
  */

@@ -4,7 +4,9 @@
 // per call; that stream bounds the operation (4 flop per byte of R at B = 8).
 //
 //   B == 1, or unaligned operands : split-K streaming GEMV on the vector ALUs
-//   B >= 2, 16-byte aligned, N%4==0: split-K GEMM on the FP32 matrix cores
+//   2 <= B <= 8, 16-byte aligned   : the same streaming order with every realisation at once
+//   (N % 4 == 0)                     (vector ALUs; R read once in 1 KB bursts per row)
+//   B > 8, aligned                 : split-K GEMM on the FP32 matrix cores
 //                                    (v_mfma_f32_16x16x4f32, one 16-row x 16-realisation tile
 //                                    per MFMA, 2 row tiles per wavefront)
 // Both write per-split partial sums to a workspace; a second kernel adds the splits in a fixed
@@ -21,6 +23,8 @@
 namespace wfs {
 
 constexpr int kRB = 256;
+constexpr int kBatchRW = 8;  // rows per wave of the small-batch kernel
+constexpr int kBatchMax = 8;  // realisations of the small-batch kernel
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -97,6 +101,68 @@ __global__ __launch_bounds__(kRB) void recon_valu_kernel(const float* __restrict
 #pragma unroll
     for (int r = 0; r < RW; ++r)
       if (row0 + r < M) ws[((int64_t)sp * 1 + 0) * M + row0 + r] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Small batches (2 <= B <= 8), aligned operands: the GEMV's streaming order with every
+// realisation at once.  Wave per (RW rows, split); lane j reads the float4 at column
+// k0 + 4 j + 256 i of each of its rows (1 KB contiguous per row and instruction, as the GEMV:
+// long DRAM bursts), the matching float4 of every realisation's slopes (cached: S is small),
+// and accumulates RW x B dot products; the wave reduces them at the end.
+// ---------------------------------------------------------------------------------------
+template <int RW, int BB>
+__global__ __launch_bounds__(kRB) void recon_batch_kernel(const float* __restrict__ R, int M,
+                                                          int N, const float* __restrict__ S,
+                                                          int B, int chunk, int splits,
+                                                          int row_groups,
+                                                          float* __restrict__ ws) {
+  const int wave = (blockIdx.x * kRB + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= row_groups * splits) return;
+  // consecutive waves take consecutive row groups of one split: the waves of a workgroup
+  // read the same slopes (L1 hits) and neighbouring rows of R
+  const int sp = wave / row_groups, g = wave - sp * row_groups;
+  const int row0 = g * RW;
+  const int k0 = sp * chunk, k1 = min(N, k0 + chunk);
+  const float* rrow[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) rrow[r] = R + (int64_t)min(row0 + r, M - 1) * N;
+  float acc[RW][BB];
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int b = 0; b < BB; ++b) acc[r][b] = 0.0f;
+  for (int k = k0 + 4 * lane; k < k1; k += 4 * 64) {
+    float4 rv[RW], sv[BB];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rv[r] = ldnt4(rrow[r] + k);
+#pragma unroll
+    for (int b = 0; b < BB; ++b)
+      sv[b] = b < B ? *reinterpret_cast<const float4*>(S + (int64_t)b * N + k)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int b = 0; b < BB; ++b)
+        acc[r][b] = fmaf(rv[r].x, sv[b].x, fmaf(rv[r].y, sv[b].y,
+                    fmaf(rv[r].z, sv[b].z, fmaf(rv[r].w, sv[b].w, acc[r][b]))));
+  }
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+      float v = acc[r][b];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc[r][b] = v;
+    }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+      for (int b = 0; b < BB; ++b)
+        if (row0 + r < M && b < B) ws[((int64_t)sp * B + b) * M + row0 + r] = acc[r][b];
   }
 }
 
@@ -233,7 +299,8 @@ __global__ __launch_bounds__(kRB) void recon_reduce_kernel(const float* __restri
 // resident wave slots, so no wave of a second round streams its chunk after the others end
 // ---------------------------------------------------------------------------------------
 static std::mutex g_occ_mu;
-static int g_slots[64][3];  // per device: resident waves of the MFMA, GEMV and unaligned kernels
+static int g_slots[64][4];  // per device: resident waves of the MFMA, GEMV, unaligned and
+                            // small-batch kernels
 
 static hipError_t resident_waves(int which, int* out) {
   int dev = 0;
@@ -247,7 +314,9 @@ static hipError_t resident_waves(int which, int* out) {
     if (e != hipSuccess) return e;
     const void* k = which == 0   ? reinterpret_cast<const void*>(recon_mfma_kernel<2>)
                     : which == 1 ? reinterpret_cast<const void*>(recon_valu_kernel<2, true>)
-                                 : reinterpret_cast<const void*>(recon_valu_kernel<2, false>);
+                    : which == 2 ? reinterpret_cast<const void*>(recon_valu_kernel<2, false>)
+                                 : reinterpret_cast<const void*>(
+                                       recon_batch_kernel<kBatchRW, kBatchMax>);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kRB, 0);
     if (e != hipSuccess) return e;
     g_slots[dev][which] = std::max(1, cus * std::max(1, blocks) * (kRB / 64));
@@ -271,6 +340,7 @@ static int choose_splits(int row_groups, int N, int align, int slots, int64_t ma
 }
 
 struct ReconShape {
+  int batch;       // 1: every realisation at once on the vector ALUs (2 <= B <= 8, aligned)
   int mfma;        // 1: matrix-core GEMM in tiles of 16 realisations; 0: one GEMV per realisation
   int aligned;     // 16-byte aligned R and S, N % 4 == 0
   int row_groups;
@@ -281,10 +351,12 @@ struct ReconShape {
 static hipError_t recon_shape(const float* R, int M, int N, const float* S, int B,
                               ReconShape* sh) {
   sh->aligned = (N % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)S % 16 == 0);
-  sh->mfma = B >= 2 && sh->aligned;
-  sh->row_groups = sh->mfma ? (M + 31) / 32 : (M + 1) / 2;
-  sh->tile_b = sh->mfma ? std::min(16, B) : 1;
-  return resident_waves(sh->mfma ? 0 : (sh->aligned ? 1 : 2), &sh->slots);
+  sh->batch = B >= 2 && B <= kBatchMax && sh->aligned;
+  sh->mfma = B > kBatchMax && sh->aligned;
+  sh->row_groups = sh->batch ? (M + kBatchRW - 1) / kBatchRW
+                             : (sh->mfma ? (M + 31) / 32 : (M + 1) / 2);
+  sh->tile_b = sh->batch ? B : (sh->mfma ? std::min(16, B) : 1);
+  return resident_waves(sh->batch ? 3 : (sh->mfma ? 0 : (sh->aligned ? 1 : 2)), &sh->slots);
 }
 
 // Floats of partial sums a call wants (its split count unconstrained by the workspace).
@@ -294,8 +366,9 @@ hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B
   hipError_t e = recon_shape(R, M, N, S, B, &sh);
   if (e != hipSuccess) return e;
   int chunk;
-  const int splits = choose_splits(sh.row_groups, N, sh.mfma ? 32 : (sh.aligned ? 256 : 64),
-                                   sh.slots, INT32_MAX, &chunk);
+  const int splits = choose_splits(sh.row_groups, N,
+                                   (sh.mfma ? 32 : (sh.aligned ? 256 : 64)), sh.slots,
+                                   INT32_MAX, &chunk);
   *floats = (int64_t)splits * sh.tile_b * M;
   return hipSuccess;
 }
@@ -311,6 +384,26 @@ hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, flo
   *used_mfma = sh.mfma;
   const int64_t max_splits = ws_floats / ((int64_t)sh.tile_b * M);
   if (max_splits < 1) return hipErrorInvalidValue;
+  if (sh.batch) {
+    int chunk;
+    const int splits = choose_splits(sh.row_groups, N, 256, sh.slots, max_splits, &chunk);
+    const int waves = sh.row_groups * splits;
+    if (B <= 2)
+      hipLaunchKernelGGL((recon_batch_kernel<kBatchRW, 2>), dim3((waves + 3) / 4), dim3(kRB), 0,
+                         st, R, M, N, S, B, chunk, splits, sh.row_groups, ws);
+    else if (B <= 4)
+      hipLaunchKernelGGL((recon_batch_kernel<kBatchRW, 4>), dim3((waves + 3) / 4), dim3(kRB), 0,
+                         st, R, M, N, S, B, chunk, splits, sh.row_groups, ws);
+    else
+      hipLaunchKernelGGL((recon_batch_kernel<kBatchRW, kBatchMax>), dim3((waves + 3) / 4),
+                         dim3(kRB), 0, st, R, M, N, S, B, chunk, splits, sh.row_groups, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)M * B;
+    hipLaunchKernelGGL(recon_reduce_kernel, dim3((unsigned)((n + kRB - 1) / kRB)), dim3(kRB), 0,
+                       st, ws, M, B, splits, C, ldc, alpha, beta, 0, B);
+    return hipGetLastError();
+  }
   if (sh.mfma) {
     constexpr int TR = 2;
     int chunk;
