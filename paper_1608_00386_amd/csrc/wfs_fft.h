@@ -1,19 +1,11 @@
 // FFT path of the Shack-Hartmann spot model: large subaperture fields without elongation
-// (the NGS sensors), one 256-thread workgroup per subaperture.
+// (the NGS sensors), one 64-lane wave per chunk of the spectrum.
 //
 // Spot (our reading of the sensor of Sec. 2.7):  I = c |F|^2,  F = DFT_N(E) of the n x n field
-// zero-padded to N x N (kernel e^{-2 pi i k m / N}), then fftshift and b x b binning.
-// With N = Q M (M = 16 or 32 points per register FFT, Q residue chunks) every output index
-// is f = Q k2 + k1 and every input index x = x2 + M x1, so
-//     DFT_N(e)[Q k2 + k1] = DFT_M( W_N^{x2 k1} sum_{x1} e[x2 + M x1] W_Q^{x1 k1} )[k2],
-// i.e. chunk k1 of the outputs is one M-point FFT of a twiddled, folded input.  The 2-D
-// transform runs chunk by chunk along x (row FFTs of the n field rows into LDS), then for
-// every chunk along y (column FFTs, one thread per (k2x, k1y)).
-// Binning: with Q = b (or Q = 1) the fftshifted bin of output (Q k2y + k1y, Q k2x + k1x) is
-// ((k2y + M/2) mod M, (k2x + M/2) mod M) when Q = b, so each thread accumulates its bins in
-// registers over the x chunks and the b partial rows are added in a fixed order at the end;
-// with Q = 1 the spot goes to LDS and bins are summed directly.  Deterministic.
-// The field phase comes from the projection kernel's buffer (kappa * psi per pixel).
+// zero-padded to N x N (kernel e^{-2 pi i k m / N}), then fftshift and b x b binning.  With
+// N = Q M (M = 16 or 32 points per register FFT) the spectrum splits into Q^2 chunks, each an
+// M x M FFT of a folded, twiddled field (fft_chunk_m below), so a subaperture spreads over Q^2
+// waves.  Deterministic.  The field phase comes from the projection kernel's buffer.
 #pragma once
 
 #include "wfs_otf.h"
@@ -113,149 +105,143 @@ inline bool fft_supported_impl(int n_sub, int n_fft, int bin) {
   return Q == 1 || Q == bin;
 }
 
-// LDS of one FFT workgroup (bytes):
-//   G [n][M] float2 | fin: spot [N][N] (Q = 1) or b row partials [Q][n_pix][n_pix] |
-//   binned image [n_pix][n_pix] (Q = 1) | block reduction [16]
-// (32 KB for a 64-pixel field in a 128-point transform: a workgroup's share per wave stays
-// near a lag-domain wave's, so both kinds of block can share a launch)
-struct FftLds {
-  int g_off, fin_off, bq_off, red_off, total;
-};
-
-__host__ __device__ inline FftLds fft_lds_layout(int n_sub, int n_fft, int n_pix) {
+// LDS of one FFT wave (bytes): the chunk X [M][M + 1] float2 (rows padded against bank
+// conflicts; later the spot |F|^2 of one chunk in the .x slots, and the binned image) and,
+// with one chunk (Q = 1), the binned image [n_pix][n_pix].
+__host__ __device__ inline int fft_wave_lds_bytes_impl(int n_fft, int n_pix) {
   const int M = n_fft >= 32 ? 32 : n_fft, Q = n_fft / M;
-  FftLds o;
-  o.g_off = 0;
-  o.fin_off = o.g_off + ((n_sub * M * 8 + 15) & ~15);
-  o.bq_off = o.fin_off + (((Q == 1) ? n_fft * n_fft * 4 : Q * n_pix * n_pix * 4) + 15) / 16 * 16;
-  o.red_off = o.bq_off + (((Q == 1) ? n_pix * n_pix * 4 : 0) + 15) / 16 * 16;
-  o.total = o.red_off + 64;
-  return o;
-}
-
-inline int fft_lds_bytes_impl(int n_sub, int n_fft, int n_pix) {
-  return fft_lds_layout(n_sub, n_fft, n_pix).total;
+  return M * (M + 1) * 8 + (Q == 1 ? ((n_pix * n_pix * 4 + 15) & ~15) : 0);
 }
 
 // ---------------------------------------------------------------------------------------
-// one subaperture per workgroup
+// One wave per spectrum chunk.  With N = Q M every output index is f = Q k2 + k1 and every
+// input index x = x2 + M x1, so chunk (k1y, k1x) of the 2-D spectrum is an M x M 2-D FFT of
+// the folded, twiddled field
+//     X[y2][x2] = sum_{y1, x1} e[y2 + M y1][x2 + M x1] W_Q^{y1 k1y + x1 k1x} W_N^{y2 k1y + x2 k1x}
+// (one rotation in turns per input pixel).  With Q = b the fftshifted bin of output
+// (Q k2y + k1y, Q k2x + k1x) is ((k2y + M/2) mod M, (k2x + M/2) mod M): each chunk adds one
+// value to every bin.  The chunk writes its partial image to global memory and bumps the
+// subaperture's counter; the wave that completes the count adds the Q^2 partial images in
+// chunk order (deterministic), applies the noise and the centre of gravity, and resets the
+// counter for the next launch.  With Q = 1 the wave holds the whole spectrum and bins it
+// itself.
 // ---------------------------------------------------------------------------------------
 template <int M>
-__device__ void fft_subap_m(const FwdParams& p, const DevSensor& S, const DevSubap& sb,
-                            int sid, int b, int v, int64_t step, char* smem) {
-  const int tid = threadIdx.x;
-  const int n = S.n_sub, N = S.n_fft, Q = N / M, np = S.n_pix;
-  const int nx1 = (n + M - 1) / M;  // input chunks per axis (1 or 2)
-  const FftLds lo = fft_lds_layout(n, N, np);
-  float2* G = reinterpret_cast<float2*>(smem + lo.g_off);
-  float* fin = reinterpret_cast<float*>(smem + lo.fin_off);
-  float* red = reinterpret_cast<float*>(smem + lo.red_off);  // 3 x 4 floats
-
-  // field phase in turns (kappa psi / 2 pi - the centring ramp and tip-tilt), read by each row
-  // thread straight from the phase buffer; dark pixels contribute nothing
+__device__ void fft_chunk_m(const FwdParams& p, const DevSensor& S, int sid, int b, int u,
+                            int64_t step, char* wsm) {
+  constexpr int G = kWave / M;  // lanes per column in the fold
+  const int lane = lane_id();
+  const int n = S.n_sub, N = S.n_fft, Q = N / M, Q2 = Q * Q, np = S.n_pix;
+  const int v = u / Q2, c = u - v * Q2;
+  const int k1y = c / Q, k1x = c - k1y * Q;
+  const DevSubap sb = cload(p.sub, S.valid_off + v);
+  const int nx1 = (n + M - 1) / M;
+  float2* X = reinterpret_cast<float2*>(wsm);  // [M][M + 1]
   const float* ph = p.phase_in + (int64_t)b * p.phase_per_real + S.phase_off + (int64_t)v * n * n;
   const uint8_t* mrow0 = p.mask + S.mask_off + (sb.a * n) * S.n_pup + sb.b * n;
-
-  // Q = b: thread (k2x, k1y) owns the partial bins fin[k1y][(k2y + M/2) % M][(k2x + M/2) % M]
-  // for every k2y and accumulates them over the x chunks (no other thread touches them)
-  if (Q > 1)
-    for (int q = tid; q < Q * np * np; q += kBlock) fin[q] = 0.0f;
-
-  for (int k1x = 0; k1x < Q; ++k1x) {
-    // rows: G[y][k2x] = DFT_M(W_N^{x2 k1x} sum_x1 e[y][x2 + M x1] W_Q^{x1 k1x})[k2x]
-    for (int y = tid; y < n; y += kBlock) {
-      float2 xr[M];
-#pragma unroll
-      for (int x2 = 0; x2 < M; ++x2) {
-        float2 s = make_float2(0.0f, 0.0f);
+  // 1. fold: lane (column x2, group g) forms rows y2 = g, g + G, ...
+  {
+    const int x2 = lane & (M - 1), g = lane / M;
+    for (int y2 = g; y2 < M; y2 += G) {
+      float2 acc = make_float2(0.0f, 0.0f);
+      for (int y1 = 0; y1 < nx1; ++y1) {
+        const int y = y2 + M * y1;
+        if (y >= n) break;
         for (int x1 = 0; x1 < nx1; ++x1) {
           const int x = x2 + M * x1;
-          if (x < n) {
+          if (x < n && mrow0[y * S.n_pup + x]) {
             float t = fmaf(ph[y * n + x], 0.15915494309189535f,
                            -fmaf((float)x, S.ramp_x, (float)y * S.ramp_y));
             t -= rintf(t);
-            if (mrow0[y * S.n_pup + x]) {
-              // e^{2 pi i t} W_Q^{x1 k1x} W_N^{x2 k1x}: one rotation in turns
-              const float rot = t - (float)(x1 * k1x) / (float)Q - (float)(x2 * k1x) / (float)N;
-              float sn, cs;
-              sincos_rev(rot - rintf(rot), &sn, &cs);
-              s.x += cs;
-              s.y += sn;
-            }
-          }
-        }
-        xr[x2] = s;
-      }
-      fft_reg<M>(xr);
-#pragma unroll
-      for (int k = 0; k < M; ++k) G[y * M + k] = xr[k];
-    }
-    __syncthreads();
-    // columns: thread (k2x, k1y); F[Q k2y + k1y][Q k2x + k1x]
-    for (int w = tid; w < M * Q; w += kBlock) {
-      const int k2x = w % M, k1y = w / M;
-      float2 xc[M];
-#pragma unroll
-      for (int y2 = 0; y2 < M; ++y2) {
-        float2 s = make_float2(0.0f, 0.0f);
-        for (int y1 = 0; y1 < nx1; ++y1) {
-          const int y = y2 + M * y1;
-          if (y < n) {
-            const float2 g = G[y * M + k2x];
-            const float rot = -(float)(y1 * k1y) / (float)Q - (float)(y2 * k1y) / (float)N;
+            // e^{2 pi i t} W_Q^{y1 k1y + x1 k1x} W_N^{y2 k1y + x2 k1x}
+            float rot = t - (float)(y1 * k1y + x1 * k1x) / (float)Q -
+                        (float)(y2 * k1y + x2 * k1x) / (float)N;
+            rot -= rintf(rot);
             float sn, cs;
-            sincos_rev(rot - rintf(rot), &sn, &cs);
-            s.x = fmaf(g.x, cs, fmaf(-g.y, sn, s.x));
-            s.y = fmaf(g.x, sn, fmaf(g.y, cs, s.y));
+            sincos_rev(rot, &sn, &cs);
+            acc.x += cs;
+            acc.y += sn;
           }
         }
-        xc[y2] = s;
       }
-      fft_reg<M>(xc);
-      if (Q == 1) {  // spot column k2x -> LDS (fftshift and binning below)
-#pragma unroll
-        for (int k = 0; k < M; ++k) fin[k * N + k2x] = S.flux_c * (xc[k].x * xc[k].x + xc[k].y * xc[k].y);
-      } else {
-        const int qx = (k2x + M / 2) % M;
-#pragma unroll
-        for (int k = 0; k < M; ++k)
-          fin[(k1y * np + (k + M / 2) % M) * np + qx] += xc[k].x * xc[k].x + xc[k].y * xc[k].y;
-      }
+      X[y2 * (M + 1) + x2] = acc;
     }
-    __syncthreads();
   }
-
-  float* Bimg = fin;  // binned image [np][np]
+  wave_sync();
+  // 2. row FFTs (lane = row)
+  if (lane < M) {
+    float2 xr[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xr[k] = X[lane * (M + 1) + k];
+    fft_reg<M>(xr);
+#pragma unroll
+    for (int k = 0; k < M; ++k) X[lane * (M + 1) + k] = xr[k];
+  }
+  wave_sync();
+  // 3. column FFTs (lane = column k2x): |F|^2 of frequency (Q k2y + k1y, Q k2x + k1x)
+  float* spot = reinterpret_cast<float*>(X);  // the .x slot of X[k2y][k2x]
+  if (lane < M) {
+    float2 xc[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xc[k] = X[k * (M + 1) + lane];
+    fft_reg<M>(xc);
+    if (Q == 1) {
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        spot[2 * (k * (M + 1) + lane)] = S.flux_c * (xc[k].x * xc[k].x + xc[k].y * xc[k].y);
+    } else {
+      // partial image of this chunk, binned layout [qy][qx], qx = (k2x + M/2) mod M
+      float* part = p.fft_part + (int64_t)b * p.fft_part_per_real + S.fft_part_off +
+                    ((int64_t)v * Q2 + c) * (M * M);
+      const int qx = (lane + M / 2) & (M - 1);
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        part[((k + M / 2) & (M - 1)) * M + qx] = xc[k].x * xc[k].x + xc[k].y * xc[k].y;
+    }
+  }
+  float* Bimg;
   if (Q == 1) {
+    wave_sync();
     // bins of the fftshifted spot: B[qy][qx] = sum_{dy,dx<b} I[(b qy + dy + N/2) % N][...]
-    float* Bq = reinterpret_cast<float*>(smem + lo.bq_off);
+    Bimg = reinterpret_cast<float*>(wsm + M * (M + 1) * 8);
     const int bb = S.bin;
-    for (int q = tid; q < np * np; q += kBlock) {
+    for (int q = lane; q < np * np; q += kWave) {
       const int qy = q / np, qx = q - qy * np;
-      float s = 0.0f;
+      float sum = 0.0f;
       for (int dy = 0; dy < bb; ++dy) {
         const int fy = (bb * qy + dy + N / 2) % N;
-        for (int dx = 0; dx < bb; ++dx) s += fin[fy * N + (bb * qx + dx + N / 2) % N];
+        for (int dx = 0; dx < bb; ++dx)
+          sum += spot[2 * (fy * (M + 1) + (bb * qx + dx + N / 2) % N)];
       }
-      Bq[q] = s;
+      Bimg[q] = sum;
     }
-    Bimg = Bq;
+    wave_sync();
   } else {
-    // the b = Q partial rows of every bin, summed in k1y order
-    for (int q = tid; q < np * np; q += kBlock) {
-      float s = 0.0f;
-      for (int k1y = 0; k1y < Q; ++k1y) s += fin[k1y * np * np + q];
-      fin[q] = S.flux_c * s;  // rows >= 1 of the partials are not read again
+    // the wave that completes the subaperture's count adds the partial images
+    __threadfence();
+    int32_t* cnt = p.fft_cnt + (int64_t)b * p.fft_cnt_per_real + S.fft_cnt_off + v;
+    int old = 0;
+    if (lane == 0) old = atomicAdd(cnt, 1);
+    old = __shfl(old, 0, kWave);
+    if (old != Q2 - 1) return;  // wave-uniform
+    __threadfence();
+    if (lane == 0) *cnt = 0;  // ready for the next launch
+    const float* part0 = p.fft_part + (int64_t)b * p.fft_part_per_real + S.fft_part_off +
+                         (int64_t)v * Q2 * (M * M);
+    Bimg = reinterpret_cast<float*>(wsm);  // X is free now
+    for (int q = lane; q < M * M; q += kWave) {
+      float sum = 0.0f;
+      for (int cc = 0; cc < Q2; ++cc) sum += __builtin_nontemporal_load(part0 + cc * (M * M) + q);
+      Bimg[q] = S.flux_c * sum;
     }
+    wave_sync();
   }
-  __syncthreads();
-
-  // noise + centre of gravity over the block (pairs of pixels, fixed reduction order)
+  // 4. noise + centre of gravity (pairs of pixels share a Philox block)
   const int np2 = np * np, npairs = (np2 + 1) >> 1;
   const float half = 0.5f * (float)(np - 1);
   float s0 = 0.0f, sx = 0.0f, sy = 0.0f;
   const bool noisy = S.noisy && p.noise_on;
-  for (int pr = tid; pr < npairs; pr += kBlock) {
+  for (int pr = lane; pr < npairs; pr += kWave) {
     const int q0 = 2 * pr, q1 = 2 * pr + 1;
     float b0 = Bimg[q0];
     float b1 = q1 < np2 ? Bimg[q1] : 0.0f;
@@ -271,38 +257,27 @@ __device__ void fft_subap_m(const FwdParams& p, const DevSensor& S, const DevSub
     sx = fmaf((float)x0 - half, b0, fmaf((float)x1 - half, b1, sx));
     sy = fmaf((float)y0 - half, b0, fmaf((float)y1 - half, b1, sy));
   }
-  s0 = wave_sum(s0);
-  sx = wave_sum(sx);
-  sy = wave_sum(sy);
-  const int wave = tid >> 6;
-  __syncthreads();
-  if (lane_id() == 0) {
-    red[wave] = s0;
-    red[4 + wave] = sx;
-    red[8 + wave] = sy;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    Cog c;
-    c.s0 = (red[0] + red[1]) + (red[2] + red[3]);
-    c.sx = (red[4] + red[5]) + (red[6] + red[7]);
-    c.sy = (red[8] + red[9]) + (red[10] + red[11]);
-    write_slopes(p, S, b, v, c);
-  }
+  Cog cg;
+  cg.s0 = wave_sum(s0);
+  cg.sx = wave_sum(sx);
+  cg.sy = wave_sum(sy);
+  write_slopes(p, S, b, v, cg);
 }
 
-__device__ __forceinline__ void fft_subap(const FwdParams& p, int task, int64_t step,
-                                          char* smem) {
+// FFT-path task t (one wave): spectrum chunk (t - start) mod Q^2 of subaperture
+// (t - start) / Q^2 of its sensor.
+__device__ __forceinline__ void fft_wave(const FwdParams& p, int task, int64_t step,
+                                         char* wsm) {
   const int total = p.fft.per_real * p.batch;
-  if (task >= total) return;  // padding blocks
-  int b, sid, v;
-  task_of(p.fft, task, b, sid, v);
+  if (task >= total) return;  // padding waves
+  int b, sid, u;
+  task = __builtin_amdgcn_readfirstlane(task);
+  task_of(p.fft, task, b, sid, u);
   const DevSensor S = cload(p.sen, sid);
-  const DevSubap sb = cload(p.sub, S.valid_off + v);
   if (S.n_fft >= 32)
-    fft_subap_m<32>(p, S, sb, sid, b, v, step, smem);
+    fft_chunk_m<32>(p, S, sid, b, u, step, wsm);
   else
-    fft_subap_m<16>(p, S, sb, sid, b, v, step, smem);
+    fft_chunk_m<16>(p, S, sid, b, u, step, wsm);
 }
 
 }  // namespace wfs

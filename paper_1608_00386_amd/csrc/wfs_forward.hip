@@ -104,5 +104,5 @@ hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st
 
 namespace wfs {
 bool fft_supported(int n_sub, int n_fft, int bin) { return fft_supported_impl(n_sub, n_fft, bin); }
-int fft_lds_bytes(int n_sub, int n_fft, int n_pix) { return fft_lds_bytes_impl(n_sub, n_fft, n_pix); }
+int fft_wave_lds_bytes(int n_fft, int n_pix) { return fft_wave_lds_bytes_impl(n_fft, n_pix); }
 }  // namespace wfs

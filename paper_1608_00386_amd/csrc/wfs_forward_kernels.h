@@ -1,6 +1,6 @@
 // The spot launch of the forward model, one kernel per (subaperture size, mode): every sensor
 // of a plan for every realisation at one time step.
-//   blocks [0, fft_blocks)   : FFT path, one subaperture per 256-thread workgroup (large fields)
+//   blocks [0, fft_blocks)   : FFT path, one spectrum chunk of a large field per wave
 //   remaining blocks         : lag-domain path, one subaperture per 64-lane wavefront at a time,
 //                              with (pipelined frames) the next step's projection blocks spread
 //                              evenly among them
@@ -36,8 +36,9 @@ void wfs_forward_kernel(
   const int64_t step = current_step(p);
   const int i = blockIdx.x;
   if constexpr (FFT) {
-    if (i < p.fft_blocks) {
-      fft_subap(p, i, step, smem);
+    if (i < p.fft_blocks) {  // FFT path: one spectrum chunk per wave
+      const int w = threadIdx.x >> 6;
+      fft_wave(p, i * kWavesPerBlock + w, step, smem + w * p.lds_per_wave);
       return;
     }
   }

@@ -49,7 +49,7 @@ const char* tlse_run(const float* im, int32_t m, int32_t n_s, int64_t ld_im, flo
                      const float* w, float* R, int64_t ld_r, float* work, hipStream_t st,
                      int* info);
 int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats);
-int fft_lds_bytes(int n_sub, int n_fft, int n_pix);
+int fft_wave_lds_bytes(int n_fft, int n_pix);
 bool fft_supported(int n_sub, int n_fft, int bin);
 }  // namespace wfs
 
@@ -147,6 +147,9 @@ struct wfs_plan_s {
   int frames = 0;
   int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
   SideStream side{};         // FFT-path blocks run here concurrently (plans with both paths)
+  float* d_fft_part = nullptr;   // FFT path: partial images of the spectrum chunks
+  int32_t* d_fft_cnt = nullptr;  // and per-subaperture chunk counters (zero between launches)
+  int64_t fft_part_per_real = 0, fft_cnt_per_real = 0;
   float4* d_na = nullptr;    // sodium-profile table (wfs_plan_na_profile), capacity na_cap
   int64_t na_cap = 0;
   std::vector<float4*> na_retired;  // outgrown tables: graphs captured earlier may hold them
@@ -601,6 +604,24 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     }
     P->adj_clear_grad = gap || end < layer_stride;
   }
+  // FFT path with several spectrum chunks: per realisation, every such sensor's partial
+  // images (Q^2 chunks of M x M floats = n_fft^2 per subaperture) and chunk counters
+  int64_t fft_part = 0, fft_cnt = 0;
+  for (int s : fft_ids) {
+    const int N = sensors[s].n_fft, M = N >= 32 ? 32 : N;
+    ds[s].fft_part_off = (int32_t)std::min<int64_t>(fft_part, (1LL << 31) - 1);
+    ds[s].fft_cnt_off = (int32_t)fft_cnt;
+    if (N / M > 1) {
+      fft_part += (int64_t)ds[s].n_valid * N * N;
+      fft_cnt += ds[s].n_valid;
+    }
+  }
+  if (fft_part > (1LL << 31) - 1) {
+    delete P;
+    return fail(WFS_EINVAL, "wfs_plan: FFT-path partial images too large");
+  }
+  P->fft_part_per_real = fft_part;
+  P->fft_cnt_per_real = fft_cnt;
   P->hsen = ds;
   P->n_slopes = slope_off;
   P->n_valid_total = aux_off;
@@ -677,7 +698,14 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.n_slopes = P->n_slopes;
   b.n_valid_total = P->n_valid_total;
   fill_tasks(b.otf, otf_ids, P->n_valid);
-  fill_tasks(b.fft, fft_ids, P->n_valid);
+  {  // FFT path: one task (wave) per spectrum chunk, Q^2 per subaperture
+    std::vector<int32_t> units(P->n_valid);
+    for (int s : fft_ids) {
+      const int Q = sensors[s].n_fft / (sensors[s].n_fft >= 32 ? 32 : sensors[s].n_fft);
+      units[s] = P->n_valid[s] * Q * Q;
+    }
+    fill_tasks(b.fft, fft_ids, units);
+  }
   for (int s = 0; s < n_sensors; ++s) {
     const int lb = project_lds_bytes(n_layers);
     P->proj_lds = std::max(P->proj_lds, lb);
@@ -711,13 +739,13 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   // LDS: lag-domain waves and FFT workgroups share one dynamic allocation; the split
   // schedule's waves need no tap region (the fused gather does)
-  int lds_fft = 0;
+  int lds_fft = 0;  // per FFT-path wave
   for (int s : fft_ids)
-    lds_fft = std::max(lds_fft, fft_lds_bytes(sensors[s].n_sub, sensors[s].n_fft,
-                                              sensors[s].n_fft / sensors[s].bin));
+    lds_fft = std::max(lds_fft, fft_wave_lds_bytes(sensors[s].n_fft,
+                                                   sensors[s].n_fft / sensors[s].bin));
   auto wave_lds = [&](bool taps, bool with_fft) {
     int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps, 0) : 0;
-    if (with_fft) w = std::max(w, (lds_fft + kWavesPerBlock - 1) / kWavesPerBlock);
+    if (with_fft) w = std::max(w, lds_fft);
     return std::max(16, (w + 15) & ~15);
   };
   const int lds_wave = wave_lds(true, true);
@@ -740,7 +768,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   P->adj_lds_per_wave = otf_ns ? ((adj_lds_bytes(otf_ns, n_layers, P->otf_max_npix) + 15) & ~15) : 16;
   if (P->adj_lds_per_wave * kWavesPerBlock > 65536) P->adj_lds_per_wave = 0;  // adjoint unsupported
   // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
-  b.fft_blocks = (int32_t)((P->fft_tasks + 7) / 8 * 8);
+  b.fft_blocks = (int32_t)((P->fft_tasks + kWavesPerBlock - 1) / kWavesPerBlock);
   default_schedule(P);
   if (P->phase_per_real > 0) {
     const size_t n = (size_t)P->phase_per_real * batch;
@@ -772,6 +800,28 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     delete P;
     return fail(WFS_EUNSUPPORTED, "wfs_plan: projection taps of an FFT-path sensor exceed 64 KiB");
   }
+  if (P->fft_cnt_per_real > 0) {  // chunk partials and counters (counters start at zero)
+    e = hipMalloc((void**)&P->d_fft_part,
+                  sizeof(float) * (size_t)P->fft_part_per_real * P->batch);
+    if (e == hipSuccess)
+      e = hipMalloc((void**)&P->d_fft_cnt,
+                    sizeof(int32_t) * (size_t)P->fft_cnt_per_real * P->batch);
+    if (e == hipSuccess)
+      e = hipMemset(P->d_fft_cnt, 0, sizeof(int32_t) * (size_t)P->fft_cnt_per_real * P->batch);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      if (P->d_fft_part) (void)hipFree(P->d_fft_part);
+      if (P->d_fft_cnt) (void)hipFree(P->d_fft_cnt);
+      (void)hipFree(P->d_blob);
+      if (P->d_phase) (void)hipFree(P->d_phase);
+      delete P;
+      return hip_fail(e, "wfs_plan: FFT-path chunk buffers");
+    }
+    P->base.fft_part = P->d_fft_part;
+    P->base.fft_cnt = P->d_fft_cnt;
+    P->base.fft_part_per_real = P->fft_part_per_real;
+    P->base.fft_cnt_per_real = (int32_t)P->fft_cnt_per_real;
+  }
   if (P->fft_tasks > 0 && P->otf_tasks > 0) {  // both paths: FFT-path blocks on a side stream
     e = hipStreamCreateWithFlags(&P->side.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->side.fork, hipEventDisableTiming);
@@ -782,6 +832,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       if (P->side.stream) (void)hipStreamDestroy(P->side.stream);
       (void)hipFree(P->d_blob);
       if (P->d_phase) (void)hipFree(P->d_phase);
+      if (P->d_fft_part) (void)hipFree(P->d_fft_part);
+      if (P->d_fft_cnt) (void)hipFree(P->d_fft_cnt);
       delete P;
       return hip_fail(e, "wfs_plan: side stream");
     }
@@ -816,6 +868,8 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (P->d_gimg) (void)hipFree(P->d_gimg);
   if (P->d_na) (void)hipFree(P->d_na);
   if (P->d_adj_tab) (void)hipFree(P->d_adj_tab);
+  if (P->d_fft_part) (void)hipFree(P->d_fft_part);
+  if (P->d_fft_cnt) (void)hipFree(P->d_fft_cnt);
   for (float4* q : P->na_retired) (void)hipFree(q);
   if (P->side.join) (void)hipEventDestroy(P->side.join);
   if (P->side.fork) (void)hipEventDestroy(P->side.fork);

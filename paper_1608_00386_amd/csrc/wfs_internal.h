@@ -57,6 +57,10 @@ struct DevSensor {
   int32_t foot_cols_off;  // first entry of this sensor's footprint-column table
   int32_t foot_floats;    // footprint floats of one subaperture, all layers
   float ramp_y;           // the same per pixel row: 1 / (2 n_fft) - tilt_y dx / lambda
+  int32_t fft_part_off;   // FFT path with several spectrum chunks: first float of this sensor's
+                          // partial images in one realisation's part of the partial buffer
+  int32_t fft_cnt_off;    // first of this sensor's chunk counters in one realisation's part
+  int32_t pad4[2];
 };
 
 // Staged-footprint field: the layer pixels one subaperture's bilinear stencils can touch,
@@ -136,6 +140,12 @@ struct FwdParams {
   int32_t lds_per_wave_otf; // bytes when the launch holds no FFT-path blocks
   int32_t otf_from_phase;   // lag-domain field source: 0 gather, 1 phase_in (split), 2 footprint
   int32_t fft_inline;       // host side: FFT-path blocks in the same launch as the others
+  // FFT path: partial binned images of the spectrum chunks ([B][fft_part_per_real] floats)
+  // and per-subaperture chunk counters ([B][fft_cnt_per_real], zero between launches)
+  float* fft_part;
+  int32_t* fft_cnt;
+  int64_t fft_part_per_real;
+  int32_t fft_cnt_per_real;
   TaskTable otf;
   TaskTable fft;
   // projection blocks of one realisation: (first pupil row | column strip << 16, sensor)
