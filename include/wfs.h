@@ -247,7 +247,10 @@ int wfs_project(wfs_plan_t plan, const float* layers, int64_t step, float* phase
  *   the grids).  By default the phase gradients go through the plan's second phase buffer and
  *   each layer pixel gathers its contributions in a fixed order: bitwise deterministic.  With
  *   WFS_FLAG_ADJOINT_ATOMIC the taps are scattered with FP32 atomics (reproducible to
- *   rounding, not bitwise).  Lag-domain sensors only (WFS_EUNSUPPORTED otherwise).
+ *   rounding, not bitwise).  Sensors on the FFT path (large fields) take the gather form
+ *   only: with them, WFS_FLAG_ADJOINT_ATOMIC returns WFS_EUNSUPPORTED.  When fwd_slopes and
+ *   fwd_aux are NULL and the plan has FFT-path sensors, the noise-free forward runs first
+ *   into a plan-owned buffer (allocated on the first call, with the FFT path's chunk shares).
  */
 int wfs_adjoint(wfs_plan_t plan, const float* layers, const float* grad_slopes,
                 const float* fwd_slopes, const float* fwd_aux, int64_t step,

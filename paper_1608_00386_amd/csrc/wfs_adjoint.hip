@@ -16,6 +16,7 @@
 //     pupil pixels from per-step lists (one small kernel per call builds them, the gather
 //     then needs no FP64 and no searches); the others search their candidates per tile;
 //   atomic scatter: each pupil pixel adds its four weighted taps with FP32 atomics.
+#include "wfs_fft.h"
 #include "wfs_otf.h"
 
 namespace wfs {
@@ -707,6 +708,26 @@ hipError_t launch_adjoint_gather_tab(const FwdParams& f, const float* gpsi, floa
 }
 
 int adj_tab_rows() { return kG2TH; }
+
+// FFT-path sensors: one wave per spectrum chunk (fft_adjoint_chunk_m), after the clear of the
+// phase-gradient images and before the gather
+__global__ __launch_bounds__(kBlock) void wfs_adjoint_fft_kernel(AdjParams ap, int lds_per_wave) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = threadIdx.x >> 6;
+  fft_adjoint_wave(ap, blockIdx.x * kWavesPerBlock + w, smem + w * lds_per_wave);
+}
+
+int fft_adj_wave_lds_bytes(int n_fft, int n_pix) { return fft_adj_wave_lds_bytes_impl(n_fft, n_pix); }
+
+hipError_t launch_adjoint_fft(const AdjParams& a, int lds_per_wave, hipStream_t st) {
+  const int64_t tasks = (int64_t)a.f.fft.per_real * a.f.batch;
+  if (tasks == 0) return hipSuccess;
+  const int64_t blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wfs_adjoint_fft_kernel, dim3((unsigned)blocks), dim3(kBlock),
+                     lds_per_wave * kWavesPerBlock, st, a, lds_per_wave);
+  return hipGetLastError();
+}
 
 hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, hipStream_t st) {
   switch (ns) {

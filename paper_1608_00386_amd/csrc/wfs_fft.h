@@ -264,6 +264,204 @@ __device__ void fft_chunk_m(const FwdParams& p, const DevSensor& S, int sid, int
   write_slopes(p, S, b, v, cg);
 }
 
+// ---------------------------------------------------------------------------------------
+// Adjoint of the FFT path (noise off), one wave per spectrum chunk.  With the forward
+// slopes (c_x, c_y) and pixel sum S of the subaperture and its slope gradients (g_x, g_y):
+//   g_B[q] = (g_x (x_q - c_x) + g_y (y_q - c_y)) / S           (nothing when S <= 0)
+//   H_c[k2] = g_B[bin of the chunk's frequency k2] F_c[k2]      (the adjoint of the binning
+//                                                               and the fftshift)
+//   G[m] = sum_c tw_c(m) IDFT_M(H_c)[m2],  tw_c(m) = e^{+2 pi i (k1 . m2 / N + k1 . m1 / Q)}
+//          (G = D^H (g_I F), the unnormalised inverse transform, split by chunks: m = m2 + M m1)
+//   g_psi[m] = 2 c Im(conj(E_m) G_m) kappa.
+// Every chunk forms its share of g_psi on the n x n field pixels; with one chunk it goes
+// straight to the pupil-frame image, otherwise to a partial buffer, and the wave that
+// completes the subaperture's count adds the shares in chunk order (deterministic).
+// ---------------------------------------------------------------------------------------
+__host__ __device__ inline int fft_adj_wave_lds_bytes_impl(int n_fft, int n_pix) {
+  const int M = n_fft >= 32 ? 32 : n_fft;
+  return M * (M + 1) * 8 + ((n_pix * n_pix * 4 + 15) & ~15);
+}
+
+template <int M>
+__device__ void fft_adjoint_chunk_m(const AdjParams& ap, const DevSensor& S, int sid, int b,
+                                    int u, char* wsm) {
+  const FwdParams& p = ap.f;
+  constexpr int G = kWave / M;
+  const int lane = lane_id();
+  const int n = S.n_sub, N = S.n_fft, Q = N / M, Q2 = Q * Q, np = S.n_pix;
+  const int v = u / Q2, c = u - v * Q2;
+  const int k1y = c / Q, k1x = c - k1y * Q;
+  // forward outputs and slope gradients of the subaperture (wave-uniform; all its chunks
+  // take the same decision, so a subaperture without gradient writes nothing)
+  const int64_t so = (int64_t)b * p.n_slopes + S.slope_off + v;
+  const float gx = ap.grad_slopes[so], gy = ap.grad_slopes[so + S.n_valid];
+  const float cx = ap.fwd_slopes[so], cy = ap.fwd_slopes[so + S.n_valid];
+  const float s0 = ap.fwd_aux[(int64_t)b * p.n_valid_total + S.aux_off + v];
+  if (!(s0 > 0.0f) || (gx == 0.0f && gy == 0.0f)) return;
+  const DevSubap sb = cload(p.sub, S.valid_off + v);
+  const int nx1 = (n + M - 1) / M;
+  float2* X = reinterpret_cast<float2*>(wsm);              // [M][M + 1]
+  float* gB = reinterpret_cast<float*>(wsm + M * (M + 1) * 8);  // [np][np]
+  const float* ph = p.phase_in + (int64_t)b * p.phase_per_real + S.phase_off + (int64_t)v * n * n;
+  const uint8_t* mrow0 = p.mask + S.mask_off + (sb.a * n) * S.n_pup + sb.b * n;
+  {
+    const float half = 0.5f * (float)(np - 1), inv = 1.0f / s0;
+    for (int q = lane; q < np * np; q += kWave) {
+      const int qy = q / np, qx = q - qy * np;
+      gB[q] = (gx * ((float)qx - half - cx) + gy * ((float)qy - half - cy)) * inv;
+    }
+  }
+  // the field's phase in turns at (y, x), or a dark pixel
+  auto turns_at = [&](int y, int x, bool& lit) {
+    lit = mrow0[y * S.n_pup + x] != 0;
+    float t = fmaf(ph[y * n + x], 0.15915494309189535f,
+                   -fmaf((float)x, S.ramp_x, (float)y * S.ramp_y));
+    return t - rintf(t);
+  };
+  // 1. the forward chunk: fold, row and column FFTs (as fft_chunk_m)
+  {
+    const int x2 = lane & (M - 1), g = lane / M;
+    for (int y2 = g; y2 < M; y2 += G) {
+      float2 acc = make_float2(0.0f, 0.0f);
+      for (int y1 = 0; y1 < nx1; ++y1) {
+        const int y = y2 + M * y1;
+        if (y >= n) break;
+        for (int x1 = 0; x1 < nx1; ++x1) {
+          const int x = x2 + M * x1;
+          if (x >= n) continue;
+          bool lit;
+          const float t = turns_at(y, x, lit);
+          if (lit) {
+            float rot = t - (float)(y1 * k1y + x1 * k1x) / (float)Q -
+                        (float)(y2 * k1y + x2 * k1x) / (float)N;
+            rot -= rintf(rot);
+            float sn, cs;
+            sincos_rev(rot, &sn, &cs);
+            acc.x += cs;
+            acc.y += sn;
+          }
+        }
+      }
+      X[y2 * (M + 1) + x2] = acc;
+    }
+  }
+  wave_sync();
+  if (lane < M) {
+    float2 xr[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xr[k] = X[lane * (M + 1) + k];
+    fft_reg<M>(xr);
+#pragma unroll
+    for (int k = 0; k < M; ++k) X[lane * (M + 1) + k] = xr[k];
+  }
+  wave_sync();
+  // 2. column lane k2x: H = g_I F, then the inverse transform along y (conjugate, forward
+  //    FFT, conjugate: the unnormalised inverse)
+  if (lane < M) {
+    float2 xc[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xc[k] = X[k * (M + 1) + lane];
+    fft_reg<M>(xc);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      float gi;
+      if (Q == 1) {  // frequency (k, lane) of the whole spectrum: bin of its fftshifted pixel
+        const int fy = (k + N / 2) % N, fx = (lane + N / 2) % N;
+        gi = gB[(fy / S.bin) * np + fx / S.bin];
+      } else {
+        gi = gB[((k + M / 2) & (M - 1)) * M + ((lane + M / 2) & (M - 1))];
+      }
+      xc[k] = make_float2(gi * xc[k].x, -gi * xc[k].y);  // conj(g_I F)
+    }
+    fft_reg<M>(xc);
+#pragma unroll
+    for (int k = 0; k < M; ++k) X[k * (M + 1) + lane] = make_float2(xc[k].x, -xc[k].y);
+  }
+  wave_sync();
+  // 3. row lane y2: the inverse transform along x
+  if (lane < M) {
+    float2 xr[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float2 z = X[lane * (M + 1) + k];
+      xr[k] = make_float2(z.x, -z.y);
+    }
+    fft_reg<M>(xr);
+#pragma unroll
+    for (int k = 0; k < M; ++k) X[lane * (M + 1) + k] = make_float2(xr[k].x, -xr[k].y);
+  }
+  wave_sync();
+  // 4. this chunk's share of g_psi on the field pixels m = (y2 + M y1, x2 + M x1)
+  const float c2k = 2.0f * S.flux_c * S.kappa;
+  float* gout = ap.gpsi + (int64_t)b * p.pupil_per_real + S.pupil_off +
+                (int64_t)sb.a * n * S.n_pup + sb.b * n;
+  float* part = Q == 1 ? nullptr
+                       : ap.fft_adj_part + (int64_t)b * ap.fft_adj_per_real + S.fft_adj_off +
+                             ((int64_t)v * Q2 + c) * (n * n);
+  {
+    const int x2 = lane & (M - 1), g = lane / M;
+    for (int y2 = g; y2 < M; y2 += G) {
+      const float2 yv = X[y2 * (M + 1) + x2];
+      for (int y1 = 0; y1 < nx1; ++y1) {
+        const int y = y2 + M * y1;
+        if (y >= n) break;
+        for (int x1 = 0; x1 < nx1; ++x1) {
+          const int x = x2 + M * x1;
+          if (x >= n) continue;
+          bool lit;
+          const float t = turns_at(y, x, lit);
+          float r = 0.0f;
+          if (lit) {
+            float rot = (float)(y2 * k1y + x2 * k1x) / (float)N +
+                        (float)(y1 * k1y + x1 * k1x) / (float)Q;
+            rot -= rintf(rot);
+            float sn, cs;
+            sincos_rev(rot, &sn, &cs);
+            const float gr = yv.x * cs - yv.y * sn, gim = yv.x * sn + yv.y * cs;  // G share
+            float es, ec;
+            sincos_rev(t, &es, &ec);
+            r = c2k * (ec * gim - es * gr);  // 2 c kappa Im(conj(E) G)
+          }
+          if (Q == 1) gout[y * S.n_pup + x] = r;
+          else part[y * n + x] = r;
+        }
+      }
+    }
+  }
+  if (Q == 1) return;
+  // 5. the wave completing the subaperture's count adds the shares in chunk order
+  __threadfence();
+  int32_t* cnt = p.fft_cnt + (int64_t)b * p.fft_cnt_per_real + S.fft_cnt_off + v;
+  int old = 0;
+  if (lane == 0) old = atomicAdd(cnt, 1);
+  old = __shfl(old, 0, kWave);
+  if (old != Q2 - 1) return;  // wave-uniform
+  __threadfence();
+  if (lane == 0) *cnt = 0;
+  const float* part0 = ap.fft_adj_part + (int64_t)b * ap.fft_adj_per_real + S.fft_adj_off +
+                       (int64_t)v * Q2 * (n * n);
+  for (int q = lane; q < n * n; q += kWave) {
+    float sum = 0.0f;
+    for (int cc = 0; cc < Q2; ++cc) sum += __builtin_nontemporal_load(part0 + cc * (n * n) + q);
+    const int y = q / n, x = q - y * n;
+    gout[y * S.n_pup + x] = sum;
+  }
+}
+
+__device__ __forceinline__ void fft_adjoint_wave(const AdjParams& ap, int task, char* wsm) {
+  const FwdParams& p = ap.f;
+  const int total = p.fft.per_real * p.batch;
+  if (task >= total) return;
+  int b, sid, u;
+  task = __builtin_amdgcn_readfirstlane(task);
+  task_of(p.fft, task, b, sid, u);
+  const DevSensor S = cload(p.sen, sid);
+  if (S.n_fft >= 32)
+    fft_adjoint_chunk_m<32>(ap, S, sid, b, u, wsm);
+  else
+    fft_adjoint_chunk_m<16>(ap, S, sid, b, u, wsm);
+}
+
 // FFT-path task t (one wave): spectrum chunk (t - start) mod Q^2 of subaperture
 // (t - start) / Q^2 of its sensor.
 __device__ __forceinline__ void fft_wave(const FwdParams& p, int task, int64_t step,

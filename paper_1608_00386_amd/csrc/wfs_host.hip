@@ -30,6 +30,8 @@ hipError_t launch_adjoint_gather_tab(const FwdParams& f, const float* gpsi, floa
                                      const int64_t* tab_off, const int32_t* blk_start,
                                      hipStream_t st);
 int adj_tab_rows();
+int fft_adj_wave_lds_bytes(int n_fft, int n_pix);
+hipError_t launch_adjoint_fft(const AdjParams& a, int lds_per_wave, hipStream_t st);
 int adj_lds_bytes(int ns, int n_layers, int n_pix);
 hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B,
                              int64_t* floats);
@@ -147,6 +149,10 @@ struct wfs_plan_s {
   int frames = 0;
   int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
   SideStream side{};         // FFT-path blocks run here concurrently (plans with both paths)
+  float* d_fft_adj = nullptr;    // FFT-path adjoint: per-chunk phase-gradient shares and the
+  float* d_adj_fwd = nullptr;    // noise-free forward outputs it needs ([B][n_slopes + n_valid])
+  int64_t fft_adj_per_real = 0;  // (both allocated on the first adjoint call)
+  int fft_adj_lds = 0;           // LDS bytes per FFT-path adjoint wave
   float* d_fft_part = nullptr;   // FFT path: partial images of the spectrum chunks
   int32_t* d_fft_cnt = nullptr;  // and per-subaperture chunk counters (zero between launches)
   int64_t fft_part_per_real = 0, fft_cnt_per_real = 0;
@@ -606,17 +612,22 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   // FFT path with several spectrum chunks: per realisation, every such sensor's partial
   // images (Q^2 chunks of M x M floats = n_fft^2 per subaperture) and chunk counters
-  int64_t fft_part = 0, fft_cnt = 0;
+  int64_t fft_part = 0, fft_cnt = 0, fft_adj = 0;
   for (int s : fft_ids) {
-    const int N = sensors[s].n_fft, M = N >= 32 ? 32 : N;
+    const int N = sensors[s].n_fft, M = N >= 32 ? 32 : N, Q = N / M;
     ds[s].fft_part_off = (int32_t)std::min<int64_t>(fft_part, (1LL << 31) - 1);
     ds[s].fft_cnt_off = (int32_t)fft_cnt;
-    if (N / M > 1) {
+    ds[s].fft_adj_off = (int32_t)std::min<int64_t>(fft_adj, (1LL << 31) - 1);
+    if (Q > 1) {
       fft_part += (int64_t)ds[s].n_valid * N * N;
       fft_cnt += ds[s].n_valid;
+      fft_adj += (int64_t)ds[s].n_valid * Q * Q * sensors[s].n_sub * sensors[s].n_sub;
     }
+    P->fft_adj_lds = std::max(P->fft_adj_lds,
+                              (fft_adj_wave_lds_bytes(N, N / sensors[s].bin) + 15) & ~15);
   }
-  if (fft_part > (1LL << 31) - 1) {
+  P->fft_adj_per_real = fft_adj;
+  if (fft_part > (1LL << 31) - 1 || fft_adj > (1LL << 31) - 1) {
     delete P;
     return fail(WFS_EINVAL, "wfs_plan: FFT-path partial images too large");
   }
@@ -870,6 +881,8 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (P->d_adj_tab) (void)hipFree(P->d_adj_tab);
   if (P->d_fft_part) (void)hipFree(P->d_fft_part);
   if (P->d_fft_cnt) (void)hipFree(P->d_fft_cnt);
+  if (P->d_fft_adj) (void)hipFree(P->d_fft_adj);
+  if (P->d_adj_fwd) (void)hipFree(P->d_adj_fwd);
   for (float4* q : P->na_retired) (void)hipFree(q);
   if (P->side.join) (void)hipEventDestroy(P->side.join);
   if (P->side.fork) (void)hipEventDestroy(P->side.fork);
@@ -1256,10 +1269,14 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   if (rc) return rc;
   rc = check_device(P, "wfs_adjoint");
   if (rc) return rc;
-  if (P->fft_tasks > 0)
-    return fail(WFS_EUNSUPPORTED, "wfs_adjoint: sensors on the FFT path have no adjoint kernel");
-  if (P->adj_lds_per_wave == 0)
+  if (P->otf_tasks > 0 && P->adj_lds_per_wave == 0)
     return fail(WFS_EUNSUPPORTED, "wfs_adjoint: lag-domain adjoint needs more than 64 KiB of LDS");
+  const bool fft = P->fft_tasks > 0;
+  if (fft && ((P->flags & WFS_FLAG_ADJOINT_ATOMIC) || P->pupil_per_real >= (1LL << 30)))
+    return fail(WFS_EUNSUPPORTED,
+                "wfs_adjoint: FFT-path sensors take the gather form only (no atomic scatter)");
+  if (fft && !P->d_phase)
+    return fail(WFS_EUNSUPPORTED, "wfs_adjoint: FFT-path sensors need the plan's phase buffer");
   AdjParams a;
   a.f = call_params(P, layers, step, 0, nullptr, nullptr);
   a.f.noise_on = 0;
@@ -1279,6 +1296,19 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
       return hip_fail(ea, "wfs_adjoint: phase-gradient images");
     }
   }
+  if (fft && !P->d_adj_fwd) {  // FFT path: chunk shares and the forward outputs it needs
+    hipError_t ea = hipMalloc((void**)&P->d_adj_fwd,
+                              sizeof(float) * (size_t)(P->n_slopes + P->n_valid_total) * P->batch);
+    if (ea == hipSuccess && P->fft_adj_per_real > 0)
+      ea = hipMalloc((void**)&P->d_fft_adj,
+                     sizeof(float) * (size_t)P->fft_adj_per_real * P->batch);
+    if (ea != hipSuccess) {
+      if (P->d_adj_fwd) (void)hipFree(P->d_adj_fwd);
+      P->d_adj_fwd = nullptr;
+      P->d_fft_adj = nullptr;
+      return hip_fail(ea, "wfs_adjoint: FFT-path buffers");
+    }
+  }
   if (gather && P->adj_ent > 0 && !P->d_adj_tab) {  // and the gather's stencil lists
     hipError_t ea = hipMalloc((void**)&P->d_adj_tab, sizeof(int2) * (size_t)P->adj_ent);
     if (ea != hipSuccess) {
@@ -1296,8 +1326,33 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
     a.f.phase_in = P->d_phase;
     a.f.otf_from_phase = 1;
   }
+  if (fft) {
+    // FFT-path sensors need the noise-free forward outputs (run them when not given) and
+    // the projected phase of their pixels
+    if (!a.fwd_slopes) {
+      FwdParams q = call_params(P, layers, step, 0, P->d_adj_fwd,
+                                P->d_adj_fwd + (int64_t)P->n_slopes * P->batch);
+      q.noise_on = 0;
+      e = launch_fwd_modes(P, q, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: forward for the FFT-path sensors");
+      a.fwd_slopes = P->d_adj_fwd;
+      a.fwd_aux = P->d_adj_fwd + (int64_t)P->n_slopes * P->batch;
+    }
+    if (!a.f.phase_in) {
+      set_proj(a.f, P->proj_fft);
+      e = launch_project(a.f, P->d_phase, P->proj_lds_fft, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: projection launch");
+      a.f.phase_in = P->d_phase;
+    }
+  }
+  a.fft_adj_part = P->d_fft_adj;
+  a.fft_adj_per_real = P->fft_adj_per_real;
   e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, P->adj_clear_grad, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: launch");
+  if (fft) {
+    e = launch_adjoint_fft(a, P->fft_adj_lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: FFT-path launch");
+  }
   if (gather) {
     e = launch_adjoint_gather_tab(a.f, P->d_gimg, grad_layers, P->d_adj_tab, P->d_adj_segs,
                                   P->adj_nseg, P->adj_maxn, P->d_adj_tab_off,

@@ -60,7 +60,9 @@ struct DevSensor {
   int32_t fft_part_off;   // FFT path with several spectrum chunks: first float of this sensor's
                           // partial images in one realisation's part of the partial buffer
   int32_t fft_cnt_off;    // first of this sensor's chunk counters in one realisation's part
-  int32_t pad4[2];
+  int32_t fft_adj_off;    // adjoint: first float of this sensor's chunk partials (n_sub^2 per
+                          // chunk) in one realisation's part of the adjoint partial buffer
+  int32_t pad4;
 };
 
 // Staged-footprint field: the layer pixels one subaperture's bilinear stencils can touch,
@@ -181,6 +183,8 @@ struct AdjParams {
   const float* fwd_aux;     // or null
   float* grad_layers;       // [B][layer_stride]
   float* gpsi;              // gather mode: [B][pupil_per_real] phase-gradient images, or null
+  float* fft_adj_part;      // FFT path: [B][fft_adj_per_real] per-chunk phase-gradient partials
+  int64_t fft_adj_per_real;
 };
 
 // Table-driven gather of the layer gradient.  For a (sensor, layer, axis) whose inverse

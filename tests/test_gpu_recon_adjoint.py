@@ -159,6 +159,44 @@ def test_adjoint_matches_oracle(name, saved, mode):
     assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("name", ["fft_ngs_n14_N32_b4", "fft_ngs_n20_N64_b2",
+                                  "fft_ngs_n64_N128_b4", "fft_ngs_n40_N128_b4",
+                                  "mixed_lgs_ngs_batch2"])
+@pytest.mark.parametrize("saved", [False, True])
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_adjoint_fft_path_matches_oracle(name, saved, mode):
+    """Sensors on the FFT path (one wave per spectrum chunk: one chunk at N = 32, four at 64,
+    sixteen at 128), alone and beside a lag-domain LGS, against the FP64 oracle gradient."""
+    torch, W = _gpu()
+    cfg, x, g = _adjoint_case(name)
+    step = 5
+    plan = W.Plan(cfg, flags=W.WFS_FLAG_SPLIT if mode == "split" else W.WFS_FLAG_FUSED)
+    assert 1 in plan.paths
+    xt = torch.from_numpy(x).cuda()
+    gt = torch.from_numpy(g).cuda()
+    if saved:
+        s, a = plan.forward(xt, step=step)
+        out = plan.adjoint(xt, gt, step=step, fwd_slopes=s, fwd_aux=a)
+    else:
+        out = plan.adjoint(xt, gt, step=step)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.adjoint(x.astype(np.float64), cfg, step, g.astype(np.float64))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-4, rel
+    assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max()
+    o2 = plan.adjoint(xt, gt, step=step)
+    assert torch.equal(o2, plan.adjoint(xt, gt, step=step))  # bitwise deterministic
+
+
+def test_adjoint_fft_path_refuses_the_atomic_scatter():
+    torch, W = _gpu()
+    cfg, x, g = _adjoint_case("fft_ngs_n14_N32_b4")
+    plan = W.Plan(cfg, flags=W.WFS_FLAG_ADJOINT_ATOMIC)
+    with pytest.raises(W.WfsError) as e:
+        plan.adjoint(torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda(), step=1)
+    assert e.value.code == -4
+
+
 @pytest.mark.parametrize("name", ["lgs_n10_N32_b4_noise", "dm_two_ngs_batch2"])
 def test_adjoint_gather_is_bitwise_deterministic(name):
     torch, W = _gpu()
