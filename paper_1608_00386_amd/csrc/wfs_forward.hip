@@ -81,9 +81,11 @@ int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floa
   return otf_lds_layout(ns, n_layers, n_pix, with_taps, foot_floats).total;
 }
 
-int project_lds_bytes(int n_layers) {
-  return n_layers * (kProjStrip + kProjRows) * (int)sizeof(Tap);
+int project_lds_bytes(int n_layers, int rows) {
+  return n_layers * (kProjStrip + rows) * (int)sizeof(Tap);
 }
+
+int project_max_groups() { return kProjMaxGroups; }
 
 int project_strip() { return kProjStrip; }
 int project_rows() { return kProjRows; }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <set>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -18,7 +19,8 @@
 namespace wfs {
 hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const SideStream* side);
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
-int project_lds_bytes(int n_layers);
+int project_lds_bytes(int n_layers, int rows);
+int project_max_groups();
 int project_strip();
 int project_rows();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
@@ -532,17 +534,20 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
              (L.boundary != 0 || (fw <= L.nx && fh <= L.ny)) &&
              L.offset + (int64_t)L.nx * L.ny <= (1LL << 30);
         if (!ok) break;
+        // the window goes to LDS column by column, each column in a slot of n_sub + 2 floats
+        // (rows fh.. of a slot are never read): a column's stores take immediate offsets
+        const int pitch = S.n_sub + 2;
         foot[(size_t)s * n_layers + l] = make_int4(fw, fh, floats, 0);
         for (int j = 0; j < fw; ++j)
           foot_cols.push_back(FootCol{(int32_t)L.offset, L.nx, L.ny, L.boundary, fw, fh,
-                                      floats + j, (l << 8) | j});
+                                      floats + j * pitch, (l << 8) | j});
         FootAxis& X = foot_axis[((size_t)s * n_layers + l) * 2];
         FootAxis& Y = foot_axis[((size_t)s * n_layers + l) * 2 + 1];
-        X = FootAxis{A.ax, A.bx0, A.dbx, 1.0 / L.nx, L.nx, L.boundary, 1, 0, 1.0f, {0, 0, 0}};
-        Y = FootAxis{A.ay, A.by0, A.dby, 1.0 / L.ny, L.ny, L.boundary, fw, floats, L.weight,
+        X = FootAxis{A.ax, A.bx0, A.dbx, 1.0 / L.nx, L.nx, L.boundary, pitch, floats, 1.0f,
                      {0, 0, 0}};
+        Y = FootAxis{A.ay, A.by0, A.dby, 1.0 / L.ny, L.ny, L.boundary, 1, 0, L.weight, {0, 0, 0}};
         cols += fw;
-        floats += fw * fh;
+        floats += fw * pitch;
       }
       if (ok) {
         d.foot_cols_off = (int32_t)foot_cols.size() - cols;
@@ -633,6 +638,30 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   P->fft_part_per_real = fft_part;
   P->fft_cnt_per_real = fft_cnt;
+  // Taller projection blocks (G row groups: each column tap serves G times more pixels) when
+  // a launch still has enough blocks to fill the chip at two per CU and SIMD pair.
+  {
+    int64_t n1 = 0;
+    for (int s = 0; s < n_sensors; ++s) n1 += (int64_t)proj_desc_s[s].size();
+    n1 *= batch;
+    int G = 1;
+    while (2 * G <= project_max_groups() && n1 / (2 * G) >= 4096 &&
+           project_lds_bytes(n_layers, project_rows() * 2 * G) <= 32768)
+      G *= 2;
+    if (G > 1) {
+      const int RG = project_rows(), RT = RG * G;
+      for (int s = 0; s < n_sensors; ++s) {
+        std::vector<int2> merged;
+        std::set<std::pair<int, int>> seen;
+        for (const int2& d : proj_desc_s[s]) {
+          const int r0 = (d.x & 0xFFFF) / RT * RT, st = d.x >> 16;
+          if (seen.insert({r0, st}).second) merged.push_back(make_int2(r0 | (st << 16), s));
+        }
+        proj_desc_s[s] = merged;
+        ds[s].proj_rows = RT;
+      }
+    }
+  }
   P->hsen = ds;
   P->n_slopes = slope_off;
   P->n_valid_total = aux_off;
@@ -655,12 +684,36 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   if (foot_cols.empty()) foot_cols.push_back(FootCol{});
   const size_t o_fcols = push_table(blob, foot_cols);
   const size_t o_faxis = push_table(blob, foot_axis);
-  std::vector<int2> desc_all, desc_fft;
-  for (int s = 0; s < n_sensors; ++s) {
-    desc_all.insert(desc_all.end(), proj_desc_s[s].begin(), proj_desc_s[s].end());
-    if (ds[s].path == kPathFft)
-      desc_fft.insert(desc_fft.end(), proj_desc_s[s].begin(), proj_desc_s[s].end());
-  }
+  // Projection blocks of all sensors interleaved by their relative place in the pupil (row
+  // group, then strip, then sensor): the sensors of a realisation read overlapping layer
+  // regions (all of them the same ground-layer pixels), and blocks that are neighbours in
+  // this order run at about the same time on the same XCD, so those reads meet in its L2
+  // instead of each sensor's pass re-fetching the layers from memory.
+  auto interleave = [&](bool fft_only) {
+    struct Key {
+      double row, col;
+      int s;
+      int2 d;
+    };
+    std::vector<Key> keys;
+    for (int s = 0; s < n_sensors; ++s) {
+      if (fft_only && ds[s].path != kPathFft) continue;
+      const double np = (double)ds[s].n_pup;
+      for (const int2& d : proj_desc_s[s])
+        keys.push_back(Key{(double)(d.x & 0xFFFF) / np,
+                           (double)(d.x >> 16) * project_strip() / np, s, d});
+    }
+    std::stable_sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+      if (a.row != b.row) return a.row < b.row;
+      if (a.col != b.col) return a.col < b.col;
+      return a.s < b.s;
+    });
+    std::vector<int2> out;
+    out.reserve(keys.size());
+    for (const Key& k : keys) out.push_back(k.d);
+    return out;
+  };
+  const std::vector<int2> desc_all = interleave(false), desc_fft = interleave(true);
   const size_t o_pall = push_table(blob, desc_all);
   const size_t o_pfft = push_table(blob, desc_fft);
   std::vector<int64_t> step0(1, 0);
@@ -718,7 +771,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     fill_tasks(b.fft, fft_ids, units);
   }
   for (int s = 0; s < n_sensors; ++s) {
-    const int lb = project_lds_bytes(n_layers);
+    const int lb = project_lds_bytes(n_layers, ds[s].proj_rows);
     P->proj_lds = std::max(P->proj_lds, lb);
     if (ds[s].path == kPathFft) P->proj_lds_fft = std::max(P->proj_lds_fft, lb);
   }

@@ -48,15 +48,17 @@ __host__ __device__ constexpr int otf_part_rows(int ns) {
 }
 
 // Per-wave LDS layout (bytes), shared with the host sizing code:
-//   E [n_sub^2] float2 | tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2 |
-//   AW [n_sub][2 n_sub - 1] float2 (weighted lag sums) |
+//   E [n_sub^2] float2 | AW [n_sub][2 n_sub - 1] float2 (weighted lag sums) |
 //   union( taps [n_layers][2 n_sub] Tap (fused gather and adjoint only),
 //          partial lag rows (one round, one pass over the lag row at a time:
 //          [jobs][ceil((2 n_sub - 1) / kOtfLagParts)] float2),
-//          P (later B) + Z (after the last round) )
-// With a staged footprint (foot_floats > 0) the field stage also lays out, from the start of
-// AW (free until the lag sums): stencil entries [n_layers][2 n_sub] FootTap (12 bytes) | the
-// footprint [foot_floats] float (first holding the window origins, [n_layers][2] int).
+//          P (later B) + Z (after the last round) ) |
+//   tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2
+// With a staged footprint (foot_floats > 0) the field stage also lays out, from offset 0
+// (E, AW and the union are free until the field is formed): stencil entries
+// [n_layers][2 n_sub] FootTap (12 bytes) | the footprint [foot_floats] float (first holding
+// the window origins, [n_layers][2] int).  The tables, written before the footprint, sit
+// past both.
 struct OtfLds {
   int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off;
   int fw_off, fp_off, total;
@@ -67,9 +69,7 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   OtfLds o;
   const int jobs = otf_part_rows(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
-  o.stab_off = ns * ns * 8;
-  o.wtab_off = o.stab_off + lags * 8;
-  o.aw_off = o.wtab_off + n_pix * 8;
+  o.aw_off = ns * ns * 8;
   const int u0 = (o.aw_off + ns * lags * 8 + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
   const int part = jobs * ((lags + kOtfLagParts - 1) / kOtfLagParts) * 8;
@@ -82,11 +82,13 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   if (o.p_off + 1024 > end) end = o.p_off + 1024;  // matrix-core image: 16 x 16 floats
   if (u0 + part > end) end = u0 + part;
   if (with_taps && u0 + taps > end) end = u0 + taps;
-  o.fw_off = (o.aw_off + 15) & ~15;
-  o.fp_off = (o.fw_off + 2 * ns * n_layers * 12 + 15) & ~15;
+  o.fw_off = 0;
+  o.fp_off = (2 * ns * n_layers * 12 + 15) & ~15;
   const int fpb = 4 * (foot_floats > 2 * n_layers ? foot_floats : 2 * n_layers);
   if (foot_floats > 0 && o.fp_off + fpb > end) end = o.fp_off + fpb;
-  o.total = (end + 15) & ~15;
+  o.stab_off = (end + 7) & ~7;
+  o.wtab_off = o.stab_off + lags * 8;
+  o.total = (o.wtab_off + n_pix * 8 + 15) & ~15;
   return o;
 }
 
@@ -296,10 +298,12 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
       }
     }
   }
-  // 2. window columns (32-bit element offsets: the plan keeps every layer below 2^30 floats).
-  // Rows leave the grid (wrap, or clamp on a zero-boundary grid) only for windows at a grid
-  // edge: when no lane's window does, the rows are plain strides.
-  const float* lay_b = p.layers + (int64_t)b * p.layer_stride;
+  // 2. window columns (32-bit byte offsets: the plan keeps every layer below 2^30 floats),
+  // all ROWS rows of a column slot (rows fh.. of a slot are loaded and stored but never
+  // read).  Rows leave the grid (wrap, or clamp on a zero-boundary grid) only for windows at
+  // a grid edge: when no lane's window does, the rows are plain strides and each column is
+  // ROWS unpredicated loads and stores at immediate offsets.
+  const char* lay_b = reinterpret_cast<const char*>(p.layers + (int64_t)b * p.layer_stride);
   float val[2][ROWS];
   int cbase[2], oyv[2];
   bool edge = false;
@@ -313,15 +317,20 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
     if (C.boundary == 0) col -= col >= C.nx ? C.nx : 0;
     else col = min(max(col, 0), C.nx - 1);
     cbase[k] = C.offset + col;
-    edge = edge || (C.fh > 0 && (oyv[k] < 0 || oyv[k] + C.fh > C.ny));
+    edge = edge || (C.fh > 0 && (oyv[k] < 0 || oyv[k] + ROWS > C.ny));
   }
   if (__builtin_amdgcn_ballot_w64(edge) == 0) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int r0 = cbase[k] + oyv[k] * fc[k].nx;
+      // a lane without a column reads the realisation's first float ROWS times
+      const bool has = fc[k].fh > 0;
+      uint32_t off = has ? (uint32_t)(cbase[k] + oyv[k] * fc[k].nx) * 4u : 0u;
+      const uint32_t stride = has ? (uint32_t)fc[k].nx * 4u : 0u;
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i)
-        if (i < fc[k].fh) val[k][i] = ld_idx(lay_b, (uint32_t)(r0 + i * fc[k].nx));
+      for (int i = 0; i < ROWS; ++i) {
+        val[k][i] = *reinterpret_cast<const float*>(lay_b + off);
+        off += stride;
+      }
     }
   } else {
 #pragma unroll
@@ -333,16 +342,21 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
         int rr = oyv[k] + i;
         if (rr >= C.ny) rr = periodic ? rr - C.ny : C.ny - 1;
         rr = max(rr, 0);
-        if (i < C.fh) val[k][i] = ld_idx(lay_b, (uint32_t)(cbase[k] + rr * C.nx));
+        val[k][i] = i < C.fh ? ld_idx(reinterpret_cast<const float*>(lay_b),
+                                       (uint32_t)(cbase[k] + rr * C.nx))
+                             : 0.0f;
       }
     }
   }
   wave_sync();  // the window overwrites the origins
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 2; ++k) {
+    if (fc[k].fh > 0) {
+      float* dst = fp + fc[k].dst;
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i)
-      if (i < fc[k].fh) fp[fc[k].dst + i * fc[k].fw] = val[k][i];
+      for (int i = 0; i < ROWS; ++i) dst[i] = val[k][i];
+    }
+  }
   wave_sync();
   // 3. stencils, in the projection kernel's chunks of layers (a last partial chunk is padded
   // with zero-weight repeats of the last layer, as there)
@@ -356,16 +370,15 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
     psi[i] = 0.0f;
   }
   auto stencil = [&](int l, bool pad) {
-    const int fw4 = cload(p.foot, fbase + l).x * 4;
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
       const FootTap cx = tab[l * TPL + pc[i]];
       const FootTap ry = tab[l * TPL + NS + pr[i]];
-      const char* w0p = reinterpret_cast<const char*>(fp) + (ry.k + cx.k);
-      const float v00 = reinterpret_cast<const float*>(w0p)[0];
-      const float v01 = reinterpret_cast<const float*>(w0p)[1];
-      const float v10 = reinterpret_cast<const float*>(w0p + fw4)[0];
-      const float v11 = reinterpret_cast<const float*>(w0p + fw4)[1];
+      // column-major window: the next row is the next float, the next column a slot later
+      const float* w0p =
+          reinterpret_cast<const float*>(reinterpret_cast<const char*>(fp) + (ry.k + cx.k));
+      const float v00 = w0p[0], v10 = w0p[1];
+      const float v01 = w0p[ROWS], v11 = w0p[ROWS + 1];
       const float r0v = fmaf(cx.w0, v00, cx.w1 * v01);
       const float r1v = fmaf(cx.w0, v10, cx.w1 * v11);
       const float wy0 = pad ? 0.0f : ry.w0, wy1 = pad ? 0.0f : ry.w1;
@@ -408,6 +421,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
   if constexpr (FIELD == kFieldFoot) {
     float ph[PPL];
     foot_phase<NS>(p, S, sb, sid, b, stepd, wsm, lo, ph);
+    wave_sync();  // E overlays the stencil entries the last stencil pass read
     float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
