@@ -633,17 +633,21 @@ __global__ __launch_bounds__(kBlock) void zero_kernel(float* x, int64_t n) {
 }
 
 template <int NS>
-static hipError_t launch_adj(AdjParams a, bool clear_grad, hipStream_t st) {
+static hipError_t launch_adj(AdjParams a, bool clear_grad, bool clear, hipStream_t st) {
   // atomic mode accumulates into the gradient; gather mode into the phase-gradient images
-  float* z = a.gpsi ? a.gpsi : a.grad_layers;
-  const int64_t n = a.gpsi ? a.f.pupil_per_real * a.f.batch : a.f.layer_stride * a.f.batch;
-  const int zb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
-  hipLaunchKernelGGL(zero_kernel, dim3(zb > 0 ? zb : 1), dim3(kBlock), 0, st, z, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  // (cleared by the first of the launches that add into them)
+  hipError_t e = hipSuccess;
+  if (clear) {
+    float* z = a.gpsi ? a.gpsi : a.grad_layers;
+    const int64_t n = a.gpsi ? a.f.pupil_per_real * a.f.batch : a.f.layer_stride * a.f.batch;
+    const int zb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(zero_kernel, dim3(zb > 0 ? zb : 1), dim3(kBlock), 0, st, z, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   // the gather writes every grid pixel; the rest of the gradient buffer (gaps between the
   // grids inside the stride) is cleared only when there is such a gap
-  if (a.gpsi && clear_grad) {
+  if (clear && a.gpsi && clear_grad) {
     const int64_t ng = a.f.layer_stride * a.f.batch;
     const int zg = (int)std::min<int64_t>((ng + kBlock - 1) / kBlock, 8192);
     hipLaunchKernelGGL(zero_kernel, dim3(zg > 0 ? zg : 1), dim3(kBlock), 0, st, a.grad_layers,
@@ -729,19 +733,20 @@ hipError_t launch_adjoint_fft(const AdjParams& a, int lds_per_wave, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, hipStream_t st) {
+hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, bool clear,
+                          hipStream_t st) {
   switch (ns) {
-    case 2: return launch_adj<2>(a, clear_grad, st);
-    case 3: return launch_adj<3>(a, clear_grad, st);
-    case 4: return launch_adj<4>(a, clear_grad, st);
-    case 5: return launch_adj<5>(a, clear_grad, st);
-    case 6: return launch_adj<6>(a, clear_grad, st);
-    case 7: return launch_adj<7>(a, clear_grad, st);
-    case 8: return launch_adj<8>(a, clear_grad, st);
-    case 9: return launch_adj<9>(a, clear_grad, st);
-    case 10: return launch_adj<10>(a, clear_grad, st);
-    case 11: return launch_adj<11>(a, clear_grad, st);
-    case 12: return launch_adj<12>(a, clear_grad, st);
+    case 2: return launch_adj<2>(a, clear_grad, clear, st);
+    case 3: return launch_adj<3>(a, clear_grad, clear, st);
+    case 4: return launch_adj<4>(a, clear_grad, clear, st);
+    case 5: return launch_adj<5>(a, clear_grad, clear, st);
+    case 6: return launch_adj<6>(a, clear_grad, clear, st);
+    case 7: return launch_adj<7>(a, clear_grad, clear, st);
+    case 8: return launch_adj<8>(a, clear_grad, clear, st);
+    case 9: return launch_adj<9>(a, clear_grad, clear, st);
+    case 10: return launch_adj<10>(a, clear_grad, clear, st);
+    case 11: return launch_adj<11>(a, clear_grad, clear, st);
+    case 12: return launch_adj<12>(a, clear_grad, clear, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -24,7 +24,8 @@ int project_max_groups();
 int project_strip();
 int project_rows();
 hipError_t launch_step(int64_t* step_dev, int64_t value, int add, hipStream_t st);
-hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, hipStream_t st);
+hipError_t launch_adjoint(const AdjParams& a, int ns, bool clear_grad, bool clear,
+                          hipStream_t st);
 hipError_t launch_adjoint_gather(const FwdParams& f, const float* gpsi, float* grad,
                                  const int32_t* blk_start, hipStream_t st);
 hipError_t launch_adjoint_gather_tab(const FwdParams& f, const float* gpsi, float* grad,
@@ -102,6 +103,15 @@ static void set_proj(FwdParams& p, const ProjTable& t) {
   p.proj_per_real = t.per_real;
 }
 
+struct OtfGroup {
+  int ns = 0, max_npix = 0, foot_floats = 0;
+  std::vector<int> ids;
+  TaskTable tasks{};
+  int64_t n_tasks = 0;
+  // LDS bytes per wave of this group's lag-domain waves in a launch without FFT-path blocks
+  int lds_split = 0, lds_fused = 0, lds_foot = 0, lds_adj = 0;
+};
+
 struct wfs_plan_s {
   int device = 0;
   int32_t n_layers = 0, n_sensors = 0, batch = 0;
@@ -121,8 +131,12 @@ struct wfs_plan_s {
   char* d_blob = nullptr;
   int64_t* d_step = nullptr;
   FwdParams base{};  // table pointers, sizes and schedule; per-call fields filled at launch
-  int otf_ns = 0;    // lag-domain template instance (0: no lag-domain sensor)
+  int otf_ns = 0;    // lag-domain template instance of group 0 (0: no lag-domain sensor)
   int otf_max_npix = 0;
+  // lag-domain sensors grouped by subaperture size, one spot launch per group: group 0's
+  // launch also carries the FFT-path and pipelined projection blocks (its task table and LDS
+  // sizes are the ones in `base` and below)
+  std::vector<OtfGroup> groups;
   int64_t otf_tasks = 0, fft_tasks = 0;
   int adj_lds_per_wave = 0;
   std::vector<int32_t> gather_blk;  // adjoint gather: first tile of each layer (+ total)
@@ -307,7 +321,7 @@ static void fill_tasks(TaskTable& tt, const std::vector<int>& ids, const std::ve
 }
 
 static void default_schedule(wfs_plan_s* P) {
-  const int64_t tasks = P->otf_tasks;
+  const int64_t tasks = P->groups.empty() ? 0 : P->groups[0].n_tasks;
   const int64_t waves = tasks;
   P->base.otf_blocks = (int32_t)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   P->base.xcd_remap = (P->flags & WFS_FLAG_NO_XCD_REMAP) ? 0 : 1;
@@ -364,7 +378,6 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<FootCol> foot_cols;
   std::vector<FootAxis> foot_axis((size_t)n_sensors * n_layers * 2);
   bool foot_ok = true;
-  int foot_max_floats = 0;
   int32_t slope_off = 0, aux_off = 0;
   int64_t phase_off = 0, pupil_off = 0;
   int otf_ns = 0;
@@ -442,15 +455,17 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
                   S.n_sub, S.n_fft, S.bin, d.elong);
     }
     if (path == kPathOtf) {
-      if (otf_ns && otf_ns != S.n_sub) {
-        delete P;
-        return fail(WFS_EUNSUPPORTED,
-                    "sensor %d: lag-domain sensors of one plan must share n_sub (%d vs %d)", s,
-                    S.n_sub, otf_ns);
-      }
-      otf_ns = S.n_sub;
+      if (!otf_ns) otf_ns = S.n_sub;
       otf_ids.push_back(s);
-      P->otf_max_npix = std::max(P->otf_max_npix, d.n_pix);
+      size_t gi = 0;
+      while (gi < P->groups.size() && P->groups[gi].ns != S.n_sub) ++gi;
+      if (gi == P->groups.size()) {
+        P->groups.emplace_back();
+        P->groups.back().ns = S.n_sub;
+      }
+      P->groups[gi].ids.push_back(s);
+      P->groups[gi].max_npix = std::max(P->groups[gi].max_npix, d.n_pix);
+      if (gi == 0) P->otf_max_npix = P->groups[0].max_npix;
     } else {
       fft_ids.push_back(s);
     }
@@ -553,7 +568,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
         d.foot_cols_off = (int32_t)foot_cols.size() - cols;
         d.foot_ncols = cols;
         d.foot_floats = floats;
-        foot_max_floats = std::max(foot_max_floats, floats);
+        for (OtfGroup& G : P->groups)
+          if (G.ns == S.n_sub) G.foot_floats = std::max(G.foot_floats, floats);
       } else {
         foot_ok = false;
       }
@@ -761,7 +777,14 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.batch = batch;
   b.n_slopes = P->n_slopes;
   b.n_valid_total = P->n_valid_total;
-  fill_tasks(b.otf, otf_ids, P->n_valid);
+  P->otf_tasks = 0;
+  for (OtfGroup& G : P->groups) {
+    fill_tasks(G.tasks, G.ids, P->n_valid);
+    G.n_tasks = (int64_t)G.tasks.per_real * batch;
+    P->otf_tasks += G.n_tasks;
+  }
+  if (P->groups.empty()) fill_tasks(b.otf, otf_ids, P->n_valid);
+  else b.otf = P->groups[0].tasks;
   {  // FFT path: one task (wave) per spectrum chunk, Q^2 per subaperture
     std::vector<int32_t> units(P->n_valid);
     for (int s : fft_ids) {
@@ -794,7 +817,6 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     P->gather_blk.push_back((int32_t)acc);
     P->gather_tab_blk.push_back((int32_t)acc_tab);
   }
-  P->otf_tasks = (int64_t)b.otf.per_real * batch;
   P->fft_tasks = (int64_t)b.fft.per_real * batch;
   if (P->otf_tasks > (1LL << 31) - 1 || P->fft_tasks > (1LL << 31) - 1) {
     (void)hipFree(P->d_blob);
@@ -821,16 +843,32 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   P->lds_fused = lds_wave;
   P->lds_split = wave_lds(false, true);
-  P->lds_foot = otf_ns ? std::max(16, (otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, false,
-                                                     foot_max_floats) + 15) & ~15)
-                       : 0;
-  P->foot_ok = otf_ns && foot_ok && P->lds_foot * kWavesPerBlock <= 65536;
+  // every group's LDS per wave, in launches without FFT-path blocks (group 0's launch with
+  // them takes the larger figures above)
+  bool adj_ok = true;
+  for (OtfGroup& G : P->groups) {
+    auto r16 = [](int x) { return std::max(16, (x + 15) & ~15); };
+    G.lds_split = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, 0));
+    G.lds_fused = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, true, 0));
+    G.lds_foot = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, G.foot_floats));
+    G.lds_adj = r16(adj_lds_bytes(G.ns, n_layers, G.max_npix));
+    if (G.lds_fused * kWavesPerBlock > 65536) {
+      (void)hipFree(P->d_blob);
+      delete P;
+      return fail(WFS_EUNSUPPORTED, "wfs_plan: %d bytes of LDS per workgroup exceed 64 KiB",
+                  G.lds_fused * kWavesPerBlock);
+    }
+    foot_ok = foot_ok && G.lds_foot * kWavesPerBlock <= 65536;
+    adj_ok = adj_ok && G.lds_adj * kWavesPerBlock <= 65536;
+  }
+  P->lds_foot = otf_ns ? P->groups[0].lds_foot : 0;
+  P->foot_ok = otf_ns && foot_ok;
   P->lds_fused_otf = wave_lds(true, false);
   P->lds_split_otf = wave_lds(false, false);
   b.lds_per_wave = P->lds_split;
   b.lds_per_wave_otf = P->lds_split_otf;
-  P->adj_lds_per_wave = otf_ns ? ((adj_lds_bytes(otf_ns, n_layers, P->otf_max_npix) + 15) & ~15) : 16;
-  if (P->adj_lds_per_wave * kWavesPerBlock > 65536) P->adj_lds_per_wave = 0;  // adjoint unsupported
+  P->adj_lds_per_wave = otf_ns ? P->groups[0].lds_adj : 16;
+  if (!adj_ok) P->adj_lds_per_wave = 0;  // adjoint unsupported
   // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
   b.fft_blocks = (int32_t)((P->fft_tasks + kWavesPerBlock - 1) / kWavesPerBlock);
   default_schedule(P);
@@ -1032,6 +1070,28 @@ static FwdParams call_params(wfs_plan_t P, const float* layers, int64_t step, ui
   return p;
 }
 
+// The spot launch of every lag-domain group (subaperture size) for `p`, which is set up for
+// group 0 (its tasks and LDS per wave, the FFT-path and projection blocks); the other groups
+// follow on `st` with their own tasks and LDS and neither FFT-path nor projection blocks.
+static hipError_t launch_groups(wfs_plan_t P, const FwdParams& p, hipStream_t st,
+                                const SideStream* side) {
+  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, side);
+  for (size_t g = 1; g < P->groups.size() && e == hipSuccess; ++g) {
+    const OtfGroup& G = P->groups[g];
+    FwdParams q = p;
+    q.otf = G.tasks;
+    q.otf_blocks = (int32_t)((G.n_tasks + kWavesPerBlock - 1) / kWavesPerBlock);
+    q.fft_blocks = 0;
+    q.proj_blocks = 0;
+    q.lds_per_wave = p.otf_from_phase == 2   ? G.lds_foot
+                     : p.otf_from_phase == 1 ? G.lds_split
+                                             : G.lds_fused;
+    q.lds_per_wave_otf = q.lds_per_wave;
+    e = launch_forward(q, G.ns, st, nullptr);
+  }
+  return e;
+}
+
 // fused: one launch; split: projection into the plan's phase buffer, then the spot launch
 static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
   if (P->foot) {  // staged footprint: the spot launch alone (no FFT-path sensor here)
@@ -1039,7 +1099,7 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
     p.n_frames = 1;
     p.lds_per_wave = P->lds_foot;
     p.lds_per_wave_otf = P->lds_foot;
-    return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
+    return launch_groups(P, p, st, &P->side);
   }
   const bool split = P->split && P->d_phase;
   if (split || P->fft_tasks > 0) {  // FFT-path sensors always read the projected phase
@@ -1051,7 +1111,7 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
   p.otf_from_phase = split ? 1 : 0;
   p.lds_per_wave = split ? P->lds_split : P->lds_fused;
   p.lds_per_wave_otf = split ? P->lds_split_otf : P->lds_fused_otf;
-  return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
+  return launch_groups(P, p, st, &P->side);
 }
 
 int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, float* slopes,
@@ -1091,7 +1151,7 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
     p.n_frames = n;
     p.lds_per_wave = P->lds_foot;
     p.lds_per_wave_otf = P->lds_foot;
-    if (p.fft_blocks == 0) return launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
+    if (p.fft_blocks == 0) return launch_groups(P, p, st, &P->side);
     // FFT-path sensors read the projected phase: frame by frame on the side stream (their
     // projection into the plan's phase buffer, then their launch), concurrently with the one
     // footprint launch of every lag-domain frame on st
@@ -1114,7 +1174,7 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
     }
     if (e == hipSuccess) {
       p.fft_blocks = 0;
-      e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, nullptr);
+      e = launch_groups(P, p, st, nullptr);
     }
     if (e == hipSuccess && fs != st) {
       e = hipEventRecord(P->side.join, fs);
@@ -1141,7 +1201,7 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
       p.proj_blocks = P->proj_all.per_real * P->batch;
       p.phase_out = buf[(k + 1) & 1];
     }
-    e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, st, &P->side);
+    e = launch_groups(P, p, st, &P->side);
   }
   return e;
 }
@@ -1174,7 +1234,7 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
   FwdParams p = call_params(P, nullptr, step, seed, slopes, aux);
   p.phase_in = phase;
   p.otf_from_phase = 1;
-  hipError_t e = launch_forward(p, P->otf_ns ? P->otf_ns : 2, (hipStream_t)stream, &P->side);
+  hipError_t e = launch_groups(P, p, (hipStream_t)stream, &P->side);
   if (e != hipSuccess) return hip_fail(e, "wfs_spots: launch");
   return WFS_OK;
 }
@@ -1400,7 +1460,13 @@ int wfs_adjoint(wfs_plan_t P, const float* layers, const float* grad_slopes,
   }
   a.fft_adj_part = P->d_fft_adj;
   a.fft_adj_per_real = P->fft_adj_per_real;
-  e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, P->adj_clear_grad, (hipStream_t)stream);
+  e = launch_adjoint(a, P->otf_ns ? P->otf_ns : 2, P->adj_clear_grad, true, (hipStream_t)stream);
+  for (size_t g = 1; g < P->groups.size() && e == hipSuccess; ++g) {
+    AdjParams ag = a;  // the other subaperture sizes add their sensors' shares
+    ag.f.otf = P->groups[g].tasks;
+    ag.f.lds_per_wave = P->groups[g].lds_adj;
+    e = launch_adjoint(ag, P->groups[g].ns, false, false, (hipStream_t)stream);
+  }
   if (e != hipSuccess) return hip_fail(e, "wfs_adjoint: launch");
   if (fft) {
     e = launch_adjoint_fft(a, P->fft_adj_lds, (hipStream_t)stream);

@@ -61,6 +61,29 @@ def mixed_case(batch=2):
     return cfg
 
 
+def uneven_case(fft=True, batch=3):
+    """Lag-domain sensors of three subaperture sizes in one plan (an on-axis LGS of 9 x 9
+    subapertures of 6 pixels, an off-axis LGS of 6 x 6 of 9 pixels, an 11 x 11 NGS of 4 pixels)
+    over the same 13.5 m pupil, and optionally an FFT-path NGS (n_sub = 14); noise on."""
+    cfg = lgs_case(9, 6, 12, 2, layers=2, n=128, pitch=0.25, noise=True, batch=batch)
+    D = cfg["sensors"][0]["pupil_d_m"]
+    obs = cfg["sensors"][0]["obs_d_m"]
+    cfg["sensors"].append(synth.configs._lgs(theta_x=20 * ARCSEC, theta_y=-15 * ARCSEC, n_sa=6,
+                                             n_sub=9, n_fft=18, bin_=2, photons=800.0,
+                                             read_noise=2.0, pupil_d=D, obs_d=obs))
+    cfg["sensors"].append(synth.configs._ngs(theta_x=-10 * ARCSEC, theta_y=25 * ARCSEC, n_sa=11,
+                                             n_sub=4, n_fft=8, bin_=2, lam=0.8e-6,
+                                             photons=600.0, read_noise=1.5, pupil_d=D,
+                                             obs_d=obs))
+    if fft:
+        cfg["sensors"].append(synth.configs._ngs(theta_x=5 * ARCSEC, theta_y=5 * ARCSEC, n_sa=2,
+                                                 n_sub=14, n_fft=32, bin_=4, lam=1.65e-6,
+                                                 photons=4000.0, read_noise=3.0, pupil_d=D,
+                                                 obs_d=obs))
+    cfg["name"] = "uneven_subapertures" + ("_fft" if fft else "")
+    return cfg
+
+
 CASES = {
     "cfg0": lambda: synth.config0(),
     "lgs_n4_N8_b2": lambda: lgs_case(6, 4, 8, 2),
@@ -77,6 +100,8 @@ CASES = {
                                             lam=1.65e-6, photons=5000.0, ro=3.0),
     "fft_ngs_n40_N128_b4": lambda: ngs_case(2, 40, 128, 4, D=16.0, obs=3.0, layers=2, n=128),
     "mixed_lgs_ngs_batch2": mixed_case,
+    "uneven_lgs_ngs": lambda: uneven_case(fft=False),
+    "uneven_lgs_ngs_fft": lambda: uneven_case(fft=True),
 }
 
 
