@@ -18,6 +18,25 @@ __global__ __launch_bounds__(kBlock) void wfs_project_kernel(FwdParams p, float*
   project_block(p, blk, phase, (double)current_step(p), smem);
 }
 
+// Stencil entries of the staged footprint for the frames of one launch: block per (frame,
+// sensor, layer, axis), thread per pupil index; frame f is at step current_step + f.
+__global__ __launch_bounds__(kBlock) void wfs_foot_entries_kernel(FwdParams p, FootEnt* out) {
+  const int per_frame = p.n_sensors * p.n_layers * 2;
+  const int f = blockIdx.x / per_frame;
+  const int r = blockIdx.x - f * per_frame;  // (sensor * n_layers + layer) * 2 + axis
+  const DevSensor S = cload(p.sen, r / (2 * p.n_layers));
+  if (S.foot_ncols == 0) return;  // no staged footprint (FFT-path sensor)
+  const FootAxis X = p.foot_axis[r];
+  const double stepd = (double)(current_step(p) + f);
+  FootEnt* e = out + (int64_t)f * p.foot_ent_per_frame + X.ent_off;
+  for (int i = threadIdx.x; i < S.n_pup; i += kBlock) {
+    const double c = fma(X.a, (double)i, X.b0) + stepd * X.db;
+    int i0;
+    const float2 w = foot_axis_tap(c, X.n, X.inv_n, X.boundary, &i0);
+    e[i] = FootEnt{i0, w.x, w.y};
+  }
+}
+
 __global__ void wfs_step_kernel(int64_t* step_dev, int64_t value, int32_t add) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *step_dev = add ? *step_dev + value : value;
 }
@@ -94,6 +113,16 @@ hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t
   const int64_t blocks = (int64_t)p.proj_per_real * p.batch;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(wfs_project_kernel, dim3((unsigned)blocks), dim3(kBlock), lds, st, p, phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_foot_entries(const FwdParams& p, FootEnt* out, int n_frames,
+                               hipStream_t st) {
+  const int64_t blocks = (int64_t)n_frames * p.n_sensors * p.n_layers * 2;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wfs_foot_entries_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, p,
+                     out);
   return hipGetLastError();
 }
 

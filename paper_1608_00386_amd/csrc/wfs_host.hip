@@ -18,6 +18,7 @@
 
 namespace wfs {
 hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const SideStream* side);
+hipError_t launch_foot_entries(const FwdParams& p, FootEnt* out, int n_frames, hipStream_t st);
 hipError_t launch_project(const FwdParams& p, float* phase, int lds, hipStream_t st);
 int project_lds_bytes(int n_layers, int rows);
 int project_max_groups();
@@ -164,6 +165,8 @@ struct wfs_plan_s {
   // split or the footprint one: all three give the same bits)
   int frames = 0;
   int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
+  FootEnt* d_foot_ent = nullptr;  // stencil entries of up to foot_ent_cap frames
+  int foot_ent_cap = 0;           // frames per footprint launch (longer runs take several)
   SideStream side{};         // FFT-path blocks run here concurrently (plans with both paths)
   float* d_fft_adj = nullptr;    // FFT-path adjoint: per-chunk phase-gradient shares and the
   float* d_adj_fwd = nullptr;    // noise-free forward outputs it needs ([B][n_slopes + n_valid])
@@ -378,6 +381,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   std::vector<FootCol> foot_cols;
   std::vector<FootAxis> foot_axis((size_t)n_sensors * n_layers * 2);
   bool foot_ok = true;
+  int64_t foot_ent = 0;  // stencil entries of one frame (every footprint sensor, layer, axis)
   int32_t slope_off = 0, aux_off = 0;
   int64_t phase_off = 0, pupil_off = 0;
   int otf_ns = 0;
@@ -559,8 +563,10 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
         FootAxis& X = foot_axis[((size_t)s * n_layers + l) * 2];
         FootAxis& Y = foot_axis[((size_t)s * n_layers + l) * 2 + 1];
         X = FootAxis{A.ax, A.bx0, A.dbx, 1.0 / L.nx, L.nx, L.boundary, pitch, floats, 1.0f,
-                     {0, 0, 0}};
-        Y = FootAxis{A.ay, A.by0, A.dby, 1.0 / L.ny, L.ny, L.boundary, 1, 0, L.weight, {0, 0, 0}};
+                     (int32_t)foot_ent, {0, 0}};
+        Y = FootAxis{A.ay, A.by0, A.dby, 1.0 / L.ny, L.ny, L.boundary, 1, 0, L.weight,
+                     (int32_t)(foot_ent + g.n_pup), {0, 0}};
+        foot_ent += 2LL * g.n_pup;
         cols += fw;
         floats += fw * pitch;
       }
@@ -862,7 +868,19 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     adj_ok = adj_ok && G.lds_adj * kWavesPerBlock <= 65536;
   }
   P->lds_foot = otf_ns ? P->groups[0].lds_foot : 0;
-  P->foot_ok = otf_ns && foot_ok;
+  P->foot_ok = otf_ns && foot_ok && foot_ent > 0 && foot_ent < (1LL << 31) / 64;
+  if (P->foot_ok) {  // the stencil-entry table: 32 MiB at most, 1 to 64 frames
+    const int64_t per = foot_ent * (int64_t)sizeof(FootEnt);
+    P->foot_ent_cap = (int)std::max<int64_t>(1, std::min<int64_t>(64, (32LL << 20) / per));
+    e = hipMalloc((void**)&P->d_foot_ent, (size_t)(per * P->foot_ent_cap));
+    if (e != hipSuccess) {
+      (void)hipFree(P->d_blob);
+      delete P;
+      return hip_fail(e, "wfs_plan: footprint stencil entries");
+    }
+    b.foot_ent = P->d_foot_ent;
+    b.foot_ent_per_frame = (int32_t)foot_ent;
+  }
   P->lds_fused_otf = wave_lds(true, false);
   P->lds_split_otf = wave_lds(false, false);
   b.lds_per_wave = P->lds_split;
@@ -913,6 +931,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       if (P->d_fft_part) (void)hipFree(P->d_fft_part);
+  if (P->d_foot_ent) (void)hipFree(P->d_foot_ent);
       if (P->d_fft_cnt) (void)hipFree(P->d_fft_cnt);
       (void)hipFree(P->d_blob);
       if (P->d_phase) (void)hipFree(P->d_phase);
@@ -1099,6 +1118,8 @@ static hipError_t launch_fwd_modes(wfs_plan_t P, FwdParams p, hipStream_t st) {
     p.n_frames = 1;
     p.lds_per_wave = P->lds_foot;
     p.lds_per_wave_otf = P->lds_foot;
+    hipError_t e = launch_foot_entries(p, P->d_foot_ent, 1, st);
+    if (e != hipSuccess) return e;
     return launch_groups(P, p, st, &P->side);
   }
   const bool split = P->split && P->d_phase;
@@ -1145,13 +1166,24 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
     return p;
   };
   hipError_t e = hipSuccess;
+  // footprint launches of every lag-domain frame, as many frames a launch as the stencil-entry
+  // table holds, each after the launch that fills the table
+  auto foot_frames = [&]() {
+    hipError_t ef = hipSuccess;
+    for (int c0 = 0; c0 < n && ef == hipSuccess; c0 += P->foot_ent_cap) {
+      FwdParams q = frame(c0);
+      q.otf_from_phase = 2;
+      q.n_frames = std::min(P->foot_ent_cap, n - c0);
+      q.lds_per_wave = P->lds_foot;
+      q.lds_per_wave_otf = P->lds_foot;
+      q.fft_blocks = 0;
+      ef = launch_foot_entries(q, P->d_foot_ent, q.n_frames, st);
+      if (ef == hipSuccess) ef = launch_groups(P, q, st, nullptr);
+    }
+    return ef;
+  };
   if (frames == 2) {
-    FwdParams p = frame(0);
-    p.otf_from_phase = 2;
-    p.n_frames = n;
-    p.lds_per_wave = P->lds_foot;
-    p.lds_per_wave_otf = P->lds_foot;
-    if (p.fft_blocks == 0) return launch_groups(P, p, st, &P->side);
+    if (P->base.fft_blocks == 0) return foot_frames();
     // FFT-path sensors read the projected phase: frame by frame on the side stream (their
     // projection into the plan's phase buffer, then their launch), concurrently with the one
     // footprint launch of every lag-domain frame on st
@@ -1172,10 +1204,7 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
       a.lds_per_wave = P->lds_split;
       e = launch_forward(a, P->otf_ns ? P->otf_ns : 2, fs, nullptr);
     }
-    if (e == hipSuccess) {
-      p.fft_blocks = 0;
-      e = launch_groups(P, p, st, nullptr);
-    }
+    if (e == hipSuccess) e = foot_frames();
     if (e == hipSuccess && fs != st) {
       e = hipEventRecord(P->side.join, fs);
       if (e == hipSuccess) e = hipStreamWaitEvent(st, P->side.join, 0);

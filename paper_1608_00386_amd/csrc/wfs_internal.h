@@ -72,11 +72,21 @@ constexpr int kFootMaxCols = 2 * kWave;  // columns summed over layers: two per 
 // One axis of one (sensor, layer) for the staged footprint: coordinate c = a i + b0 + k db of
 // pupil index i at step k on a grid of n points (1/n, boundary), and how a stencil entry is
 // stored: weights times `weight`, window index koff + kmul * (tap - window origin).
+// ent_off: first entry of this axis (one per pupil index) in a frame's stencil-entry table.
 struct FootAxis {
   double a, b0, db, inv_n;
   int32_t n, boundary, kmul, koff;
   float weight;
-  int32_t pad[3];
+  int32_t ent_off;
+  int32_t pad[2];
+};
+
+// Bilinear stencil of one pupil index along one axis at one step: the first tap's grid index
+// (wrapped into [0, n) on a periodic grid, the floor of the clamped coordinate on a
+// zero-boundary one) and the two weights (0 for taps off a zero-boundary grid).
+struct FootEnt {
+  int32_t i0;
+  float w0, w1;
 };
 
 // One window column of one sensor's footprint: where it is read and where it goes.
@@ -167,6 +177,9 @@ struct FwdParams {
   const FootAxis* foot_axis;   // [n_sensors][n_layers][2] (x, y)
   const FootCol* foot_cols;    // per sensor: its window columns, layer by layer
   int32_t n_frames;
+  // stencil entries of every frame of a footprint launch, [frame][entries of one frame]
+  const FootEnt* foot_ent;
+  int32_t foot_ent_per_frame;
 };
 
 // A plan-owned second stream with fork/join events: a launch that holds FFT-path blocks runs

@@ -188,25 +188,12 @@ constexpr int kFieldGather = 0;  // bilinear stencils straight from the layers, 
 constexpr int kFieldPhase = 1;   // the projection kernel's phase buffer p.phase_in
 constexpr int kFieldFoot = 2;    // the subaperture's layer footprint, staged in LDS
 
-// Footprint origin along one axis: the grid index of the smallest coordinate c the
-// subaperture's stencils touch, wrapped into [0, n) on a periodic grid (same arithmetic as
-// make_tap, so both agree on every index), the unclamped floor of the clamped coordinate on a
-// zero-boundary grid.
-__device__ __forceinline__ int foot_origin(double c, int32_t n, double inv_n, int32_t boundary) {
-  if (boundary == 0) {
-    const double cw = c - (double)n * floor(c * inv_n);
-    int i0 = (int32_t)floor(cw);
-    if (i0 >= n) i0 -= n;
-    if (i0 < 0) i0 += n;
-    return i0;
-  }
-  return (int32_t)floor(fmin(fmax(c, -4.0), (double)n + 4.0));
-}
-
-// One axis of a bilinear stencil against a staged footprint: the weights of make_tap (same
-// arithmetic, bit for bit) and the first tap's index relative to the footprint origin o.
-__device__ __forceinline__ float2 foot_tap(double c, int32_t n, double inv_n, int32_t boundary,
-                                           int o, int* rel) {
+// One axis of a bilinear stencil for the staged footprint: the weights of make_tap (same
+// arithmetic, bit for bit) and the first tap's grid index, wrapped into [0, n) on a periodic
+// grid, the floor of the clamped coordinate on a zero-boundary grid.  The window of a
+// subaperture starts at the index of its pupil pixel with the smaller coordinate.
+__device__ __forceinline__ float2 foot_axis_tap(double c, int32_t n, double inv_n,
+                                                int32_t boundary, int* i0_out) {
   if (boundary == 0) {
     const double cw = c - (double)n * floor(c * inv_n);
     const double f0 = floor(cw);
@@ -214,9 +201,7 @@ __device__ __forceinline__ float2 foot_tap(double c, int32_t n, double inv_n, in
     const float f = (float)(cw - f0);
     if (i0 >= n) i0 -= n;
     if (i0 < 0) i0 += n;
-    int r = i0 - o;
-    if (r < 0) r += n;
-    *rel = r;
+    *i0_out = i0;
     return make_float2(1.0f - f, f);
   }
   const double cc = fmin(fmax(c, -4.0), (double)n + 4.0);
@@ -225,7 +210,7 @@ __device__ __forceinline__ float2 foot_tap(double c, int32_t n, double inv_n, in
   const float f = (float)(cc - f0);
   const bool ok0 = i0 >= 0 && i0 < n;
   const bool ok1 = i0 + 1 >= 0 && i0 + 1 < n;
-  *rel = i0 - o;
+  *i0_out = i0;
   return make_float2(ok0 ? 1.0f - f : 0.0f, ok1 ? f : 0.0f);
 }
 
@@ -239,7 +224,8 @@ struct FootTap {
 // Phase of the lane's pixels from a footprint staged in LDS (Sec. 2.2, inside the spot wave):
 //   1. the origin of each layer window along each axis (the window holds the layer pixels the
 //      subaperture's stencils can touch; bounds fixed per sensor and layer), then every
-//      stencil entry (lane per layer, axis and pupil index; FP64 coordinates);
+//      stencil entry (lane per layer, axis and pupil index), both from the launch's table of
+//      stencil entries (FP64 coordinates, computed once per frame for every pupil index);
 //   2. each lane loads up to two window columns (all rows; the column descriptors are read
 //      at the start), then the window goes to LDS over the origins table;
 //   3. each pixel sums its stencils from LDS, layer by layer.
@@ -248,7 +234,7 @@ struct FootTap {
 // for bit.
 template <int NS>
 __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& S,
-                                           const DevSubap& sb, int sid, int b, double stepd,
+                                           const DevSubap& sb, int sid, int b, int frame,
                                            char* wsm, const OtfLds& lo, float* ph) {
   constexpr int NPIX = NS * NS;
   constexpr int PPL = (NPIX + kWave - 1) / kWave;
@@ -268,15 +254,14 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
     fc[k] = pc < S.foot_ncols ? p.foot_cols[S.foot_cols_off + pc]
                               : FootCol{0, 1, 1, 0, 0, 0, 0, 0};
   }
-  // 1. window origins, lane per (layer, axis); then the stencil entries, lane per (layer,
-  //    axis, pupil index)
+  // 1. window origins, lane per (layer, axis): the first tap of the pupil index with the
+  //    smaller coordinate; then the stencil entries, lane per (layer, axis, pupil index),
+  //    from the launch's entry table of this frame
+  const FootEnt* ent = p.foot_ent + (int64_t)frame * p.foot_ent_per_frame;
   for (int e = lane; e < 2 * nl; e += kWave) {
     const FootAxis X = p.foot_axis[fbase * 2 + e];
     const int i0 = (e & 1) ? sb.a * NS : sb.b * NS;
-    const double sh = stepd * X.db;
-    const double cf = fma(X.a, (double)i0, X.b0) + sh;
-    const double cl = fma(X.a, (double)(i0 + NS - 1), X.b0) + sh;
-    forg[e] = foot_origin(fmin(cf, cl), X.n, X.inv_n, X.boundary);
+    forg[e] = ent[X.ent_off + (X.a >= 0.0 ? i0 : i0 + NS - 1)].i0;
   }
   wave_sync();
   {
@@ -287,12 +272,12 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
       const int l = l0 + lp;
       if (lp < LPP && l < nl) {
         const FootAxis X = p.foot_axis[(fbase + l) * 2 + axis];
-        const double c = fma(X.a, (double)idx, X.b0) + stepd * X.db;
-        int rel;
-        const float2 w = foot_tap(c, X.n, X.inv_n, X.boundary, forg[2 * l + axis], &rel);
+        const FootEnt E = ent[X.ent_off + idx];
+        int rel = E.i0 - forg[2 * l + axis];
+        if (X.boundary == 0 && rel < 0) rel += X.n;
         FootTap t;
-        t.w0 = w.x * X.weight;  // rows: the projection kernel's ry.w0 * wl
-        t.w1 = w.y * X.weight;
+        t.w0 = E.w0 * X.weight;  // rows: the projection kernel's ry.w0 * wl
+        t.w1 = E.w1 * X.weight;
         t.k = (X.koff + rel * X.kmul) * 4;  // byte offset in the window
         tab[l * TPL + j] = t;
       }
@@ -404,7 +389,7 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
 template <int NS, int FIELD>
 __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S,
                                           const DevSubap& sb, int sid, int b, double stepd,
-                                          char* wsm, const OtfLds& lo) {
+                                          char* wsm, const OtfLds& lo, int frame = 0) {
   constexpr int NPIX = NS * NS;
   constexpr int PPL = (NPIX + kWave - 1) / kWave;  // pixels per lane
   const int lane = lane_id();
@@ -420,7 +405,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
   }
   if constexpr (FIELD == kFieldFoot) {
     float ph[PPL];
-    foot_phase<NS>(p, S, sb, sid, b, stepd, wsm, lo, ph);
+    foot_phase<NS>(p, S, sb, sid, b, frame, wsm, lo, ph);
     wave_sync();  // E overlays the stencil entries the last stencil pass read
     float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
 #pragma unroll
@@ -875,8 +860,8 @@ __device__ __forceinline__ void write_slopes(const FwdParams& p, const DevSensor
 template <int NS, int FIELD>
 __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
                                          const DevSubap& sb, int sid, int b, int64_t step,
-                                         char* wsm, const OtfLds& lo) {
-  otf_field<NS, FIELD>(p, S, sb, sid, b, (double)step, wsm, lo);
+                                         char* wsm, const OtfLds& lo, int frame = 0) {
+  otf_field<NS, FIELD>(p, S, sb, sid, b, (double)step, wsm, lo, frame);
   const NaEntry el = na_entry(p, step);
 #pragma unroll
   for (int rd = 0; rd < Otf<NS>::kRounds; ++rd)
@@ -894,7 +879,7 @@ __device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm, in
   const DevSubap sb = cload(p.sub, S.valid_off + v);
   const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix, false,
                                    FIELD == kFieldFoot ? S.foot_floats : 0);
-  otf_spot<NS, FIELD>(p, S, sb, sid, b, step, wsm, lo);
+  otf_spot<NS, FIELD>(p, S, sb, sid, b, step, wsm, lo, frame);
   const Cog c = cog_sums(p, S, sid, b, v, step + p.noise_dstep,
                          reinterpret_cast<const float*>(wsm + lo.b_off));
   write_slopes(p, S, b, v, c, frame);
