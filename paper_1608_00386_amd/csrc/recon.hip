@@ -5,7 +5,8 @@
 //
 //   B == 1, or unaligned operands : split-K streaming GEMV on the vector ALUs
 //   2 <= B <= 8, 16-byte aligned   : the same streaming order with every realisation at once
-//   (N % 4 == 0)                     (vector ALUs; R read once in 1 KB bursts per row)
+//   (N % 4 == 0)                     (vector ALUs; R read once in 1 KB bursts per row, the
+//                                    slopes staged in LDS per workgroup)
 //   B > 8, aligned                 : split-K GEMM on the FP32 matrix cores
 //                                    (v_mfma_f32_16x16x4f32, one 16-row x 16-realisation tile
 //                                    per MFMA, 2 row tiles per wavefront)
@@ -25,6 +26,7 @@ namespace wfs {
 constexpr int kRB = 256;
 constexpr int kBatchRW = 8;  // rows per wave of the small-batch kernel
 constexpr int kBatchMax = 8;  // realisations of the small-batch kernel
+constexpr bool kBatchPF = true;  // small-batch kernel: next slice's rows of R in flight
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -105,48 +107,87 @@ __global__ __launch_bounds__(kRB) void recon_valu_kernel(const float* __restrict
 }
 
 // ---------------------------------------------------------------------------------------
-// Small batches (2 <= B <= 8), aligned operands: the GEMV's streaming order with every
-// realisation at once.  Wave per (RW rows, split); lane j reads the float4 at column
-// k0 + 4 j + 256 i of each of its rows (1 KB contiguous per row and instruction, as the GEMV:
-// long DRAM bursts), the matching float4 of every realisation's slopes (cached: S is small),
-// and accumulates RW x B dot products; the wave reduces them at the end.
+// Small batch (2 <= B <= 8, aligned), slopes staged in LDS: workgroup = one split (columns
+// [k0, k1)) x 4 row groups of 8 rows, one per wave.  The split's columns go by in slices of
+// 256: the workgroup stages the slice of every realisation's slopes in LDS (double-buffered,
+// the next slice's global loads in flight while this one is used; one barrier a slice), and
+// each lane streams the float4 at column k + 4 lane of its wave's 8 rows (1 KB contiguous per
+// row and instruction) and forms 8 x B dot products, reduced across the wave at the end.
+// Holding the slopes in LDS instead of registers halves the vector-memory instructions and
+// frees the registers for a second set of R loads (PF: the next slice's rows are in flight
+// while this slice is summed).
 // ---------------------------------------------------------------------------------------
-template <int RW, int BB>
-__global__ __launch_bounds__(kRB) void recon_batch_kernel(const float* __restrict__ R, int M,
-                                                          int N, const float* __restrict__ S,
-                                                          int B, int chunk, int splits,
-                                                          int row_groups,
-                                                          float* __restrict__ ws) {
-  const int wave = (blockIdx.x * kRB + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (wave >= row_groups * splits) return;
-  // consecutive waves take consecutive row groups of one split: the waves of a workgroup
-  // read the same slopes (L1 hits) and neighbouring rows of R
-  const int sp = wave / row_groups, g = wave - sp * row_groups;
-  const int row0 = g * RW;
+template <int BB, bool PF>
+__global__ __launch_bounds__(kRB) void recon_batch_lds_kernel(const float* __restrict__ R,
+                                                              int M, int N,
+                                                              const float* __restrict__ S,
+                                                              int B, int chunk, int quads,
+                                                              float* __restrict__ ws) {
+  constexpr int RW = kBatchRW;
+  __shared__ float4 slab[2][BB][64];
+  const int wg = blockIdx.x;
+  const int sp = wg / quads, q = wg - sp * quads;  // consecutive workgroups: one split
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row0 = (q * 4 + wave) * RW;
   const int k0 = sp * chunk, k1 = min(N, k0 + chunk);
+  const int ns = (k1 - k0 + 255) / 256;
   const float* rrow[RW];
 #pragma unroll
   for (int r = 0; r < RW; ++r) rrow[r] = R + (int64_t)min(row0 + r, M - 1) * N;
+  // slope slice loads: thread t stages float4 j = t & 63 of realisations t / 64 and 4 + t / 64
+  auto load_s = [&](int s, float4 (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = (threadIdx.x >> 6) + 4 * h, k = k0 + 256 * s + 4 * (threadIdx.x & 63);
+      v[h] = (b < B && b < BB && k < k1)
+                 ? *reinterpret_cast<const float4*>(S + (int64_t)b * N + k)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store_s = [&](int buf, const float4 (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = (threadIdx.x >> 6) + 4 * h;
+      if (b < BB) slab[buf][b][threadIdx.x & 63] = v[h];
+    }
+  };
+  auto load_r = [&](int s, float4 (&v)[RW]) {
+    const int k = k0 + 256 * s + 4 * lane;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) v[r] = k < k1 ? ldnt4(rrow[r] + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
   float acc[RW][BB];
 #pragma unroll
   for (int r = 0; r < RW; ++r)
 #pragma unroll
     for (int b = 0; b < BB; ++b) acc[r][b] = 0.0f;
-  for (int k = k0 + 4 * lane; k < k1; k += 4 * 64) {
-    float4 rv[RW], sv[BB];
+  float4 sv[2], rv[RW], rn[RW];
+  load_s(0, sv);
+  if constexpr (PF) load_r(0, rv);
+  store_s(0, sv);
+  __syncthreads();
+  for (int s = 0; s < ns; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < ns) load_s(s + 1, sv);
+    if constexpr (PF) {
+      if (s + 1 < ns) load_r(s + 1, rn);
+    } else {
+      load_r(s, rv);
+    }
 #pragma unroll
-    for (int r = 0; r < RW; ++r) rv[r] = ldnt4(rrow[r] + k);
+    for (int b = 0; b < BB; ++b) {
+      const float4 x = slab[cur][b][lane];
 #pragma unroll
-    for (int b = 0; b < BB; ++b)
-      sv[b] = b < B ? *reinterpret_cast<const float4*>(S + (int64_t)b * N + k)
-                    : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int r = 0; r < RW; ++r)
+        acc[r][b] = fmaf(rv[r].x, x.x, fmaf(rv[r].y, x.y,
+                    fmaf(rv[r].z, x.z, fmaf(rv[r].w, x.w, acc[r][b]))));
+    }
+    if (s + 1 < ns) store_s(cur ^ 1, sv);
+    __syncthreads();
+    if constexpr (PF) {
 #pragma unroll
-    for (int r = 0; r < RW; ++r)
-#pragma unroll
-      for (int b = 0; b < BB; ++b)
-        acc[r][b] = fmaf(rv[r].x, sv[b].x, fmaf(rv[r].y, sv[b].y,
-                    fmaf(rv[r].z, sv[b].z, fmaf(rv[r].w, sv[b].w, acc[r][b]))));
+      for (int r = 0; r < RW; ++r) rv[r] = rn[r];
+    }
   }
 #pragma unroll
   for (int r = 0; r < RW; ++r)
@@ -316,7 +357,7 @@ static hipError_t resident_waves(int which, int* out) {
                     : which == 1 ? reinterpret_cast<const void*>(recon_valu_kernel<2, true>)
                     : which == 2 ? reinterpret_cast<const void*>(recon_valu_kernel<2, false>)
                                  : reinterpret_cast<const void*>(
-                                       recon_batch_kernel<kBatchRW, kBatchMax>);
+                                       recon_batch_lds_kernel<kBatchMax, kBatchPF>);
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, kRB, 0);
     if (e != hipSuccess) return e;
     g_slots[dev][which] = std::max(1, cus * std::max(1, blocks) * (kRB / 64));
@@ -386,17 +427,18 @@ hipError_t recon_launch(const float* R, int M, int N, const float* S, int B, flo
   if (max_splits < 1) return hipErrorInvalidValue;
   if (sh.batch) {
     int chunk;
-    const int splits = choose_splits(sh.row_groups, N, 256, sh.slots, max_splits, &chunk);
-    const int waves = sh.row_groups * splits;
+    const int quads = (sh.row_groups + 3) / 4;  // workgroups of 4 row groups per split
+    const int splits = choose_splits(quads * 4, N, 256, sh.slots, max_splits, &chunk);
+    const int grid = quads * splits;
     if (B <= 2)
-      hipLaunchKernelGGL((recon_batch_kernel<kBatchRW, 2>), dim3((waves + 3) / 4), dim3(kRB), 0,
-                         st, R, M, N, S, B, chunk, splits, sh.row_groups, ws);
+      hipLaunchKernelGGL((recon_batch_lds_kernel<2, kBatchPF>), dim3(grid), dim3(kRB), 0, st, R,
+                         M, N, S, B, chunk, quads, ws);
     else if (B <= 4)
-      hipLaunchKernelGGL((recon_batch_kernel<kBatchRW, 4>), dim3((waves + 3) / 4), dim3(kRB), 0,
-                         st, R, M, N, S, B, chunk, splits, sh.row_groups, ws);
+      hipLaunchKernelGGL((recon_batch_lds_kernel<4, kBatchPF>), dim3(grid), dim3(kRB), 0, st, R,
+                         M, N, S, B, chunk, quads, ws);
     else
-      hipLaunchKernelGGL((recon_batch_kernel<kBatchRW, kBatchMax>), dim3((waves + 3) / 4),
-                         dim3(kRB), 0, st, R, M, N, S, B, chunk, splits, sh.row_groups, ws);
+      hipLaunchKernelGGL((recon_batch_lds_kernel<kBatchMax, kBatchPF>), dim3(grid), dim3(kRB), 0,
+                         st, R, M, N, S, B, chunk, quads, ws);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)M * B;
