@@ -189,6 +189,12 @@ __device__ __forceinline__ float bilinear(const float* __restrict__ g, const Tap
 __device__ __forceinline__ void task_of(const TaskTable& tt, int t, int& b, int& sid, int& v) {
   b = t / tt.per_real;
   int r = t - b * tt.per_real;
+  if (tt.order) {
+    const int2 e = cload(tt.order, r);
+    sid = e.x;
+    v = e.y;
+    return;
+  }
   int k = 0;
   while (k + 1 < tt.n && r >= tt.start[k + 1]) ++k;
   sid = tt.ids[k];

@@ -691,6 +691,33 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   P->pupil_per_real = pupil_off;
   P->otf_ns = otf_ns;
 
+  // Lag-domain tasks of each group interleaved by the subaperture's relative place in the
+  // pupil (row, column, then sensor): the sensors of a realisation whose subapertures see
+  // the same layer pixels run at about the same time on one XCD, so waves that gather the
+  // layers (staged footprint, fused gather) meet those pixels in its L2.
+  std::vector<int2> task_order;
+  std::vector<size_t> order_off;
+  for (OtfGroup& G : P->groups) {
+    struct Key {
+      double row, col;
+      int s, v;
+    };
+    std::vector<Key> keys;
+    for (int s : G.ids)
+      for (int v = 0; v < P->n_valid[s]; ++v) {
+        const DevSubap& q = subs[(size_t)ds[s].valid_off + v];
+        keys.push_back(Key{(q.a + 0.5) / ds[s].n_sa, (q.b + 0.5) / ds[s].n_sa, s, v});
+      }
+    std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+      if (x.row != y.row) return x.row < y.row;
+      if (x.col != y.col) return x.col < y.col;
+      return x.s < y.s;
+    });
+    order_off.push_back(task_order.size());
+    for (const Key& k : keys) task_order.push_back(make_int2(k.s, k.v));
+  }
+  if (task_order.empty()) task_order.push_back(make_int2(0, 0));
+
   // tables -> one device blob
   std::vector<char> blob;
   const size_t o_lay = push_table(blob, dl);
@@ -743,6 +770,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   if (adj_segs.empty()) adj_segs.push_back(AdjSeg{});
   const size_t o_adjseg = push_table(blob, adj_segs);
   const size_t o_adjoff = push_table(blob, adj_tab_off);
+  const size_t o_order = push_table(blob, task_order);
   blob.resize((blob.size() + 255) & ~size_t(255));
 
   hipError_t e = hipGetDevice(&P->device);
@@ -784,8 +812,10 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.n_slopes = P->n_slopes;
   b.n_valid_total = P->n_valid_total;
   P->otf_tasks = 0;
-  for (OtfGroup& G : P->groups) {
+  for (size_t gi = 0; gi < P->groups.size(); ++gi) {
+    OtfGroup& G = P->groups[gi];
     fill_tasks(G.tasks, G.ids, P->n_valid);
+    G.tasks.order = reinterpret_cast<const int2*>(P->d_blob + o_order) + order_off[gi];
     G.n_tasks = (int64_t)G.tasks.per_real * batch;
     P->otf_tasks += G.n_tasks;
   }

@@ -114,6 +114,9 @@ struct TaskTable {
   int32_t per_real;           // tasks per realisation
   int32_t ids[kMaxSensors];
   int32_t start[kMaxSensors + 1];
+  // optional: task r of a realisation is (sensor, subaperture) order[r] (the sensors'
+  // subapertures interleaved by pupil position); null: sensor after sensor as above
+  const int2* order;
 };
 
 struct FwdParams {
