@@ -664,8 +664,10 @@ def main():
     field = r1["schedule"]["field"]
     if frames == "one_launch":
         kern_ms = r1["gpu_ms_per_frame"]
-        kern_name = ("wfs_forward_kernel<10, footprint> (K frames in one launch, each wave "
-                     "projects its subaperture from a footprint staged in LDS)")
+        kern_name = ("wfs_forward_kernel<10, footprint> (the K frames of one call in launches "
+                     "of up to 64 frames, each after the small launch that fills its frames' "
+                     "stencil entries; each wave projects its subaperture from a footprint "
+                     "staged in LDS)")
         traffic_key = "wfs_forward_kernel<10, 2, false, false>"
     elif frames == "pipelined":
         kern_ms = (r1["gpu_ms_per_frame"] * args.steps - r1["project_ms"]) / args.steps
@@ -713,7 +715,7 @@ def main():
                      "algorithmic_flop_per_frame": flops,
                      "projection_flop_per_frame": proj_flops(cfg1, r1["plan"]),
                      "projection_in_launch": in_wave_proj,
-                     "frames_per_launch": args.steps if frames == "one_launch" else 1,
+                     "frames_per_call": args.steps if frames == "one_launch" else 1,
                      "spots_only_kernel_ms": r1["spots_ms"],
                      "spots_only_frac": spot_flops / (r1["spots_ms"] * 1e-3) / PEAK_FP32_VALU,
                      "schedule": r1["schedule"]},
