@@ -25,13 +25,21 @@ struct AdjLds {
   int u_off, gz_off, gh_off, gb_off, total;
 };
 
+// Row pitch (float2) of the adjoint's lag array U: at least 2 n_sub - 1 and congruent to n_sub
+// modulo 16, so that lane q = r n_sub + c of the correlation loop, reading U at offset
+// -(pitch r + c), falls on bank pair q mod 16: every half-wave meets each pair twice, the
+// fewest a 64-bit read can (a pitch of 2 n_sub - 1 put up to four lanes on one pair).
+__host__ __device__ constexpr int adj_u_pitch(int ns) {
+  return 2 * ns - 1 + (((1 - ns) % 16) + 16) % 16;
+}
+
 __host__ __device__ inline AdjLds adj_lds_layout(int ns, int n_layers, int n_pix) {
   const OtfLds f = otf_lds_layout(ns, n_layers, n_pix);
   const int nl = 2 * ns - 1, np2 = n_pix * n_pix;
   AdjLds a;
   int o = f.total;
   a.u_off = o;
-  o += nl * nl * 8;
+  o += nl * adj_u_pitch(ns) * 8;
   a.gz_off = o;
   o += np2 * 8;
   a.gh_off = o;
@@ -122,6 +130,7 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   wave_sync();
   // U[k] = c Kel(k) s(kx) s(ky) ghat[k mod n_pix] on all (2 NS - 1)^2 lags
   constexpr int NL = 2 * NS - 1;
+  constexpr int UP = adj_u_pitch(NS);
   const NaEntry el = na_entry(p, step);
   float2* U = reinterpret_cast<float2*>(wsm + la.u_off);
   const float2* stab = reinterpret_cast<const float2*>(wsm + lo.stab_off);
@@ -139,7 +148,7 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
     const float sr = sx.x * sy.x - sx.y * sy.y, si = sx.x * sy.y + sx.y * sy.x;
     const float tr = sr * k.x - si * k.y;
     const float ti = sr * k.y + si * k.x;
-    U[t2] = make_float2(tr * g.x - ti * g.y, tr * g.y + ti * g.x);
+    U[iy * UP + ix] = make_float2(tr * g.x - ti * g.y, tr * g.y + ti * g.x);
   }
   // taps again (the forward scratch region is free now); the gather mode needs none
   const int nlay = p.n_layers;
@@ -157,16 +166,16 @@ __device__ void otf_adjoint_subap(const AdjParams& ap, int t, int64_t step, char
   float* gl = ap.grad_layers + (int64_t)b * p.layer_stride;
   for (int q = lane; q < NS * NS; q += kWave) {
     const int r = q / NS, c = q - r * NS;
-    const float2 e = E[q];
+    const float2 e = E[r * Otf<NS>::kEP + c];
     if (e.x == 0.0f && e.y == 0.0f) continue;  // dark pixel
     float2 V = make_float2(0.0f, 0.0f);
 #pragma unroll 2
     for (int r2 = 0; r2 < NS; ++r2) {
-      const float2* urow = U + (r2 - r + NS - 1) * NL + (NS - 1 - c);
+      const float2* urow = U + (r2 - r + NS - 1) * UP + (NS - 1 - c);
 #pragma unroll
       for (int c2 = 0; c2 < NS; ++c2) {
         const float2 u = urow[c2];
-        const float2 f = E[r2 * NS + c2];
+        const float2 f = E[r2 * Otf<NS>::kEP + c2];
         // u * conj(f)
         V.x = fmaf(u.x, f.x, fmaf(u.y, f.y, V.x));
         V.y = fmaf(u.y, f.x, fmaf(-u.x, f.y, V.y));

@@ -96,6 +96,8 @@ hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const Side
   return launch_forward_ns(c, ns, st);
 }
 
+int foot_pitch(int ns) { return otf_pitch(ns + 2); }
+
 int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats) {
   return otf_lds_layout(ns, n_layers, n_pix, with_taps, foot_floats).total;
 }

@@ -55,6 +55,7 @@ const char* tlse_run(const float* im, int32_t m, int32_t n_s, int64_t ld_im, flo
                      const float* w, float* R, int64_t ld_r, float* work, hipStream_t st,
                      int* info);
 int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats);
+int foot_pitch(int ns);
 int fft_wave_lds_bytes(int n_fft, int n_pix);
 bool fft_supported(int n_sub, int n_fft, int bin);
 }  // namespace wfs
@@ -554,8 +555,9 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
              L.offset + (int64_t)L.nx * L.ny <= (1LL << 30);
         if (!ok) break;
         // the window goes to LDS column by column, each column in a slot of n_sub + 2 floats
-        // (rows fh.. of a slot are never read): a column's stores take immediate offsets
-        const int pitch = S.n_sub + 2;
+        // rounded up to odd (rows fh.. of a slot are never read): a column's stores take
+        // immediate offsets, and the lanes storing neighbouring columns hit distinct banks
+        const int pitch = foot_pitch(S.n_sub);
         foot[(size_t)s * n_layers + l] = make_int4(fw, fh, floats, 0);
         for (int j = 0; j < fw; ++j)
           foot_cols.push_back(FootCol{(int32_t)L.offset, L.nx, L.ny, L.boundary, fw, fh,

@@ -25,12 +25,18 @@ namespace wfs {
 // Lag-domain path
 // ------------------------------------------------------------------------------------------
 
+__host__ __device__ constexpr int otf_pitch(int n) { return n | 1; }
+
 template <int NS>
 struct Otf {
   static constexpr int kJobs = NS * (NS + 1) / 2;  // row pairs (dy, r), dy >= 0
   static constexpr int kLags = 2 * NS - 1;         // dx = -(NS-1) .. NS-1
   static constexpr int kParts = kOtfLagParts;        // passes over the lag row
   static constexpr int kChunk = (kLags + kParts - 1) / kParts;  // lag columns per pass
+  // odd LDS pitches (float2) of the field rows and of the partial lag rows: lanes reading
+  // different rows of E, or writing their own partial row, fall on distinct bank pairs
+  static constexpr int kEP = otf_pitch(NS);
+  static constexpr int kPS = otf_pitch(kChunk);
   static constexpr int kRounds = (kJobs + kWave - 1) / kWave;
   static constexpr int kJobsPerRound = (kJobs + kRounds - 1) / kRounds;
   // one round (n_sub <= 10): partial-row slots grouped by pairs of lag rows (dy, NS - 1 - dy),
@@ -48,17 +54,18 @@ __host__ __device__ constexpr int otf_part_rows(int ns) {
 }
 
 // Per-wave LDS layout (bytes), shared with the host sizing code:
-//   E [n_sub^2] float2 | AW [n_sub][2 n_sub - 1] float2 (weighted lag sums) |
+//   E [n_sub][pitch] float2 (pitch = n_sub rounded up to odd) | AW [n_sub][2 n_sub - 1]
+//   float2 (weighted lag sums) |
 //   union( taps [n_layers][2 n_sub] Tap (fused gather and adjoint only),
 //          partial lag rows (one round, one pass over the lag row at a time:
-//          [jobs][ceil((2 n_sub - 1) / kOtfLagParts)] float2),
+//          [jobs][ceil((2 n_sub - 1) / kOtfLagParts) rounded up to odd] float2),
 //          P (later B) + Z (after the last round) ) |
 //   tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2
 // With a staged footprint (foot_floats > 0) the field stage also lays out, from offset 0
-// (E, AW and the union are free until the field is formed): stencil entries
+// (E, AW, the union and the tables are free until the field is formed): stencil entries
 // [n_layers][2 n_sub] FootTap (12 bytes) | the footprint [foot_floats] float (first holding
-// the window origins, [n_layers][2] int).  The tables, written before the footprint, sit
-// past both.
+// the window origins, [n_layers][2] int).  The tables are then copied in after the window
+// has been read.
 struct OtfLds {
   int e_off, stab_off, wtab_off, aw_off, taps_off, part_off, p_off, z_off, b_off;
   int fw_off, fp_off, total;
@@ -69,10 +76,10 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   OtfLds o;
   const int jobs = otf_part_rows(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
-  o.aw_off = ns * ns * 8;
+  o.aw_off = ns * otf_pitch(ns) * 8;
   const int u0 = (o.aw_off + ns * lags * 8 + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
-  const int part = jobs * ((lags + kOtfLagParts - 1) / kOtfLagParts) * 8;
+  const int part = jobs * otf_pitch((lags + kOtfLagParts - 1) / kOtfLagParts) * 8;
   o.taps_off = u0;
   o.part_off = u0;
   o.p_off = u0;  // the fold writes P after the last round has read its partial rows
@@ -82,13 +89,14 @@ __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix
   if (o.p_off + 1024 > end) end = o.p_off + 1024;  // matrix-core image: 16 x 16 floats
   if (u0 + part > end) end = u0 + part;
   if (with_taps && u0 + taps > end) end = u0 + taps;
+  o.stab_off = (end + 7) & ~7;
+  o.wtab_off = o.stab_off + lags * 8;
+  end = o.wtab_off + n_pix * 8;
   o.fw_off = 0;
   o.fp_off = (2 * ns * n_layers * 12 + 15) & ~15;
   const int fpb = 4 * (foot_floats > 2 * n_layers ? foot_floats : 2 * n_layers);
   if (foot_floats > 0 && o.fp_off + fpb > end) end = o.fp_off + fpb;
-  o.stab_off = (end + 7) & ~7;
-  o.wtab_off = o.stab_off + lags * 8;
-  o.total = (o.wtab_off + n_pix * 8 + 15) & ~15;
+  o.total = (end + 15) & ~15;
   return o;
 }
 
@@ -238,7 +246,8 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
                                            char* wsm, const OtfLds& lo, float* ph) {
   constexpr int NPIX = NS * NS;
   constexpr int PPL = (NPIX + kWave - 1) / kWave;
-  constexpr int ROWS = NS + 2;
+  constexpr int ROWS = NS + 2;                   // window rows loaded per column
+  constexpr int SLOT = otf_pitch(ROWS);          // LDS floats per window column
   constexpr int TPL = 2 * NS;       // stencil entries per layer: columns, then rows
   constexpr int LPP = kWave / TPL;  // layers per pass
   const int lane = lane_id();
@@ -363,7 +372,7 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
       const float* w0p =
           reinterpret_cast<const float*>(reinterpret_cast<const char*>(fp) + (ry.k + cx.k));
       const float v00 = w0p[0], v10 = w0p[1];
-      const float v01 = w0p[ROWS], v11 = w0p[ROWS + 1];
+      const float v01 = w0p[SLOT], v11 = w0p[SLOT + 1];
       const float r0v = fmaf(cx.w0, v00, cx.w1 * v01);
       const float r1v = fmaf(cx.w0, v10, cx.w1 * v11);
       const float wy0 = pad ? 0.0f : ry.w0, wy1 = pad ? 0.0f : ry.w1;
@@ -394,19 +403,22 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
   constexpr int PPL = (NPIX + kWave - 1) / kWave;  // pixels per lane
   const int lane = lane_id();
   const int nl = p.n_layers;
-  // small per-sensor tables -> LDS (consumed by the fold and the image stages)
-  {
+  // small per-sensor tables -> LDS (consumed by the lag sums and the image stages); with a
+  // staged footprint they overlay the window, so they follow it
+  auto tables = [&]() {
     float2* st = reinterpret_cast<float2*>(wsm + lo.stab_off);
     float2* wt = reinterpret_cast<float2*>(wsm + lo.wtab_off);
     for (int k = lane; k < 2 * NS - 1 + S.n_pix; k += kWave) {
       if (k < 2 * NS - 1) st[k] = p.stab[S.stab_off + k];
       else wt[k - (2 * NS - 1)] = p.wtab[S.wtab_off + k - (2 * NS - 1)];
     }
-  }
+  };
+  if constexpr (FIELD != kFieldFoot) tables();
   if constexpr (FIELD == kFieldFoot) {
     float ph[PPL];
     foot_phase<NS>(p, S, sb, sid, b, frame, wsm, lo, ph);
-    wave_sync();  // E overlays the stencil entries the last stencil pass read
+    wave_sync();  // E and the tables overlay the stencil entries and the window just read
+    tables();
     float2* E = reinterpret_cast<float2*>(wsm + lo.e_off);
 #pragma unroll
     for (int i = 0; i < PPL; ++i) {
@@ -418,7 +430,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
         turns -= rintf(turns);
         float sn, cs;
         sincos_rev(turns, &sn, &cs);
-        E[q] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+        E[r * Otf<NS>::kEP + c] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
       }
     }
     wave_sync();
@@ -436,7 +448,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
         turns -= rintf(turns);
         float sn, cs;
         sincos_rev(turns, &sn, &cs);
-        E[q] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+        E[r * Otf<NS>::kEP + c] = amp ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
       }
     }
     wave_sync();
@@ -518,7 +530,8 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
       turns -= rintf(turns);
       float sn, cs;
       sincos_rev(turns, &sn, &cs);
-      if (q < NPIX) E[q] = amp[i] ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
+      if (q < NPIX)
+        E[pr[i] * Otf<NS>::kEP + pc[i]] = amp[i] ? make_float2(cs, sn) : make_float2(0.0f, 0.0f);
     }
     wave_sync();
   }
@@ -556,12 +569,12 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
     const int q = lane / W, k = lane - q * W;
     if (q < NQ) {
       const int dyA = q, dyB = NS - 1 - q, nA = NS - q;
-      const float2* rows = part + q * (NS + 1) * Otf<NS>::kChunk + k;  // the pair's slots
+      const float2* rows = part + q * (NS + 1) * Otf<NS>::kPS + k;  // the pair's slots
       float2 a = make_float2(0.0f, 0.0f), bsum = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int t = 0; t <= NS; ++t) {
         const bool inA = t < nA;
-        const float2 v = rows[t * Otf<NS>::kChunk];
+        const float2 v = rows[t * Otf<NS>::kPS];
         if (inA) {
           a.x += v.x;
           a.y += v.y;
@@ -588,7 +601,7 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
         if (r >= r0 && r < r1) {
-          const float2 v = part[(base + r - j0) * Otf<NS>::kChunk + k];
+          const float2 v = part[(base + r - j0) * Otf<NS>::kPS + k];
           a.x += v.x;
           a.y += v.y;
         }
@@ -631,13 +644,13 @@ __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap
     // the second row stays in registers; the first streams from LDS one pixel at a time
     float2 e2[NS];
 #pragma unroll
-    for (int c = 0; c < NS; ++c) e2[c] = E[(r + dy) * NS + c];
+    for (int c = 0; c < NS; ++c) e2[c] = E[(r + dy) * Otf<NS>::kEP + c];
     float2 acc[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) acc[k] = make_float2(0.0f, 0.0f);
 #pragma unroll
     for (int c1 = 0; c1 < NS; ++c1) {
-      const float2 e1 = E[r * NS + c1];
+      const float2 e1 = E[r * Otf<NS>::kEP + c1];
 #pragma unroll
       for (int c2 = 0; c2 < NS; ++c2) {
         // E[r][c1] conj(E[r+dy][c2]) -> lag dx = c2 - c1, column c2 - c1 + NS - 1
@@ -650,7 +663,7 @@ __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap
       }
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) part[lane * Otf<NS>::kChunk + k] = acc[k];
+    for (int k = 0; k < W; ++k) part[lane * Otf<NS>::kPS + k] = acc[k];
   }
   wave_sync();
   otf_lagsum<NS, IX0, W>(S, sb, el, wsm, lo, j0);
