@@ -19,7 +19,9 @@ __global__ __launch_bounds__(kBlock) void wfs_project_kernel(FwdParams p, float*
 }
 
 // Stencil entries of the staged footprint for the frames of one launch: block per (frame,
-// sensor, layer, axis), thread per pupil index; frame f is at step current_step + f.
+// sensor, layer, axis), thread per pupil index; frame f is at step current_step + f.  The
+// window of a subaperture starts at the first tap of its pupil index of smallest coordinate,
+// so each entry's offset in that window is known here (same arithmetic as the projection).
 __global__ __launch_bounds__(kBlock) void wfs_foot_entries_kernel(FwdParams p, FootEnt* out) {
   const int per_frame = p.n_sensors * p.n_layers * 2;
   const int f = blockIdx.x / per_frame;
@@ -29,11 +31,18 @@ __global__ __launch_bounds__(kBlock) void wfs_foot_entries_kernel(FwdParams p, F
   const FootAxis X = p.foot_axis[r];
   const double stepd = (double)(current_step(p) + f);
   FootEnt* e = out + (int64_t)f * p.foot_ent_per_frame + X.ent_off;
+  const int ns = S.n_sub;
   for (int i = threadIdx.x; i < S.n_pup; i += kBlock) {
+    int i0, o;
     const double c = fma(X.a, (double)i, X.b0) + stepd * X.db;
-    int i0;
     const float2 w = foot_axis_tap(c, X.n, X.inv_n, X.boundary, &i0);
-    e[i] = FootEnt{i0, w.x, w.y};
+    const int first = (i / ns) * ns;
+    const int io = X.a >= 0.0 ? first : first + ns - 1;  // the window origin's pupil index
+    (void)foot_axis_tap(fma(X.a, (double)io, X.b0) + stepd * X.db, X.n, X.inv_n, X.boundary,
+                        &o);
+    int rel = i0 - o;
+    if (X.boundary == 0 && rel < 0) rel += X.n;
+    e[i] = FootEnt{w.x * X.weight, w.y * X.weight, (X.koff + rel * X.kmul) * 4, i0};
   }
 }
 

@@ -541,6 +541,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     if (path == kPathOtf) {
       int cols = 0, floats = 0;
       bool ok = true;
+      d.foot_ent_off = (int32_t)foot_ent;
       for (int l = 0; l < n_layers && ok; ++l) {
         const wfs_layer_desc& L = layers[l];
         const DevAffine& A = aff[(size_t)s * n_layers + l];

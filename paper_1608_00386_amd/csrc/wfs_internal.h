@@ -62,7 +62,8 @@ struct DevSensor {
   int32_t fft_cnt_off;    // first of this sensor's chunk counters in one realisation's part
   int32_t fft_adj_off;    // adjoint: first float of this sensor's chunk partials (n_sub^2 per
                           // chunk) in one realisation's part of the adjoint partial buffer
-  int32_t pad4;
+  int32_t foot_ent_off;   // staged footprint: first of this sensor's stencil entries in a
+                          // frame's table, [n_layers][2 axes][n_pup]
 };
 
 // Staged-footprint field: the layer pixels one subaperture's bilinear stencils can touch,
@@ -81,12 +82,15 @@ struct FootAxis {
   int32_t pad[2];
 };
 
-// Bilinear stencil of one pupil index along one axis at one step: the first tap's grid index
-// (wrapped into [0, n) on a periodic grid, the floor of the clamped coordinate on a
-// zero-boundary one) and the two weights (0 for taps off a zero-boundary grid).
+// Bilinear stencil of one pupil index along one axis at one step, as the staged footprint
+// uses it: the two weights times the axis weight (0 for taps off a zero-boundary grid), the
+// byte offset of the first tap in the window of the pupil index's subaperture, and the first
+// tap's grid index (wrapped into [0, n) on a periodic grid, the floor of the clamped
+// coordinate on a zero-boundary one; the window origin when the index is the subaperture's
+// one of smallest coordinate).
 struct FootEnt {
-  int32_t i0;
   float w0, w1;
+  int32_t k, i0;
 };
 
 // One window column of one sensor's footprint: where it is read and where it goes.

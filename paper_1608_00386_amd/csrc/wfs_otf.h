@@ -266,11 +266,12 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
   // 1. window origins, lane per (layer, axis): the first tap of the pupil index with the
   //    smaller coordinate; then the stencil entries, lane per (layer, axis, pupil index),
   //    from the launch's entry table of this frame
-  const FootEnt* ent = p.foot_ent + (int64_t)frame * p.foot_ent_per_frame;
+  const FootEnt* ent =
+      p.foot_ent + (int64_t)frame * p.foot_ent_per_frame + S.foot_ent_off;  // [nl][2][n_pup]
   for (int e = lane; e < 2 * nl; e += kWave) {
-    const FootAxis X = p.foot_axis[fbase * 2 + e];
     const int i0 = (e & 1) ? sb.a * NS : sb.b * NS;
-    forg[e] = ent[X.ent_off + (X.a >= 0.0 ? i0 : i0 + NS - 1)].i0;
+    const double a = p.foot_axis[fbase * 2 + e].a;
+    forg[e] = ent[e * S.n_pup + (a >= 0.0 ? i0 : i0 + NS - 1)].i0;
   }
   wave_sync();
   {
@@ -280,14 +281,11 @@ __device__ __forceinline__ void foot_phase(const FwdParams& p, const DevSensor& 
     for (int l0 = 0; l0 < nl; l0 += LPP) {
       const int l = l0 + lp;
       if (lp < LPP && l < nl) {
-        const FootAxis X = p.foot_axis[(fbase + l) * 2 + axis];
-        const FootEnt E = ent[X.ent_off + idx];
-        int rel = E.i0 - forg[2 * l + axis];
-        if (X.boundary == 0 && rel < 0) rel += X.n;
+        const FootEnt E = ent[(2 * l + axis) * S.n_pup + idx];
         FootTap t;
-        t.w0 = E.w0 * X.weight;  // rows: the projection kernel's ry.w0 * wl
-        t.w1 = E.w1 * X.weight;
-        t.k = (X.koff + rel * X.kmul) * 4;  // byte offset in the window
+        t.w0 = E.w0;  // rows: the projection kernel's ry.w0 * wl
+        t.w1 = E.w1;
+        t.k = E.k;  // byte offset in the window
         tab[l * TPL + j] = t;
       }
     }
