@@ -665,7 +665,7 @@ def main():
     if frames == "one_launch":
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = ("wfs_forward_kernel<10, footprint> (the K frames of one call in launches "
-                     "of up to 64 frames, each after the small launch that fills its frames' "
+                     "of up to 256 frames, each after the small launch that fills its frames' "
                      "stencil entries; each wave projects its subaperture from a footprint "
                      "staged in LDS)")
         traffic_key = "wfs_forward_kernel<10, 2, false, false>"

@@ -113,8 +113,8 @@ typedef struct {
  *   Validation: n_fft % bin == 0, n_fft >= 2*n_sub, grids inside the stride, positive sizes.
  *   Lag-domain sensors (n_sub <= 12) may have different n_sub: each size gets its own spot
  *   launch.  Allocates the device tables, the phase buffers and, where every lag-domain
- *   sensor can stage its footprint, a table of stencil entries for up to 64 frames of one
- *   footprint launch (32 MiB at most).  Synchronises the device (uploads the tables).
+ *   sensor can stage its footprint, a table of stencil entries for up to 256 frames of one
+ *   footprint launch (64 MiB at most).  Synchronises the device (uploads the tables).
  */
 int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_stride,
              const wfs_sensor_desc* sensors, int32_t n_sensors, int32_t batch,
@@ -178,7 +178,7 @@ int wfs_forward(wfs_plan_t plan, const float* layers, int64_t step, uint64_t see
  *   advanced): the same results, bit for bit, as n_steps calls of wfs_forward.  slopes:
  *   device [n_steps][B][n_slopes]; aux: device [n_steps][B][n_valid_total] or NULL.  The
  *   frames run as wfs_plan_schedule's `frames` says: with the staged footprint, one launch
- *   covers up to 64 frames (frame k's blocks follow frame k - 1's: no launch gap, no phase
+ *   covers up to 256 frames (frame k's blocks follow frame k - 1's: no launch gap, no phase
  *   buffer; a small launch before it fills the frames' stencil entries); pipelined, each launch forms the spots of step k and projects the layers for
  *   step k + 1 into the plan's second phase buffer.  Frozen flow (Sec. 2.1) makes every
  *   frame's input known in advance.  Layers must not change during the call.

@@ -902,9 +902,9 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   P->lds_foot = otf_ns ? P->groups[0].lds_foot : 0;
   P->foot_ok = otf_ns && foot_ok && foot_ent > 0 && foot_ent < (1LL << 31) / 64;
-  if (P->foot_ok) {  // the stencil-entry table: 32 MiB at most, 1 to 64 frames
+  if (P->foot_ok) {  // the stencil-entry table: 64 MiB at most, 1 to 256 frames
     const int64_t per = foot_ent * (int64_t)sizeof(FootEnt);
-    P->foot_ent_cap = (int)std::max<int64_t>(1, std::min<int64_t>(64, (32LL << 20) / per));
+    P->foot_ent_cap = (int)std::max<int64_t>(1, std::min<int64_t>(256, (64LL << 20) / per));
     e = hipMalloc((void**)&P->d_foot_ent, (size_t)(per * P->foot_ent_cap));
     if (e != hipSuccess) {
       (void)hipFree(P->d_blob);
