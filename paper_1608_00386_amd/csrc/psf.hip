@@ -8,15 +8,17 @@
 // a long-exposure image (unit sum per frame, zero frequency at pixel (N/2, N/2)).  The 2-D DFT
 // is two passes over HBM: a row pass (one workgroup per pupil row: phase, field and an N-point
 // FFT in LDS; only the n_pup non-zero rows exist) and a column pass (a few adjacent columns per
-// workgroup, FFT in LDS, intensity accumulated in place).  Both FFTs are Stockham radix-4
-// stages with one radix-2 stage when log2 N is odd; twiddles come from an N-point table
-// computed in double precision on the host (staged in LDS by the column pass).
+// workgroup, FFT in LDS, intensity accumulated in place).  Both FFTs are the Stockham
+// radix-16 (+ one radix-2, 4 or 8 stage) transforms of lds_fft.h, compiled per log2 N, on
+// bank-conflict-free padded LDS; their twiddle table is computed in double precision on the
+// host (staged in LDS by the column pass).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/wfs.h"
@@ -29,8 +31,9 @@ int set_error(int code, const char* msg);
 constexpr int kPsfBlock = 256;
 constexpr int kPsfPoints = 4096;     // largest transform (and one row-pass workgroup's LDS)
 constexpr int kPsfColPoints = 16384; // LDS points of a column-pass workgroup (C columns x N)
-constexpr int kPsfColLds = 160 * 1024;  // its LDS bytes at most: C (N + 1) + N float2
-constexpr int kPsfRowLds = kPsfPoints * 8;  // one row
+constexpr int kPsfColLds = 160 * 1024;  // its LDS bytes at most: C pitch + N - 1 float2
+constexpr int kPsfRowLds = fft_span(kPsfPoints) * 8;  // one padded row
+constexpr int kPsfMinLog2 = 4, kPsfMaxLog2 = 12;
 constexpr int kPsfMaxLambda = 16;
 constexpr int kPsfMaxStars = 256;
 
@@ -44,7 +47,7 @@ struct PsfParams {
   const DevLayer* lay;
   const PsfAff* aff;     // [n_stars][n_layers]
   const uint8_t* mask;   // [n_pup][n_pup] pupil amplitude (0 / 1)
-  const float2* tw;      // exp(-2 pi i m / N), m < N
+  const float2* tw;      // the N - 1 twiddles of lds_fft, stage after stage
   float2* T;             // [n_stars][n_pup][N] row transforms
   double* part;          // [n_stars][n_pup][2]: row sums of A phi and A phi^2 (reference wavelength)
   float* psf;            // this wavelength's [n_stars][N][N]
@@ -66,12 +69,14 @@ struct RowLayer {
 
 // Row pass: workgroup (row y, star s).  Phase of the pupil row, field, N-point FFT, row of T
 // stored in C-column tiles: T[s][k / C][y][k % C], so the column pass reads whole tiles.
+template <int LOG2N>
 __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
   extern __shared__ float2 sh[];
   __shared__ double red[2][kPsfBlock];
   __shared__ RowLayer rl[kMaxLayers];
+  constexpr int N = 1 << LOG2N;
   const int y = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
-  const int n = p.n_pup, N = p.N, C = p.cols;
+  const int n = p.n_pup, C = p.cols, lc = __builtin_ctz(C);  // C: a power of two
   if (tid < p.n_layers) {
     const DevLayer L = p.lay[tid];
     const PsfAff A = p.aff[s * p.n_layers + tid];
@@ -131,12 +136,12 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
         sincosf(p.kappa * phi[j], &sn, &cs);
         e = make_float2(cs, sn);
       }
-      if (x < N) sh[x] = e;
+      if (x < N) sh[fft_pad(x)] = e;
     }
   }
   for (int x = n + tid; x < N; x += kPsfBlock) {  // zero padding beyond the pupil
     if (x >= ((n + kPix * kPsfBlock - 1) / (kPix * kPsfBlock)) * kPix * kPsfBlock)
-      sh[x] = make_float2(0.0f, 0.0f);
+      sh[fft_pad(x)] = make_float2(0.0f, 0.0f);
   }
   if (p.write_part) {  // fixed-order tree: deterministic row sums
     red[0][tid] = s1;
@@ -156,11 +161,11 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
     }
   }
   __syncthreads();
-  lds_fft<kPsfPoints, kPsfBlock>(sh, 1, N, N, p.log2N, p.tw);
+  lds_fft<LOG2N, N, kPsfBlock>(sh, 1, fft_span(N), p.tw);
   float2* out = p.T + (int64_t)s * n * N + (int64_t)y * C;
   for (int x = tid; x < N; x += kPsfBlock) {
-    const int kt = x / C;
-    out[(int64_t)kt * n * C + (x - kt * C)] = sh[x];
+    const int kt = x >> lc;
+    out[(int64_t)kt * n * C + (x - kt * C)] = sh[fft_pad(x)];
   }
 }
 
@@ -168,22 +173,24 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
 // column groups share an XCD (and its L2 lines of T).  Zero rows beyond the pupil are implicit.
 constexpr int kPsfColBlock = 1024;  // 16 waves: the column pass is LDS-latency bound
 
+template <int LOG2N>
 __global__ __launch_bounds__(kPsfColBlock) void psf_cols_kernel(PsfParams p) {
   extern __shared__ float2 sh[];
+  constexpr int N = 1 << LOG2N;
   const int tid = threadIdx.x;
-  const int C = p.cols, N = p.N, n = p.n_pup, ld = N + 1;
-  const int groups = N / C;
+  const int C = p.cols, lc = __builtin_ctz(C), n = p.n_pup, ld = fft_pitch(N, C);
+  const int groups = N >> lc;
   const int lb = xcd_logical_block(blockIdx.x, groups * p.n_stars);
   const int s = lb / groups, k0 = (lb - s * groups) * C;
   const float2* src = p.T + (int64_t)s * n * N + (int64_t)k0 * n;  // tile k0 / C: [n][C]
   float2* tws = sh + C * ld;  // the twiddle table, staged in LDS after the data
   for (int i = tid; i < C * N; i += kPsfColBlock) {
-    const int c = i & (C - 1), y = i / C;
-    sh[c * ld + y] = y < n ? src[i] : make_float2(0.0f, 0.0f);
+    const int c = i & (C - 1), y = i >> lc;
+    sh[c * ld + fft_pad(y)] = y < n ? src[i] : make_float2(0.0f, 0.0f);
   }
-  for (int i = tid; i < N; i += kPsfColBlock) tws[i] = p.tw[i];
+  for (int i = tid; i < N - 1; i += kPsfColBlock) tws[i] = p.tw[i];
   __syncthreads();
-  lds_fft<kPsfColPoints, kPsfColBlock>(sh, C, ld, N, p.log2N, tws);
+  lds_fft<LOG2N, kPsfColPoints, kPsfColBlock>(sh, C, ld, tws);
   // intensities from LDS, then every read of the long-exposure image before any write (one
   // memory latency per thread instead of one per pixel)
   float* __restrict__ dst = p.psf + (int64_t)s * N * N;
@@ -195,8 +202,8 @@ __global__ __launch_bounds__(kPsfColBlock) void psf_cols_kernel(PsfParams p) {
   for (int r = 0; r < kPer; ++r) {
     const int i = tid + r * kPsfColBlock;
     if (i < C * N) {
-      const int c = i & (C - 1), v = i / C;
-      const float2 f = sh[c * ld + v];
+      const int c = i & (C - 1), v = i >> lc;
+      const float2 f = sh[c * ld + fft_pad(v)];
       val[r] = (f.x * f.x + f.y * f.y) * p.scale;
       at[r] = (int64_t)((v + h) & (N - 1)) * N + ((k0 + c + h) & (N - 1));
     }
@@ -315,6 +322,22 @@ static void psf_free(psf_plan_t P) {
   delete P;
 }
 
+// Calls f(std::integral_constant<int, log2 N>) for a transform size of the plan.
+template <class F>
+static void psf_dispatch(int log2N, F&& f) {
+  switch (log2N) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    case 11: f(std::integral_constant<int, 11>{}); break;
+    default: f(std::integral_constant<int, 12>{}); break;
+  }
+}
+
 template <class T>
 static hipError_t upload(T** dst, const std::vector<T>& v) {
   hipError_t e = hipMalloc((void**)dst, v.size() * sizeof(T));
@@ -420,25 +443,31 @@ int psf_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     while ((1 << lg) < N) ++lg;
     P->N.push_back(N);
     P->log2N.push_back(lg);
-    // C columns of N points plus the N twiddles must fit the 160 KB of LDS
+    // C padded columns of N points plus the N - 1 twiddles must fit the 160 KB of LDS
     P->cols.push_back(N >= 4096 ? 2 : std::min(16, kPsfColPoints / N));
     P->kappa.push_back((float)(lambda_ref_m / lambda_m[l]));
     P->psf_off.push_back(P->psf_floats);
     P->psf_floats += (int64_t)n_stars * N * N;
     P->tw_off.push_back((int64_t)tw.size());
-    for (int m = 0; m < N; ++m) {
-      const double a = -2.0 * M_PI * (double)m / (double)N;
+    for (int m = 0; m < N - 1; ++m) {
+      const double a = -2.0 * M_PI * (double)fft_tw_angle(lg, m) / (double)N;
       tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
     }
     Nmax = std::max(Nmax, N);
   }
   // the column pass holds more than the default 64 KB of LDS (data, padding and twiddles)
-  if ((e = hipFuncSetAttribute((const void*)psf_cols_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kPsfColLds)) !=
-          hipSuccess ||
-      (e = hipFuncSetAttribute((const void*)psf_rows_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kPsfRowLds)) !=
-          hipSuccess) {
+  e = hipSuccess;
+  for (int lg = kPsfMinLog2; lg <= kPsfMaxLog2 && e == hipSuccess; ++lg) {
+    psf_dispatch(lg, [&](auto L) {
+      constexpr int LG = decltype(L)::value;
+      if ((e = hipFuncSetAttribute((const void*)psf_cols_kernel<LG>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kPsfColLds)) ==
+          hipSuccess)
+        e = hipFuncSetAttribute((const void*)psf_rows_kernel<LG>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kPsfRowLds);
+    });
+  }
+  if (e != hipSuccess) {
     psf_free(P);
     return psf_hip(e, "psf_plan: column-pass LDS");
   }
@@ -504,8 +533,10 @@ int psf_accumulate(psf_plan_t P, const float* layers, int64_t step, float* psf,
     p.kappa = P->kappa[l];
     p.scale = (float)(1.0 / ((double)p.N * p.N * (double)P->n_lit));
     p.write_part = (l == 0 && phase_var) ? 1 : 0;
-    psf_rows_kernel<<<dim3(P->n_pup, P->n_stars), kPsfBlock, (size_t)p.N * sizeof(float2),
-                      st>>>(p);
+    psf_dispatch(p.log2N, [&](auto L) {
+      psf_rows_kernel<decltype(L)::value><<<dim3(P->n_pup, P->n_stars), kPsfBlock,
+                                            (size_t)fft_span(p.N) * sizeof(float2), st>>>(p);
+    });
     if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: rows");
     if (p.write_part) {
       PsfVarParams q{};
@@ -520,8 +551,10 @@ int psf_accumulate(psf_plan_t P, const float* layers, int64_t step, float* psf,
       if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: variance");
     }
     const int blocks = (p.N / p.cols) * P->n_stars;
-    const size_t lds = ((size_t)p.cols * (p.N + 1) + p.N) * sizeof(float2);
-    psf_cols_kernel<<<blocks, kPsfColBlock, lds, st>>>(p);
+    const size_t lds = ((size_t)p.cols * fft_pitch(p.N, p.cols) + p.N - 1) * sizeof(float2);
+    psf_dispatch(p.log2N, [&](auto L) {
+      psf_cols_kernel<decltype(L)::value><<<blocks, kPsfColBlock, lds, st>>>(p);
+    });
     if ((e = hipGetLastError()) != hipSuccess) return psf_hip(e, "psf_accumulate: columns");
   }
   return WFS_OK;

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/wfs.h"
 #include "lds_fft.h"
@@ -39,19 +40,23 @@ struct ScreenParams {
   uint32_t seed_lo, seed_hi, sid_lo, sid_hi;
 };
 
-// exp(-2 pi i m / n) for m < n into LDS (FP32 sincospi: about one ulp).
-__device__ __forceinline__ void screen_twiddles(float2* tws, int n, int nthreads) {
-  for (int m = threadIdx.x; m < n; m += nthreads) {
+// The n - 1 twiddles of lds_fft into LDS (FP32 sincospi: about one ulp).
+template <int LOG2N>
+__device__ __forceinline__ void screen_twiddles(float2* tws, int nthreads) {
+  constexpr int n = 1 << LOG2N;
+  for (int m = threadIdx.x; m < n - 1; m += nthreads) {
     float sn, cs;
-    sincospif(-2.0f * (float)m / (float)n, &sn, &cs);
+    sincospif(-2.0f * (float)fft_tw_angle(LOG2N, m) / (float)n, &sn, &cs);
     tws[m] = make_float2(cs, sn);
   }
 }
 
 // Row pass: workgroup per row ky of the spectrum.
+template <int LOG2N>
 __global__ __launch_bounds__(kScrBlock) void screen_rows_kernel(ScreenParams p) {
   extern __shared__ float2 sh[];
-  const int ky = blockIdx.x, tid = threadIdx.x, n = p.n, C = p.cols;
+  constexpr int n = 1 << LOG2N;
+  const int ky = blockIdx.x, tid = threadIdx.x, C = p.cols, lc = __builtin_ctz(C);
   const int iy = ky < n / 2 ? ky : ky - n;  // frequency index in [-n/2, n/2)
   const float fy = (float)iy * p.inv_ndx;
   for (int kx = tid; kx < n; kx += kScrBlock) {
@@ -69,38 +74,40 @@ __global__ __launch_bounds__(kScrBlock) void screen_rows_kernel(ScreenParams p) 
     float sn, cs;
     sincos_rev(u24(w.y), &sn, &cs);
     // conjugate spectrum: the forward transform of conj(S) is conj of the inverse of S
-    sh[kx] = make_float2(r * cs * amp, -(r * sn * amp));
+    sh[fft_pad(kx)] = make_float2(r * cs * amp, -(r * sn * amp));
   }
-  float2* tws = sh + n;  // the twiddles, after the row
-  screen_twiddles(tws, n, kScrBlock);
+  float2* tws = sh + fft_span(n);  // the twiddles, after the row
+  screen_twiddles<LOG2N>(tws, kScrBlock);
   __syncthreads();
-  lds_fft<kScrMaxN, kScrBlock>(sh, 1, n, n, p.log2n, tws);
+  lds_fft<LOG2N, n, kScrBlock>(sh, 1, fft_span(n), tws);
   float2* o = p.T + (int64_t)ky * C;
   for (int x = tid; x < n; x += kScrBlock) {
-    const int kt = x / C;
-    o[(int64_t)kt * n * C + (x - kt * C)] = sh[x];
+    const int kt = x >> lc;
+    o[(int64_t)kt * n * C + (x - kt * C)] = sh[fft_pad(x)];
   }
 }
 
 // Column pass: C adjacent columns per workgroup; the screen is the real part.
+template <int LOG2N>
 __global__ __launch_bounds__(kScrColBlock) void screen_cols_kernel(ScreenParams p) {
   extern __shared__ float2 sh[];
-  const int tid = threadIdx.x, n = p.n, C = p.cols, ld = n + 1;
-  const int groups = n / C;
+  constexpr int n = 1 << LOG2N;
+  const int tid = threadIdx.x, C = p.cols, lc = __builtin_ctz(C), ld = fft_pitch(n, C);
+  const int groups = n >> lc;
   const int g = xcd_logical_block(blockIdx.x, groups);
   const int x0 = g * C;
   const float2* src = p.T + (int64_t)x0 * n;  // tile x0 / C: [n][C]
   float2* tws = sh + C * ld;
   for (int i = tid; i < C * n; i += kScrColBlock) {
-    const int c = i & (C - 1), y = i / C;
-    sh[c * ld + y] = src[i];
+    const int c = i & (C - 1), y = i >> lc;
+    sh[c * ld + fft_pad(y)] = src[i];
   }
-  screen_twiddles(tws, n, kScrColBlock);
+  screen_twiddles<LOG2N>(tws, kScrColBlock);
   __syncthreads();
-  lds_fft<kScrColPoints, kScrColBlock>(sh, C, ld, n, p.log2n, tws);
+  lds_fft<LOG2N, kScrColPoints, kScrColBlock>(sh, C, ld, tws);
   for (int i = tid; i < C * n; i += kScrColBlock) {
-    const int c = i & (C - 1), y = i / C;
-    p.out[(int64_t)y * n + x0 + c] = sh[c * ld + y].x;
+    const int c = i & (C - 1), y = i >> lc;
+    p.out[(int64_t)y * n + x0 + c] = sh[c * ld + fft_pad(y)].x;
   }
 }
 
@@ -109,6 +116,22 @@ __global__ __launch_bounds__(kScrColBlock) void screen_cols_kernel(ScreenParams 
 using namespace wfs;
 
 static int scr_fail(int code, const char* msg) { return set_error(code, msg); }
+
+// Calls f(std::integral_constant<int, log2 n>) for a screen size 16 <= n <= 4096.
+template <class F>
+static void scr_dispatch(int log2n, F&& f) {
+  switch (log2n) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 9: f(std::integral_constant<int, 9>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    case 11: f(std::integral_constant<int, 11>{}); break;
+    default: f(std::integral_constant<int, 12>{}); break;
+  }
+}
 
 extern "C" {
 
@@ -132,8 +155,15 @@ int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_
   static std::once_flag lds_once;
   static hipError_t lds_err = hipSuccess;
   std::call_once(lds_once, [] {
-    lds_err = hipFuncSetAttribute((const void*)screen_cols_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    for (int lg = 4; lg <= 12 && lds_err == hipSuccess; ++lg)
+      scr_dispatch(lg, [&](auto L) {  // columns and twiddles, or a 4096-point row and its
+                                      // twiddles, hold more than the default 64 KB of LDS
+        lds_err = hipFuncSetAttribute((const void*)screen_cols_kernel<decltype(L)::value>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (lds_err == hipSuccess)
+          lds_err = hipFuncSetAttribute((const void*)screen_rows_kernel<decltype(L)::value>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      });
   });
   if (lds_err != hipSuccess) return scr_fail(WFS_EDEVICE, hipGetErrorString(lds_err));
   hipStream_t st = (hipStream_t)stream;
@@ -150,10 +180,15 @@ int screen_generate(int32_t n, double pitch_m, double r0_m, double L0_m, uint64_
   p.seed_hi = (uint32_t)(seed >> 32);
   p.sid_lo = (uint32_t)stream_id;
   p.sid_hi = (uint32_t)(stream_id >> 32);
-  screen_rows_kernel<<<n, kScrBlock, 2 * (size_t)n * sizeof(float2), st>>>(p);
+  const size_t row_lds = ((size_t)fft_span(n) + n - 1) * sizeof(float2);
+  scr_dispatch(log2n, [&](auto L) {
+    screen_rows_kernel<decltype(L)::value><<<n, kScrBlock, row_lds, st>>>(p);
+  });
   if ((e = hipGetLastError()) != hipSuccess) return scr_fail(WFS_EDEVICE, hipGetErrorString(e));
-  const size_t lds = ((size_t)cols * (n + 1) + n) * sizeof(float2);
-  screen_cols_kernel<<<n / cols, kScrColBlock, lds, st>>>(p);
+  const size_t lds = ((size_t)cols * fft_pitch(n, cols) + n - 1) * sizeof(float2);
+  scr_dispatch(log2n, [&](auto L) {
+    screen_cols_kernel<decltype(L)::value><<<n / cols, kScrColBlock, lds, st>>>(p);
+  });
   if ((e = hipGetLastError()) != hipSuccess) return scr_fail(WFS_EDEVICE, hipGetErrorString(e));
   return WFS_OK;
 }

@@ -105,6 +105,13 @@ static void set_proj(FwdParams& p, const ProjTable& t) {
   p.proj_per_real = t.per_real;
 }
 
+// One projection tile height offered by a plan: blocks of rows pupil rows (all sensors, and
+// the FFT-path sensors alone) and the LDS bytes of a block.
+struct ProjSet {
+  ProjTable all, fft;
+  int rows = 0, lds = 0, lds_fft = 0;
+};
+
 struct OtfGroup {
   int ns = 0, max_npix = 0, foot_floats = 0;
   std::vector<int> ids;
@@ -155,7 +162,9 @@ struct wfs_plan_s {
   int lds_split_otf = 0, lds_fused_otf = 0;  // same, in a launch without FFT-path blocks
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
-  ProjTable proj_all{}, proj_fft{};
+  ProjTable proj_all{}, proj_fft{};  // the projection blocks of the current tile height
+  std::vector<ProjSet> proj_sets;    // every tile height the plan offers (rows ascending)
+  int proj_set = 0;                  // the current one
   float* d_phase = nullptr;   // split-mode phase buffer [B][phase_per_real]
   float* d_phase2 = nullptr;  // second buffer (pipelined frames), same allocation
   int split = 0;             // 1: projection kernel + spot kernel; 0: fused gather
@@ -182,6 +191,19 @@ struct wfs_plan_s {
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
+
+// Makes projection tile height i of the plan the current one (host only: the descriptors of
+// every height are on the device already, and each height gives the same bits).
+static void use_proj_set(wfs_plan_s* P, int i) {
+  const ProjSet& q = P->proj_sets[i];
+  P->proj_set = i;
+  P->proj_all = q.all;
+  P->proj_fft = q.fft;
+  P->proj_lds = q.lds;
+  P->proj_lds_fft = q.lds_fft;
+  P->base.proj_lds = q.lds;
+  set_proj(P->base, q.all);
+}
 
 // ------------------------------------------------------------------------------------------
 // geometry
@@ -415,14 +437,14 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     d.ramp_y = (float)(0.5 / S.n_fft - S.tilt_y_rad * g.dx / S.lambda_m);
     // projection blocks: (group of project_rows() pupil rows, strip of project_strip()
     // columns) holding at least one pixel of a valid subaperture; packed row0 | strip << 16
-    d.proj_rows = project_rows();
+    d.pad5 = 0;
     d.inv_nsub = 1.0f / (float)S.n_sub;
     d.subidx_off = (int32_t)subidx.size();
     {
       std::vector<int32_t> idx((size_t)S.n_sa * S.n_sa, -1);
       for (const DevSubap& q : g.subs) idx[(size_t)q.a * S.n_sa + q.b] = q.v;
       subidx.insert(subidx.end(), idx.begin(), idx.end());
-      const int W = project_strip(), RG = d.proj_rows;
+      const int W = project_strip(), RG = project_rows();
       const int strips = (g.n_pup + W - 1) / W;
       for (int r0 = 0; r0 < g.n_pup; r0 += RG)
         for (int st = 0; st < strips; ++st) {
@@ -663,28 +685,20 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   }
   P->fft_part_per_real = fft_part;
   P->fft_cnt_per_real = fft_cnt;
-  // Taller projection blocks (G row groups: each column tap serves G times more pixels) when
-  // a launch still has enough blocks to fill the chip at two per CU and SIMD pair.
+  // Projection tile heights: G groups of project_rows() rows per block, G = 1, 2, 4 where a
+  // block's taps fit 32 KiB of LDS (taller blocks share each column tap among more pixels).
+  // By default the tallest whose launch still has enough blocks to fill the chip at two per
+  // CU and SIMD pair; wfs_plan_tune times them all.
+  std::vector<int> proj_gs{1};
+  int proj_g_default = 0;
   {
     int64_t n1 = 0;
     for (int s = 0; s < n_sensors; ++s) n1 += (int64_t)proj_desc_s[s].size();
     n1 *= batch;
-    int G = 1;
-    while (2 * G <= project_max_groups() && n1 / (2 * G) >= 4096 &&
-           project_lds_bytes(n_layers, project_rows() * 2 * G) <= 32768)
-      G *= 2;
-    if (G > 1) {
-      const int RG = project_rows(), RT = RG * G;
-      for (int s = 0; s < n_sensors; ++s) {
-        std::vector<int2> merged;
-        std::set<std::pair<int, int>> seen;
-        for (const int2& d : proj_desc_s[s]) {
-          const int r0 = (d.x & 0xFFFF) / RT * RT, st = d.x >> 16;
-          if (seen.insert({r0, st}).second) merged.push_back(make_int2(r0 | (st << 16), s));
-        }
-        proj_desc_s[s] = merged;
-        ds[s].proj_rows = RT;
-      }
+    for (int G = 2; G <= project_max_groups(); G *= 2) {
+      if (project_lds_bytes(n_layers, project_rows() * G) > 32768) break;
+      proj_gs.push_back(G);
+      if (n1 / G >= 4096) proj_g_default = (int)proj_gs.size() - 1;
     }
   }
   P->hsen = ds;
@@ -741,7 +755,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   // regions (all of them the same ground-layer pixels), and blocks that are neighbours in
   // this order run at about the same time on the same XCD, so those reads meet in its L2
   // instead of each sensor's pass re-fetching the layers from memory.
-  auto interleave = [&](bool fft_only) {
+  auto interleave = [&](const std::vector<std::vector<int2>>& lists, bool fft_only) {
     struct Key {
       double row, col;
       int s;
@@ -751,7 +765,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     for (int s = 0; s < n_sensors; ++s) {
       if (fft_only && ds[s].path != kPathFft) continue;
       const double np = (double)ds[s].n_pup;
-      for (const int2& d : proj_desc_s[s])
+      for (const int2& d : lists[s])
         keys.push_back(Key{(double)(d.x & 0xFFFF) / np,
                            (double)(d.x >> 16) * project_strip() / np, s, d});
     }
@@ -765,9 +779,28 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     for (const Key& k : keys) out.push_back(k.d);
     return out;
   };
-  const std::vector<int2> desc_all = interleave(false), desc_fft = interleave(true);
-  const size_t o_pall = push_table(blob, desc_all);
-  const size_t o_pfft = push_table(blob, desc_fft);
+  // blocks of G row groups: the G = 1 blocks merged by row group (sensor | log2 G << 24)
+  std::vector<size_t> o_pall, o_pfft, n_pall, n_pfft;
+  for (int G : proj_gs) {
+    const int RT = project_rows() * G;
+    int lg = 0;
+    while ((1 << lg) < G) ++lg;
+    std::vector<std::vector<int2>> lists(n_sensors);
+    for (int s = 0; s < n_sensors; ++s) {
+      std::set<std::pair<int, int>> seen;
+      for (const int2& d : proj_desc_s[s]) {
+        const int r0 = (d.x & 0xFFFF) / RT * RT, st = d.x >> 16;
+        if (seen.insert({r0, st}).second)
+          lists[s].push_back(make_int2(r0 | (st << 16), s | (lg << 24)));
+      }
+    }
+    const std::vector<int2> desc_all = interleave(lists, false),
+                            desc_fft = interleave(lists, true);
+    o_pall.push_back(push_table(blob, desc_all));
+    o_pfft.push_back(push_table(blob, desc_fft));
+    n_pall.push_back(desc_all.size());
+    n_pfft.push_back(desc_fft.size());
+  }
   std::vector<int64_t> step0(1, 0);
   const size_t o_step = push_table(blob, step0);
   if (adj_segs.empty()) adj_segs.push_back(AdjSeg{});
@@ -800,10 +833,22 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   b.foot_cols = reinterpret_cast<const FootCol*>(P->d_blob + o_fcols);
   b.foot_axis = reinterpret_cast<const FootAxis*>(P->d_blob + o_faxis);
   b.n_frames = 1;
-  P->proj_all.desc = reinterpret_cast<const int2*>(P->d_blob + o_pall);
-  P->proj_all.per_real = (int32_t)desc_all.size();
-  P->proj_fft.desc = reinterpret_cast<const int2*>(P->d_blob + o_pfft);
-  P->proj_fft.per_real = (int32_t)desc_fft.size();
+  {
+    bool any_fft = false;
+    for (int s = 0; s < n_sensors; ++s) any_fft = any_fft || ds[s].path == kPathFft;
+    for (size_t i = 0; i < proj_gs.size(); ++i) {
+      ProjSet q;
+      q.all.desc = reinterpret_cast<const int2*>(P->d_blob + o_pall[i]);
+      q.all.per_real = (int32_t)n_pall[i];
+      q.fft.desc = reinterpret_cast<const int2*>(P->d_blob + o_pfft[i]);
+      q.fft.per_real = (int32_t)n_pfft[i];
+      q.rows = project_rows() * proj_gs[i];
+      q.lds = project_lds_bytes(n_layers, q.rows);
+      q.lds_fft = any_fft ? q.lds : 0;
+      P->proj_sets.push_back(q);
+    }
+    use_proj_set(P, proj_g_default);
+  }
   P->d_step = reinterpret_cast<int64_t*>(P->d_blob + o_step);
   P->d_adj_segs = reinterpret_cast<const AdjSeg*>(P->d_blob + o_adjseg);
   P->d_adj_tab_off = reinterpret_cast<const int64_t*>(P->d_blob + o_adjoff);
@@ -831,11 +876,6 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       units[s] = P->n_valid[s] * Q * Q;
     }
     fill_tasks(b.fft, fft_ids, units);
-  }
-  for (int s = 0; s < n_sensors; ++s) {
-    const int lb = project_lds_bytes(n_layers, ds[s].proj_rows);
-    P->proj_lds = std::max(P->proj_lds, lb);
-    if (ds[s].path == kPathFft) P->proj_lds_fft = std::max(P->proj_lds_fft, lb);
   }
   set_proj(b, P->proj_all);
   b.phase_per_real = P->phase_per_real;
@@ -1302,23 +1342,36 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
 }
 
 int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xcd_remap,
-                      int32_t* fft_launch) {
+                      int32_t* fft_launch, int32_t* proj_rows) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_schedule: null plan");
   const bool split = P->split && P->d_phase;
   if (field) *field = P->foot ? 2 : (split ? 1 : 0);
   if (frames) *frames = P->frames;
   if (xcd_remap) *xcd_remap = P->base.xcd_remap;
   if (fft_launch) *fft_launch = P->base.fft_inline;
+  if (proj_rows) *proj_rows = P->proj_sets[P->proj_set].rows;
   return WFS_OK;
 }
 
 int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t xcd_remap,
-                          int32_t fft_launch) {
+                          int32_t fft_launch, int32_t proj_rows) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_set_schedule: null plan");
   if (field < -1 || field > 2 || frames < -1 || frames > 2 || xcd_remap < -1 ||
-      xcd_remap > 1 || fft_launch < -1 || fft_launch > 1)
+      xcd_remap > 1 || fft_launch < -1 || fft_launch > 1 || proj_rows < -1)
     return fail(WFS_EINVAL, "wfs_plan_set_schedule: field=%d frames=%d xcd_remap=%d "
-                "fft_launch=%d out of range", field, frames, xcd_remap, fft_launch);
+                "fft_launch=%d proj_rows=%d out of range", field, frames, xcd_remap, fft_launch,
+                proj_rows);
+  int ps = P->proj_set;
+  if (proj_rows >= 0) {
+    ps = -1;
+    for (size_t i = 0; i < P->proj_sets.size(); ++i)
+      if (P->proj_sets[i].rows == proj_rows) ps = (int)i;
+    if (ps < 0)
+      return fail(WFS_EUNSUPPORTED,
+                  "wfs_plan_set_schedule: the plan offers no projection blocks of %d rows "
+                  "(%d to %d, doubling, where a block's taps fit 32 KiB of LDS)",
+                  proj_rows, P->proj_sets.front().rows, P->proj_sets.back().rows);
+  }
   const int cur_field = P->foot ? 2 : ((P->split && P->d_phase) ? 1 : 0);
   const int f = field < 0 ? cur_field : field;
   const int fr = frames < 0 ? P->frames : frames;
@@ -1342,6 +1395,7 @@ int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t x
   P->frames = fr;
   if (xcd_remap >= 0) P->base.xcd_remap = xcd_remap;
   if (fft_launch >= 0) P->base.fft_inline = fft_launch;
+  use_proj_set(P, ps);
   return WFS_OK;
 }
 
@@ -1575,35 +1629,48 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   };
   const FwdParams keep = P->base;
   const int keep_split = P->split, keep_foot = P->foot, keep_frames = P->frames;
-  // candidates (field, frames, block order, FFT-path blocks in the lag-domain launch), timed on
-  // nf frames in a row (the stepping loop the plan serves); only schedules whose single frames
-  // and frames in a row give the same bits: the gather field steps frame by frame, the split
-  // and footprint fields share their bits with pipelined and one-launch frames
+  const int keep_ps = P->proj_set;
+  // candidates (field, frames, block order, FFT-path blocks in the lag-domain launch,
+  // projection tile height), timed on nf frames in a row (the stepping loop the plan serves);
+  // only schedules whose single frames and frames in a row give the same bits: the gather
+  // field steps frame by frame, the split and footprint fields share their bits with
+  // pipelined and one-launch frames; every tile height gives the same bits
   struct Cand {
-    int field, frames, remap, inl;
+    int field, frames, remap, inl, ps;
   };
   std::vector<Cand> cands;
   const bool has_fft = P->fft_tasks > 0, mixed = P->fft_tasks > 0 && P->otf_tasks > 0;
   const bool phase_ok = P->d_phase && P->proj_lds <= 65536;
   const bool foot1 = P->foot_ok && !has_fft;  // footprint field for single frames
   const uint32_t fl = P->flags;
+  const int n_ps = (int)P->proj_sets.size();
+  // the tile heights of the projection kernel, for a schedule that launches it (the split
+  // field, and the FFT-path sensors of any field)
+  auto add = [&](Cand c) {
+    const bool proj = c.field == 1 || has_fft;
+    for (int ps = 0; ps < (proj ? n_ps : 1); ++ps) {
+      c.ps = proj ? ps : keep_ps;
+      cands.push_back(c);
+    }
+  };
   for (int remap = 0; remap < 2; ++remap)
     for (int inl = 0; inl < (mixed ? 2 : 1); ++inl) {
-      if (!(fl & (WFS_FLAG_SPLIT | WFS_FLAG_FOOTPRINT))) cands.push_back({0, 0, remap, inl});
+      if (!(fl & (WFS_FLAG_SPLIT | WFS_FLAG_FOOTPRINT))) add({0, 0, remap, inl, 0});
       if (phase_ok && !(fl & WFS_FLAG_FUSED)) {
         if (!((fl & WFS_FLAG_FOOTPRINT) && foot1)) {
-          cands.push_back({1, 0, remap, inl});
-          cands.push_back({1, 1, remap, inl});
+          add({1, 0, remap, inl, 0});
+          add({1, 1, remap, inl, 0});
         }
       }
       if (inl == 0 && P->foot_ok && !(fl & (WFS_FLAG_FUSED | WFS_FLAG_SPLIT)) &&
           (foot1 || phase_ok))
-        cands.push_back({foot1 ? 2 : 1, 2, remap, 0});
+        add({foot1 ? 2 : 1, 2, remap, 0, 0});
     }
   auto apply = [&](const Cand& c) {
     P->base = keep;
     P->base.xcd_remap = c.remap;
     P->base.fft_inline = c.inl;
+    use_proj_set(P, c.ps);
     P->split = c.field == 1;
     P->foot = c.field == 2;
     P->frames = c.frames;
@@ -1655,6 +1722,7 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   (void)hipFree(aux);
   if (e != hipSuccess) {
     P->base = keep;
+    use_proj_set(P, keep_ps);
     P->split = keep_split;
     P->foot = keep_foot;
     P->frames = keep_frames;

@@ -38,8 +38,7 @@ struct DevSensor {
   int32_t n_sa, n_sub, n_fft, bin;
   int32_t n_pix, n_pup, n_valid, valid_off;  // valid_off: first row of the subap table
   int32_t slope_off, aux_off, mask_off, path;
-  int32_t noisy, elong, phase_off, proj_rows;  // phase_off: offset in the phase buffer;
-                                               // proj_rows: pixel rows per projection block
+  int32_t noisy, elong, phase_off, pad5;  // phase_off: offset in the phase buffer
   float kappa;       // lambda_ref / lambda
   float flux_c;      // F_ph / (n_fft^2 n_sub^2)
   float read_noise;  // electrons rms

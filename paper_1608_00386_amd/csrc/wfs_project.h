@@ -7,9 +7,10 @@
 namespace wfs {
 
 // Block = (realisation, sensor, G groups of kProjRows consecutive pupil rows, strip of
-// kProjStrip pupil columns) from one two-word descriptor (G = the sensor's proj_rows /
-// kProjRows, chosen per plan: taller blocks share each column tap among more rows when there
-// are blocks enough to fill the chip); thread = one pupil column and two rows of each group
+// kProjStrip pupil columns) from one two-word descriptor (row0 | strip << 16, sensor |
+// log2 G << 24; G is a tile choice of the plan: taller blocks share each column tap among
+// more rows, shorter ones fill the chip with more blocks); thread = one pupil column and two
+// rows of each group
 // (ty and ty + kProjRows / 2, ty = wave).  The column taps of the strip and the row taps of
 // the rows (FP64 coordinates, byte offsets) go to LDS once per block; each thread then has
 // the stencil loads of both its pixels for kProjLC layers in flight at once, consecutive
@@ -94,12 +95,13 @@ __device__ __forceinline__ void project_block(const FwdParams& p, int blk, float
                                               double stepd, char* smem) {
   const int b = blk / p.proj_per_real;
   const int2 d = cload(p.proj_desc, blk - b * p.proj_per_real);
-  const int sid = d.y;
+  const int sid = d.y & 0xFFFFFF;
   const int row0 = d.x & 0xFFFF, c0 = (d.x >> 16) * kProjStrip;
+  const int rows = kProjRows << (d.y >> 24);
   const int tx = threadIdx.x & (kProjStrip - 1);
   const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / kProjStrip);  // wave index
   const DevSensor S = cload(p.sen, sid);
-  const int ns = S.n_sub, rows = S.proj_rows;
+  const int ns = S.n_sub;
   const int ic = c0 + tx;
   const int bs = fdiv(ic, ns, S.inv_nsub);
   project_taps(p, sid, row0, rows, c0, stepd, smem, ty, tx);

@@ -156,24 +156,27 @@ class Plan:
     FFT_LAUNCH = ("side_stream", "same_launch")
 
     def schedule(self):
-        """dict(field, frames, xcd_remap, fft_launch) of the current launch schedule: field is
-        where a frame's spot waves get the phase ("gather", "split", "footprint"), frames how
-        ``forward_steps`` runs ("sequential", "pipelined", "one_launch"), fft_launch where
-        FFT-path blocks run ("side_stream" or "same_launch")."""
-        v = [ctypes.c_int32() for _ in range(4)]
+        """dict(field, frames, xcd_remap, fft_launch, proj_rows) of the current launch
+        schedule: field is where a frame's spot waves get the phase ("gather", "split",
+        "footprint"), frames how ``forward_steps`` runs ("sequential", "pipelined",
+        "one_launch"), fft_launch where FFT-path blocks run ("side_stream" or "same_launch"),
+        proj_rows the projection kernel's pupil rows per block."""
+        v = [ctypes.c_int32() for _ in range(5)]
         L.check(self._lib.wfs_plan_schedule(self._h, *[ctypes.byref(x) for x in v]),
                 "wfs_plan_schedule")
         return dict(field=self.FIELDS[v[0].value], frames=self.FRAMES[v[1].value],
-                    xcd_remap=v[2].value, fft_launch=self.FFT_LAUNCH[v[3].value])
+                    xcd_remap=v[2].value, fft_launch=self.FFT_LAUNCH[v[3].value],
+                    proj_rows=v[4].value)
 
-    def set_schedule(self, field=None, frames=None, xcd_remap=None, fft_launch=None):
+    def set_schedule(self, field=None, frames=None, xcd_remap=None, fft_launch=None,
+                     proj_rows=None):
         """Pin a launch schedule (names as ``schedule`` reports them; None keeps a choice)."""
         def code(names, v):
             return -1 if v is None else (names.index(v) if isinstance(v, str) else int(v))
         L.check(self._lib.wfs_plan_set_schedule(
             self._h, code(self.FIELDS, field), code(self.FRAMES, frames),
-            -1 if xcd_remap is None else int(xcd_remap), code(self.FFT_LAUNCH, fft_launch)),
-            "wfs_plan_set_schedule")
+            -1 if xcd_remap is None else int(xcd_remap), code(self.FFT_LAUNCH, fft_launch),
+            -1 if proj_rows is None else int(proj_rows)), "wfs_plan_set_schedule")
 
     def footprint(self, step=0):
         """(distinct layer pixels read, projected pixels) per realisation at ``step``."""

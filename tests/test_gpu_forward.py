@@ -393,3 +393,46 @@ def test_pinned_schedules_give_the_same_bits(name):
     with pytest.raises(W.WfsError) as e:
         plan.set_schedule(field="gather", frames="pipelined")
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("name", ["mixed_lgs_ngs_batch2", "config2_batch2", "cfg1"])
+def test_projection_tile_heights_give_the_same_bits(name):
+    """The projection kernel's tile height (wfs_plan_set_schedule's proj_rows: 8, 16 or 32
+    pupil rows per block) moves pixels between blocks, not their arithmetic: the projected
+    phase and the slopes (single split frames, pipelined frames) are bit for bit the same at
+    every height the plan offers; a height it does not offer is refused."""
+    torch, W = _gpu()
+    if name == "config2_batch2":
+        cfg, B = synth.config2(batch=2), 2
+        x = synth.make_batch(cfg, range(B))
+    elif name == "cfg1":
+        cfg, B = synth.config1(), 1
+        x = synth.make_batch(cfg, [0])
+    else:
+        cfg = CASES[name]()
+        x = layers_for(cfg)
+        B = x.shape[0]
+    xt = torch.from_numpy(x).cuda()
+    plan = W.Plan(cfg, batch=B)
+    offered = []
+    for rows in (8, 16, 32):
+        try:
+            plan.set_schedule(field="split", frames="sequential", proj_rows=rows)
+        except W.WfsError as e:
+            assert e.code == -4
+            continue
+        assert plan.schedule()["proj_rows"] == rows
+        offered.append((rows, plan.project(xt, step=5).clone(),
+                        plan.forward(xt, step=5, seed=3)[0].clone()))
+        plan.set_schedule(frames="pipelined")
+        offered[-1] += (plan.forward_steps(xt, 5, 3, seed=3)[0].clone(),)
+    assert offered and offered[0][0] == 8
+    for rows, ph, s1, s3 in offered[1:]:
+        assert torch.equal(ph, offered[0][1]), rows
+        assert torch.equal(s1, offered[0][2]), rows
+        assert torch.equal(s3, offered[0][3]), rows
+    assert torch.equal(offered[0][3][0], offered[0][2])
+    for bad in (12, 64):
+        with pytest.raises(W.WfsError) as e:
+            plan.set_schedule(proj_rows=bad)
+        assert e.value.code == -4
