@@ -286,7 +286,11 @@ def bench_calibration(torch, W, batch=128, amp=0.5, eps=0.05, loop_steps=60, gai
     t0 = time.perf_counter()
     R = W.tlse(im, eps=eps)
     tlse_ms = (time.perf_counter() - t0) * 1e3
+    m_act, n_s = im.shape
     del im
+    # library FLOPs of the solve: syrk m^2 n_s, Cholesky m^3 / 3, two triangular solves of
+    # m^2 n_s each (FP32, priced against the FP32 matrix-core peak)
+    tlse_flops = 3.0 * m_act * m_act * n_s + m_act ** 3 / 3.0
     # closed loop against open loop, same layers and steps, with and without noise
     B = cfg4["batch"]
     x0 = torch.from_numpy(synth.make_batch(cfg4, range(B))).cuda()
@@ -325,6 +329,12 @@ def bench_calibration(torch, W, batch=128, amp=0.5, eps=0.05, loop_steps=60, gai
                 lgs_frames_per_s=n_lgs * 2 * n / (cal_ms * 1e-3),
                 effective_tflops=2 * n * real_flops / (cal_ms * 1e-3) / 1e12,
                 tlse_ms=tlse_ms,
+                tlse_roofline=dict(bound="mfma", flops=tlse_flops,
+                                   achieved=tlse_flops / (tlse_ms * 1e-3) / 1e12, peak=157.3,
+                                   unit="TFLOP/s",
+                                   frac=tlse_flops / (tlse_ms * 1e-3) / 1e12 / 157.3,
+                                   note="rocBLAS ssyrk + rocSOLVER spotrf + 2 rocBLAS strsm, "
+                                        "host-timed call including its synchronisation"),
                 closed_loop_steps=loop_steps,
                 closed_over_open_slope_norm=ratio,
                 closed_over_open_slope_norm_noise_free=ratio_nf,

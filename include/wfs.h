@@ -15,7 +15,7 @@
  *   - All data buffers are DEVICE pointers owned by the caller (float32, row-major).
  *   - Every call that takes a `stream` (a hipStream_t; NULL = the default stream) is
  *     asynchronous on it and never synchronises the device, except wfs_plan, wfs_plan_destroy,
- *     wfs_plan_na_profile and wfs_plan_tune (and wfs_tlse).  No call allocates device memory
+ *     wfs_plan_na_profile and wfs_plan_tune (and wfs_tlse, include/wfs_tlse.h).  No call allocates device memory
  *     except wfs_plan, wfs_plan_na_profile, recon_apply (first use on a stream, or a larger
  *     problem than that stream has seen; never while the stream is capturing a graph) and
  *     wfs_adjoint (first use of a plan).
@@ -335,21 +335,6 @@ int wfs_calibrate_work(wfs_plan_t plan, int64_t* work_floats);
 int wfs_calibrate(wfs_plan_t plan, const float* base, int64_t act_offset, int32_t n_act,
                   float amplitude, int64_t step, uint64_t seed, float* im, int64_t ld_im,
                   float* ref_slopes, float* work, int64_t work_floats, void* stream);
-
-/*
- * wfs_tlse -- control matrix from an interaction matrix (Sec. 2.6: least-squares estimator,
- *   with a regularisation coefficient and per-actuator weights that set how the correction is
- *   shared between the DMs):  R = (D^T D + lambda diag(w))^-1 D^T,  lambda = eps * mean of
- *   diag(D^T D), where D[k][j] = im[j][k] (n_s slopes x m actuators).  im: device [m][ld_im]
- *   as wfs_calibrate writes it.  weights: device [m], >= 0, or NULL (all 1).  R: device
- *   [m][ld_r], row-major as recon_apply takes it; R == im (in place, ld_r == ld_im) is
- *   allowed.  work: device, >= m*m + 64 floats.  Set-up work: rocBLAS syrk and trsm with a
- *   rocSOLVER Cholesky factorisation, FP32; synchronises `stream`.  Returns WFS_EINVAL when
- *   the regularised matrix is not positive definite (eps = 0 with a rank-deficient D).
- */
-int wfs_tlse(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
-             const float* weights, float* R, int64_t ld_r, float* work, int64_t work_floats,
-             void* stream);
 
 /*
  * Point-spread functions and Strehl ratios (Sec. 2.8: PSFs at user wavelengths and pixel

@@ -1,4 +1,4 @@
-"""ctypes view of libwfs.so (include/wfs.h).  Loading fails loudly when the library is absent:
+"""ctypes view of libwfs.so (include/wfs.h) and libwfs_tlse.so (include/wfs_tlse.h).  Loading fails loudly when the library is absent:
 there is no other implementation to fall back to."""
 
 import ctypes
@@ -7,6 +7,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwfs.so")
+TLSE_LIB_PATH = os.path.join(HERE, "libwfs_tlse.so")
 
 WFS_OK = 0
 WFS_EINVAL = -1
@@ -102,8 +103,6 @@ _PROTOS = {
     "wfs_calibrate_work": (_c.c_int, [_P, _c.POINTER(_c.c_int64)]),
     "wfs_calibrate": (_c.c_int, [_P, _P, _c.c_int64, _c.c_int32, _c.c_float, _c.c_int64,
                                  _c.c_uint64, _P, _c.c_int64, _P, _P, _c.c_int64, _P]),
-    "wfs_tlse": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_float, _P, _P,
-                            _c.c_int64, _P, _c.c_int64, _P]),
     "psf_plan": (_c.c_int, [_c.POINTER(LayerDesc), _c.c_int32, _c.c_int64,
                             _c.POINTER(_c.c_double), _c.c_int32, _c.c_double, _c.c_double,
                             _c.c_int32, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int32),
@@ -117,6 +116,14 @@ _PROTOS = {
                                    _c.c_uint64, _c.c_uint64, _P, _P, _c.c_int64, _P]),
     "wfs_last_error": (_c.c_char_p, []),
 }
+
+# libwfs_tlse.so (include/wfs_tlse.h): the control-matrix solve, the one library that links
+# rocBLAS and rocSOLVER
+_TLSE_PROTOS = {
+    "wfs_tlse": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_float, _P, _P,
+                            _c.c_int64, _P, _c.c_int64, _P]),
+}
+_tlse = None
 
 
 def lib():
@@ -134,6 +141,23 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def lib_tlse():
+    """The loaded libwfs_tlse.so (after libwfs.so, whose error state it shares)."""
+    global _tlse
+    if _tlse is None:
+        lib()
+        if not os.path.exists(TLSE_LIB_PATH):
+            raise ImportError(f"{TLSE_LIB_PATH} is missing: build it with "
+                              "`python -m paper_1608_00386_amd.build`")
+        L = ctypes.CDLL(TLSE_LIB_PATH)
+        for name, (res, args) in _TLSE_PROTOS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _tlse = L
+    return _tlse
 
 
 def check(rc, what=""):

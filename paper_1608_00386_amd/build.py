@@ -14,6 +14,9 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwfs.so")
+# the control-matrix solve (rocBLAS / rocSOLVER) is a library of its own, beside libwfs.so
+TLSE_SRC = "tlse.hip"
+TLSE_LIB = os.path.join(HERE, "libwfs_tlse.so")
 ARCH = os.environ.get("WFS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -46,7 +49,8 @@ def _run(cmd):
 
 
 def build(verbose=False, extra=()):
-    """Compile every csrc/*.hip unit to an object (in parallel), then link libwfs.so."""
+    """Compile every csrc/*.hip unit to an object (in parallel), then link libwfs.so (all but
+    tlse.hip) and libwfs_tlse.so (tlse.hip, rocBLAS, rocSOLVER and libwfs.so)."""
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with tempfile.TemporaryDirectory(prefix="wfs_build_") as tmpdir:
@@ -60,17 +64,27 @@ def build(verbose=False, extra=()):
         msgs = [l for _, lines in results for l in lines]
         if any(rc != 0 for rc, _ in results):
             raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
+        tlse_obj = [o for s, o in zip(srcs, objs) if os.path.basename(s) == TLSE_SRC]
+        wfs_objs = [o for o in objs if o not in tlse_obj]
         tmp = LIB + ".tmp"
-        # rocBLAS / rocSOLVER: the one-off dense algebra of the control matrix (wfs_tlse)
-        rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
-        link = ([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs +
-                [f"-L{rocm_lib}", "-lrocsolver", "-lrocblas", "-o", tmp])
+        link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + wfs_objs + ["-o", tmp]
         rc, lines = _run(link)
         if rc != 0:
             raise RuntimeError("link failed:\n" + "\n".join(lines))
-        if verbose and msgs + lines:
-            print("\n".join(msgs + lines))
-    os.replace(tmp, LIB)
+        os.replace(tmp, LIB)
+        # rocBLAS / rocSOLVER: the one-off dense algebra of the control matrix (wfs_tlse);
+        # libwfs.so found beside it at load time
+        rocm_lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+        tmp2 = TLSE_LIB + ".tmp"
+        link2 = ([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + tlse_obj +
+                 [f"-L{HERE}", "-lwfs", "-Wl,-rpath,$ORIGIN", f"-L{rocm_lib}", "-lrocsolver",
+                  "-lrocblas", "-o", tmp2])
+        rc, lines2 = _run(link2)
+        if rc != 0:
+            raise RuntimeError("link failed:\n" + "\n".join(lines2))
+        os.replace(tmp2, TLSE_LIB)
+        if verbose and msgs + lines + lines2:
+            print("\n".join(msgs + lines + lines2))
     return LIB
 
 

@@ -51,9 +51,6 @@ hipError_t calib_poke(float* layers, const float* base, int64_t stride, int32_t 
                       int32_t n_chunk, float amp, hipStream_t st);
 hipError_t calib_diff(const float* slopes, int32_t h, int32_t n_slopes, int32_t n_chunk,
                       float amp, float* im, int64_t ld_im, hipStream_t st);
-const char* tlse_run(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
-                     const float* w, float* R, int64_t ld_r, float* work, hipStream_t st,
-                     int* info);
 int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats);
 int foot_pitch(int ns);
 int fft_wave_lds_bytes(int n_fft, int n_pix);
@@ -1873,34 +1870,6 @@ int wfs_calibrate(wfs_plan_t P, const float* base, int64_t act_offset, int32_t n
                         st)) != hipSuccess)
       return hip_fail(e, "wfs_calibrate: difference");
   }
-  return WFS_OK;
-}
-
-int wfs_tlse(const float* im, int32_t m, int32_t n_s, int64_t ld_im, float eps,
-             const float* weights, float* R, int64_t ld_r, float* work, int64_t work_floats,
-             void* stream) {
-  if (!im || !R || !work) return fail(WFS_EINVAL, "wfs_tlse: null im, R or work");
-  if (m < 1 || n_s < 1) return fail(WFS_EINVAL, "wfs_tlse: m=%d n_s=%d must be >= 1", m, n_s);
-  if (m > 46000) return fail(WFS_EINVAL, "wfs_tlse: m=%d > 46000 actuators", m);
-  if (ld_im < n_s || ld_r < n_s || ld_im > INT32_MAX || ld_r > INT32_MAX)
-    return fail(WFS_EINVAL, "wfs_tlse: ld_im=%lld and ld_r=%lld must lie in [n_s=%d, 2^31)",
-                (long long)ld_im, (long long)ld_r, n_s);
-  if (R == im && ld_r != ld_im)
-    return fail(WFS_EINVAL, "wfs_tlse: in place (R == im) needs ld_r == ld_im");
-  if (!std::isfinite(eps) || eps < 0.0f)
-    return fail(WFS_EINVAL, "wfs_tlse: eps must be finite and >= 0");
-  const int64_t need = (int64_t)m * m + 64;
-  if (work_floats < need)
-    return fail(WFS_EINVAL, "wfs_tlse: work holds %lld floats, needs %lld",
-                (long long)work_floats, (long long)need);
-  int info = 0;
-  const char* err = tlse_run(im, m, n_s, ld_im, eps, weights, R, ld_r, work,
-                             (hipStream_t)stream, &info);
-  if (err) return fail(WFS_EDEVICE, "wfs_tlse: %s", err);
-  if (info != 0)
-    return fail(WFS_EINVAL,
-                "wfs_tlse: the regularised normal matrix is not positive definite (leading "
-                "minor %d): raise eps or the weights", info);
   return WFS_OK;
 }
 

@@ -298,9 +298,9 @@ def tlse(im, eps=1e-3, weights=None, out=None, stream=None):
         out = torch.empty(m, n_s, device=im.device)
     _need(out, "out", shape=(m, n_s))
     work = torch.empty(m * m + 64, device=im.device)
-    L.check(L.lib().wfs_tlse(_ptr(im), int(m), int(n_s), int(n_s), float(eps), _ptr(weights),
-                             _ptr(out), int(n_s), _ptr(work), work.numel(), _stream(stream)),
-            "wfs_tlse")
+    L.check(L.lib_tlse().wfs_tlse(_ptr(im), int(m), int(n_s), int(n_s), float(eps),
+                                  _ptr(weights), _ptr(out), int(n_s), _ptr(work), work.numel(),
+                                  _stream(stream)), "wfs_tlse")
     return out
 
 

@@ -12,10 +12,11 @@ import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "wfs.h")
+TLSE_HEADER = os.path.join(ROOT, "include", "wfs_tlse.h")
 
 
-def _declared_functions():
-    txt = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    txt = open(header).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     names = re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
@@ -35,6 +36,32 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
     # the ctypes prototypes cover the whole header
     assert set(_declared_functions()) == set(_lib._PROTOS)
+    T = _lib.lib_tlse()
+    assert _declared_functions(TLSE_HEADER) == ["wfs_tlse"]
+    for n in _declared_functions(TLSE_HEADER):
+        assert hasattr(T, n), n
+    assert set(_declared_functions(TLSE_HEADER)) == set(_lib._TLSE_PROTOS)
+
+
+def test_hot_path_library_needs_no_dense_algebra_library():
+    """libwfs.so (the per-frame path) does not link rocBLAS or rocSOLVER; only the control-matrix
+    library does, and it finds libwfs.so beside itself."""
+    import shutil
+    import subprocess
+    from paper_1608_00386_amd import _lib
+    readelf = shutil.which("readelf")
+    if readelf is None:
+        pytest.skip("no readelf")
+
+    def needed(path):
+        out = subprocess.run([readelf, "-d", path], capture_output=True, text=True,
+                             check=True).stdout
+        return re.findall(r"\(NEEDED\)\s+Shared library: \[([^\]]+)\]", out), out
+    libs, _ = needed(_lib.LIB_PATH)
+    assert libs and not any("rocblas" in n or "rocsolver" in n for n in libs), libs
+    libs, out = needed(_lib.TLSE_LIB_PATH)
+    assert "libwfs.so" in libs and any("rocblas" in n for n in libs), libs
+    assert "$ORIGIN" in out
 
 
 def test_struct_layouts_match_header_sizes(tmp_path):
@@ -165,15 +192,16 @@ def test_calibration_calls_reject_bad_arguments_without_a_device():
                            None) == -1
     assert "null plan" in L.wfs_last_error().decode()
     # wfs_tlse: shapes, leading dimensions, eps, workspace, in-place stride
-    assert L.wfs_tlse(None, 4, 8, 8, 0.1, None, fake, 8, fake, 100, None) == -1
-    assert L.wfs_tlse(fake, 0, 8, 8, 0.1, None, fake, 8, fake, 100, None) == -1
-    assert L.wfs_tlse(fake, 4, 8, 7, 0.1, None, fake, 8, fake, 100, None) == -1
+    T = _lib.lib_tlse()
+    assert T.wfs_tlse(None, 4, 8, 8, 0.1, None, fake, 8, fake, 100, None) == -1
+    assert T.wfs_tlse(fake, 0, 8, 8, 0.1, None, fake, 8, fake, 100, None) == -1
+    assert T.wfs_tlse(fake, 4, 8, 7, 0.1, None, fake, 8, fake, 100, None) == -1
     assert "ld_im" in L.wfs_last_error().decode()
-    assert L.wfs_tlse(fake, 4, 8, 8, -1.0, None, fake, 8, fake, 100, None) == -1
-    assert L.wfs_tlse(fake, 4, 8, 8, math.nan, None, fake, 8, fake, 100, None) == -1
-    assert L.wfs_tlse(fake, 4, 8, 8, 0.1, None, fake, 8, fake, 79, None) == -1
+    assert T.wfs_tlse(fake, 4, 8, 8, -1.0, None, fake, 8, fake, 100, None) == -1
+    assert T.wfs_tlse(fake, 4, 8, 8, math.nan, None, fake, 8, fake, 100, None) == -1
+    assert T.wfs_tlse(fake, 4, 8, 8, 0.1, None, fake, 8, fake, 79, None) == -1
     assert "work" in L.wfs_last_error().decode()
-    assert L.wfs_tlse(fake, 4, 8, 8, 0.1, None, ctypes.c_void_p(4096), 9, fake, 100,
+    assert T.wfs_tlse(fake, 4, 8, 8, 0.1, None, ctypes.c_void_p(4096), 9, fake, 100,
                       None) == -1
     assert "in place" in L.wfs_last_error().decode()
 
