@@ -177,7 +177,8 @@ int wfs_forward(wfs_plan_t plan, const float* layers, int64_t step, uint64_t see
  *   with step0 = WFS_STEP_DEVICE, the device counter + 0 .. n_steps - 1; the counter is not
  *   advanced): the same results, bit for bit, as n_steps calls of wfs_forward.  slopes:
  *   device [n_steps][B][n_slopes]; aux: device [n_steps][B][n_valid_total] or NULL.  The
- *   frames run as wfs_plan_schedule's `frames` says: with the staged footprint, one launch
+ *   frames run as wfs_plan_schedule's `frames` says (overlapped: projections on a second
+ *   stream, forked from and joined to `stream`): with the staged footprint, one launch
  *   covers up to 256 frames (frame k's blocks follow frame k - 1's: no launch gap, no phase
  *   buffer; a small launch before it fills the frames' stencil entries); pipelined, each launch forms the spots of step k and projects the layers for
  *   step k + 1 into the plan's second phase buffer.  Frozen flow (Sec. 2.1) makes every
@@ -203,7 +204,9 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
  *   itself (one launch, no phase buffer).  frames: how wfs_forward_steps runs, 0 = one
  *   wfs_forward per frame, 1 = pipelined split frames, 2 = one footprint launch for all
  *   frames (FFT-path sensors, which read the projected phase, then run frame by frame on
- *   the plan's second stream beside it).  Fields 1 and 2 and frames 0-2 give the same bits;
+ *   the plan's second stream beside it), 3 = overlapped split frames (frame k + 1 projected
+ *   on a plan-owned stream while frame k's spots run on `stream`; the call forks from and
+ *   joins `stream`).  Fields 1 and 2 and frames 0-3 give the same bits;
  *   field 0 its own.  Field 2 for single frames needs a plan without FFT-path sensors.
  *   xcd_remap = 1 when blocks are renumbered so neighbouring tasks share an XCD.
  *   fft_launch (plans with both paths, fields 0 and 1): 0 = the FFT-path blocks run as a
@@ -220,7 +223,7 @@ int wfs_plan_schedule(wfs_plan_t plan, int32_t* field, int32_t* frames, int32_t*
 /*
  * wfs_plan_set_schedule -- pin a launch schedule (values as wfs_plan_schedule reports them;
  *   -1 keeps a choice).  WFS_EUNSUPPORTED when the plan cannot run it: field 1 or frames 1
- *   without a phase buffer, field 2 or frames 2 where a lag-domain sensor cannot stage its
+ *   or 3 without a phase buffer, field 2 or frames 2 where a lag-domain sensor cannot stage its
  *   footprint, field 2 for single frames with FFT-path sensors, frames 1 or 2 with field 0,
  *   a proj_rows the plan does not offer.  Host only; no device work.
  */
@@ -268,7 +271,8 @@ int wfs_set_step(wfs_plan_t plan, int64_t step, void* stream);
 int wfs_advance_step(wfs_plan_t plan, int64_t delta, void* stream);
 
 /*
- * wfs_plan_tune -- time every launch schedule the plan can run (field, frame schedule, block
+ * wfs_plan_tune -- time every launch schedule the plan can run (field, frame schedule incl.
+ *   overlapped frames, block
  *   order, projection tile height where the projection kernel runs and, with both paths,
  *   where the FFT-path blocks run) on max(2, iters) frames in a
  *   row from `layers` and keep the fastest; only schedules whose single frames and frames in

@@ -168,13 +168,22 @@ struct wfs_plan_s {
   int foot_ok = 0;           // every lag-domain sensor can stage its footprint, no FFT path
   int foot = 0;              // staged-footprint field (overrides split / fused gather)
   // wfs_forward_steps: 0 one wfs_forward per frame, 1 pipelined split frames, 2 one
-  // staged-footprint launch for all frames (1 and 2 only when the single-frame field is the
-  // split or the footprint one: all three give the same bits)
+  // staged-footprint launch for all frames, 3 split frames with the next frame's projection
+  // on a second stream (1-3 only when the single-frame field is the split or the footprint
+  // one: all four give the same bits)
   int frames = 0;
   int lds_foot = 0;          // LDS bytes per lag-domain wave with the staged footprint
   FootEnt* d_foot_ent = nullptr;  // stencil entries of up to foot_ent_cap frames
   int foot_ent_cap = 0;           // frames per footprint launch (longer runs take several)
   SideStream side{};         // FFT-path blocks run here concurrently (plans with both paths)
+  // overlapped frames (frames == 3): frame k + 1 is projected here while frame k's spots run
+  // on the caller's stream; proj_done[i] / spot_done[i]: the last projection into / spot
+  // launch from phase buffer i
+  struct {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, proj_done[2] = {nullptr, nullptr},
+               spot_done[2] = {nullptr, nullptr};
+  } ovl;
   float* d_fft_adj = nullptr;    // FFT-path adjoint: per-chunk phase-gradient shares and the
   float* d_adj_fwd = nullptr;    // noise-free forward outputs it needs ([B][n_slopes + n_valid])
   int64_t fft_adj_per_real = 0;  // (both allocated on the first adjoint call)
@@ -188,6 +197,18 @@ struct wfs_plan_s {
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
+
+static void destroy_ovl(wfs_plan_s* P) {
+  for (int i = 0; i < 2; ++i) {
+    if (P->ovl.proj_done[i]) (void)hipEventDestroy(P->ovl.proj_done[i]);
+    if (P->ovl.spot_done[i]) (void)hipEventDestroy(P->ovl.spot_done[i]);
+    P->ovl.proj_done[i] = P->ovl.spot_done[i] = nullptr;
+  }
+  if (P->ovl.fork) (void)hipEventDestroy(P->ovl.fork);
+  if (P->ovl.stream) (void)hipStreamDestroy(P->ovl.stream);
+  P->ovl.fork = nullptr;
+  P->ovl.stream = nullptr;
+}
 
 // Makes projection tile height i of the plan the current one (host only: the descriptors of
 // every height are on the device already, and each height gives the same bits).
@@ -1013,6 +1034,23 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     P->base.fft_part_per_real = P->fft_part_per_real;
     P->base.fft_cnt_per_real = (int32_t)P->fft_cnt_per_real;
   }
+  if (P->d_phase) {  // overlapped frames: the projection stream and its events
+    e = hipStreamCreateWithFlags(&P->ovl.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ovl.fork, hipEventDisableTiming);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipEventCreateWithFlags(&P->ovl.proj_done[i], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ovl.spot_done[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      destroy_ovl(P);
+      (void)hipFree(P->d_blob);
+      (void)hipFree(P->d_phase);
+      if (P->d_fft_part) (void)hipFree(P->d_fft_part);
+      if (P->d_fft_cnt) (void)hipFree(P->d_fft_cnt);
+      delete P;
+      return hip_fail(e, "wfs_plan: projection stream");
+    }
+  }
   if (P->fft_tasks > 0 && P->otf_tasks > 0) {  // both paths: FFT-path blocks on a side stream
     e = hipStreamCreateWithFlags(&P->side.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->side.fork, hipEventDisableTiming);
@@ -1021,6 +1059,7 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       if (P->side.join) (void)hipEventDestroy(P->side.join);
       if (P->side.fork) (void)hipEventDestroy(P->side.fork);
       if (P->side.stream) (void)hipStreamDestroy(P->side.stream);
+      destroy_ovl(P);
       (void)hipFree(P->d_blob);
       if (P->d_phase) (void)hipFree(P->d_phase);
       if (P->d_fft_part) (void)hipFree(P->d_fft_part);
@@ -1067,6 +1106,7 @@ int wfs_plan_destroy(wfs_plan_t P) {
   if (P->side.join) (void)hipEventDestroy(P->side.join);
   if (P->side.fork) (void)hipEventDestroy(P->side.fork);
   if (P->side.stream) (void)hipStreamDestroy(P->side.stream);
+  destroy_ovl(P);
   delete P;
   if (e != hipSuccess) return hip_fail(e, "wfs_plan_destroy");
   return WFS_OK;
@@ -1222,7 +1262,11 @@ int wfs_forward(wfs_plan_t P, const float* layers, int64_t step, uint64_t seed, 
 // Frames step0 .. step0 + n - 1 (or the device counter + k), outputs of frame k at slopes +
 // k * (slopes of one frame).  Staged footprint: one launch for all frames.  Pipelined (split
 // schedule only): project frame 0; then launch k computes the spots of frame k from phase
-// buffer k % 2 and projects frame k + 1 into the other buffer.
+// buffer k % 2 and projects frame k + 1 into the other buffer.  Overlapped: the projection of
+// frame k + 1 (into buffer (k + 1) % 2, once the spots of frame k - 1 have read it) runs on
+// the plan's projection stream while the spots of frame k (after its projection) run on st;
+// the projection kernel is bound by the vector L1's access rate, the spot kernel by vector
+// issue, so the two share the chip.
 static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, int n,
                             uint64_t seed, float* slopes, float* aux, int frames,
                             hipStream_t st) {
@@ -1279,6 +1323,39 @@ static hipError_t run_steps(wfs_plan_t P, const float* layers, int64_t step0, in
       e = hipEventRecord(P->side.join, fs);
       if (e == hipSuccess) e = hipStreamWaitEvent(st, P->side.join, 0);
     }
+    return e;
+  }
+  if (frames == 3 && P->ovl.stream && P->d_phase) {
+    float* buf[2] = {P->d_phase, P->d_phase2};
+    hipStream_t ps = P->ovl.stream;
+    auto project_into = [&](int k) {
+      FwdParams q = frame(k);
+      set_proj(q, P->proj_all);
+      hipError_t r = launch_project(q, buf[k & 1], P->proj_lds, ps);
+      if (r == hipSuccess) r = hipEventRecord(P->ovl.proj_done[k & 1], ps);
+      return r;
+    };
+    e = hipEventRecord(P->ovl.fork, st);  // the projections follow everything queued on st
+    if (e == hipSuccess) e = hipStreamWaitEvent(ps, P->ovl.fork, 0);
+    if (e == hipSuccess) e = project_into(0);
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+      if (k + 1 < n) {
+        if (k >= 1) e = hipStreamWaitEvent(ps, P->ovl.spot_done[(k - 1) & 1], 0);
+        if (e == hipSuccess) e = project_into(k + 1);
+        if (e != hipSuccess) break;
+      }
+      e = hipStreamWaitEvent(st, P->ovl.proj_done[k & 1], 0);
+      if (e != hipSuccess) break;
+      FwdParams p = frame(k);
+      p.phase_in = buf[k & 1];
+      p.otf_from_phase = 1;
+      p.proj_blocks = 0;
+      p.lds_per_wave = P->lds_split;
+      p.lds_per_wave_otf = P->lds_split_otf;
+      e = launch_groups(P, p, st, &P->side);
+      if (e == hipSuccess) e = hipEventRecord(P->ovl.spot_done[k & 1], st);
+    }
+    // the last projection is joined by the wait before the last spot launch
     return e;
   }
   if (!pipelined) {
@@ -1353,7 +1430,7 @@ int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xc
 int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t xcd_remap,
                           int32_t fft_launch, int32_t proj_rows) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_set_schedule: null plan");
-  if (field < -1 || field > 2 || frames < -1 || frames > 2 || xcd_remap < -1 ||
+  if (field < -1 || field > 2 || frames < -1 || frames > 3 || xcd_remap < -1 ||
       xcd_remap > 1 || fft_launch < -1 || fft_launch > 1 || proj_rows < -1)
     return fail(WFS_EINVAL, "wfs_plan_set_schedule: field=%d frames=%d xcd_remap=%d "
                 "fft_launch=%d proj_rows=%d out of range", field, frames, xcd_remap, fft_launch,
@@ -1379,7 +1456,7 @@ int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t x
     return fail(WFS_EUNSUPPORTED,
                 "wfs_plan_set_schedule: a sensor cannot take the footprint field for single "
                 "frames");
-  if (fr == 1 && !phase_ok)
+  if ((fr == 1 || fr == 3) && !phase_ok)
     return fail(WFS_EUNSUPPORTED, "wfs_plan_set_schedule: no phase buffer for pipelined frames");
   if (fr == 2 && !P->foot_ok)
     return fail(WFS_EUNSUPPORTED,
@@ -1657,6 +1734,7 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
         if (!((fl & WFS_FLAG_FOOTPRINT) && foot1)) {
           add({1, 0, remap, inl, 0});
           add({1, 1, remap, inl, 0});
+          if (P->ovl.stream) add({1, 3, remap, inl, 0});
         }
       }
       if (inl == 0 && P->foot_ok && !(fl & (WFS_FLAG_FUSED | WFS_FLAG_SPLIT)) &&

@@ -152,14 +152,14 @@ class Plan:
         return slopes, aux
 
     FIELDS = ("gather", "split", "footprint")
-    FRAMES = ("sequential", "pipelined", "one_launch")
+    FRAMES = ("sequential", "pipelined", "one_launch", "overlapped")
     FFT_LAUNCH = ("side_stream", "same_launch")
 
     def schedule(self):
         """dict(field, frames, xcd_remap, fft_launch, proj_rows) of the current launch
         schedule: field is where a frame's spot waves get the phase ("gather", "split",
         "footprint"), frames how ``forward_steps`` runs ("sequential", "pipelined",
-        "one_launch"), fft_launch where FFT-path blocks run ("side_stream" or "same_launch"),
+        "one_launch", "overlapped": the next frame projected on a second stream), fft_launch where FFT-path blocks run ("side_stream" or "same_launch"),
         proj_rows the projection kernel's pupil rows per block."""
         v = [ctypes.c_int32() for _ in range(5)]
         L.check(self._lib.wfs_plan_schedule(self._h, *[ctypes.byref(x) for x in v]),

@@ -296,6 +296,47 @@ def test_config0_paper_sampling_counts():
     np.testing.assert_allclose(plan1.pix_scale[0], oracle.pixel_scale(synth.config1()["sensors"][0]))
 
 
+@pytest.mark.parametrize("name", ["mixed_lgs_ngs_batch2", "config2_batch2"])
+def test_overlapped_frames_match_single_frames_and_replay(name):
+    """Overlapped frames (frame k + 1 projected on the plan's projection stream while frame
+    k's spots run): every frame equals the single-frame call bit for bit, eagerly and in a
+    captured graph replayed several times with eager work in between."""
+    torch, W = _gpu()
+    if name == "config2_batch2":
+        cfg, B = synth.config2(batch=2), 2
+        x = synth.make_batch(cfg, range(B))
+    else:
+        cfg = CASES[name]()
+        x = layers_for(cfg)
+        B = x.shape[0]
+    plan = W.Plan(cfg, batch=B)
+    xt = torch.from_numpy(x).cuda()
+    n, k0 = 5, 7
+    plan.set_schedule(field="split", frames="overlapped")
+    assert plan.schedule()["frames"] == "overlapped"
+    ref = torch.stack([plan.forward(xt, step=k0 + k, seed=2)[0].clone() for k in range(n)])
+    s, _ = plan.forward_steps(xt, k0, n, seed=2)
+    assert torch.equal(s, ref)
+    out = torch.empty_like(ref)
+    aux = torch.empty(n, B, plan.n_valid_total, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.forward_steps(xt, k0, n, seed=2, slopes=out, aux=aux)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.forward_steps(xt, k0, n, seed=2, slopes=out, aux=aux)
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        plan.forward_steps(xt, 1, 2, seed=9)  # eager work between the replays
+        torch.cuda.synchronize()
+
+
 def test_side_stream_graph_replays_match_eager():
     """A plan with FFT-path and lag-domain sensors runs the FFT-path blocks on a side stream
     (fork and join events); a captured graph of single frames and of frames in a row replays
@@ -375,7 +416,7 @@ def test_pinned_schedules_give_the_same_bits(name):
     ref = [plan.forward(xt, step=k0 + k, seed=4) for k in range(n)]
     ref = [(s.clone(), a.clone()) for s, a in ref]
     for fft_launch in ("side_stream", "same_launch"):
-        for frames in ("sequential", "pipelined"):
+        for frames in ("sequential", "pipelined", "overlapped"):
             for remap in (0, 1):
                 plan.set_schedule(field="split", frames=frames, xcd_remap=remap,
                                   fft_launch=fft_launch)
