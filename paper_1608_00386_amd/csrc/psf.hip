@@ -58,20 +58,27 @@ struct PsfParams {
 };
 
 // Per-layer parameters of one pupil row, staged in LDS by the workgroup: the row tap (fixed
-// for the row) and the column affine map.
+// for the row), the column affine map, and how the two layer rows are read (flags: kRowStaged
+// = copied to LDS first, kRowVec4 = with 16-byte loads).
 struct RowLayer {
   double a, b, inv_n;
   int64_t offset;
   int32_t n, boundary, r0, r1;
   float w0, w1, weight;
-  int32_t pad;
+  int32_t flags;
 };
+constexpr int kRowStaged = 1, kRowVec4 = 2;
 
 // Row pass: workgroup (row y, star s).  Phase of the pupil row, field, N-point FFT, row of T
 // stored in C-column tiles: T[s][k / C][y][k % C], so the column pass reads whole tiles.
+// The phase is a bilinear gather of every layer; when the pupil row is one pass of the
+// threads and two rows of a layer fit twice in the FFT buffer (free until the field is
+// written), the two layer rows of the pupil row's row tap are first copied to LDS with
+// coalesced loads (double-buffered by layer, one barrier a layer) and the stencils read LDS:
+// about a sixth of the load instructions of the per-pixel gather, the same arithmetic.
 template <int LOG2N>
 __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
-  extern __shared__ float2 sh[];
+  extern __shared__ __align__(16) float2 sh[];
   __shared__ double red[2][kPsfBlock];
   __shared__ RowLayer rl[kMaxLayers];
   constexpr int N = 1 << LOG2N;
@@ -95,7 +102,12 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
     r.w0 = ry.w0;
     r.w1 = ry.w1;
     r.weight = L.weight;
-    r.pad = 0;
+    r.flags = 0;
+    if (n <= 4 * kPsfBlock && 4 * L.nx <= 2 * fft_span(N)) {
+      r.flags = kRowStaged;
+      const uintptr_t a0 = reinterpret_cast<uintptr_t>(p.layers + L.offset);
+      if ((L.nx & 3) == 0 && (a0 & 15) == 0 && (fft_span(N) & 3) == 0) r.flags |= kRowVec4;
+    }
     rl[tid] = r;
   }
   __syncthreads();
@@ -112,19 +124,54 @@ __global__ __launch_bounds__(kPsfBlock) void psf_rows_kernel(PsfParams p) {
       lit[j] = x < n && p.mask[(int64_t)y * n + x];
       phi[j] = 0.0f;
     }
+    int ks = 0;  // staged layers so far (workgroup-uniform)
     for (int l = 0; l < p.n_layers; ++l) {
       const RowLayer r = rl[l];
       const Tap ry{r.r0, r.r1, r.w0, r.w1};
       const float* g = p.layers + r.offset;
+      if (r.flags & kRowStaged) {  // workgroup-uniform
+        // rows ry.i0 / nx and ry.i1 / nx of the layer -> buffer ks % 2, each buffer half of
+        // the FFT region (its last readers, the staged layer before the previous one, are
+        // behind the previous staged layer's barrier)
+        float* b0 = reinterpret_cast<float*>(sh) + (ks++ & 1) * fft_span(N);
+        float* b1 = b0 + r.n;
+        if (r.flags & kRowVec4) {
+          const float4* g0 = reinterpret_cast<const float4*>(g + ry.i0);
+          const float4* g1 = reinterpret_cast<const float4*>(g + ry.i1);
+          for (int c = tid; c < (r.n >> 2); c += kPsfBlock) {
+            reinterpret_cast<float4*>(b0)[c] = g0[c];
+            reinterpret_cast<float4*>(b1)[c] = g1[c];
+          }
+        } else {
+          for (int c = tid; c < r.n; c += kPsfBlock) {
+            b0[c] = g[ry.i0 + c];
+            b1[c] = g[ry.i1 + c];
+          }
+        }
+        __syncthreads();
 #pragma unroll
-      for (int j = 0; j < kPix; ++j) {
-        if (lit[j]) {
-          const int x = x0 + tid + j * kPsfBlock;
-          const Tap cx = make_tap(fma(r.a, (double)x, r.b), r.n, r.inv_n, r.boundary, 1);
-          phi[j] = fmaf(r.weight, bilinear(g, cx, ry), phi[j]);
+        for (int j = 0; j < kPix; ++j) {
+          if (lit[j]) {
+            const int x = x0 + tid + j * kPsfBlock;
+            const Tap cx = make_tap(fma(r.a, (double)x, r.b), r.n, r.inv_n, r.boundary, 1);
+            const float v00 = b0[cx.i0], v01 = b0[cx.i1], v10 = b1[cx.i0], v11 = b1[cx.i1];
+            const float v = ry.w0 * fmaf(cx.w0, v00, cx.w1 * v01) +
+                            ry.w1 * fmaf(cx.w0, v10, cx.w1 * v11);  // as bilinear()
+            phi[j] = fmaf(r.weight, v, phi[j]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kPix; ++j) {
+          if (lit[j]) {
+            const int x = x0 + tid + j * kPsfBlock;
+            const Tap cx = make_tap(fma(r.a, (double)x, r.b), r.n, r.inv_n, r.boundary, 1);
+            phi[j] = fmaf(r.weight, bilinear(g, cx, ry), phi[j]);
+          }
         }
       }
     }
+    __syncthreads();  // the staged rows are read before the field overwrites the buffer
 #pragma unroll
     for (int j = 0; j < kPix; ++j) {
       const int x = x0 + tid + j * kPsfBlock;
