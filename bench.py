@@ -191,7 +191,7 @@ def bench_batched(torch, W, steps=20, batch=8):
     cfg = synth.config2(batch=batch)
     x = torch.from_numpy(synth.make_batch(cfg, range(batch))).cuda()
     plan = W.Plan(cfg, batch=batch)
-    plan.tune(x, iters=3)
+    plan.tune(x, iters=20)  # 20 frames a candidate: the steady state of frames in a row
     slopes, aux = plan.forward(x, step=0)
 
     def step(i):
@@ -245,7 +245,7 @@ def bench_closed_loop(torch, W, steps=20, batch=8, gain=0.4):
     cfg = synth.config4(batch=batch)
     x = torch.from_numpy(synth.make_batch(cfg, range(batch))).cuda()
     plan = W.Plan(cfg, batch=batch)
-    plan.tune(x, iters=3)
+    plan.tune(x, iters=20)
     R = torch.from_numpy(synth.make_reconstructor(cfg["n_act_rows"], plan.n_slopes)).cuda()
     slopes, aux = plan.forward(x, step=0)
     dm = x.view(batch, -1)[:, cfg["dm_offset"]:]

@@ -214,21 +214,24 @@ int wfs_spots(wfs_plan_t plan, const float* phase, int64_t step, uint64_t seed, 
  *   the same launch as the lag-domain blocks (and, pipelined, the next step's projection:
  *   one launch per step).  proj_rows: the projection kernel's tile height, pupil rows per
  *   block (8, 16 or 32 where a block's layer taps fit 32 KiB of LDS; taller blocks share each
- *   column tap among more pixels, shorter ones give more blocks).  All choices give the same
- *   bits.  Any output pointer may be NULL.
+ *   column tap among more pixels, shorter ones give more blocks).  lag_passes: the split
+ *   field's spot waves form each lag row of the autocorrelation in 2 or 3 passes (3: less LDS
+ *   per wave, more waves per CU, a little more arithmetic).  All choices give the same bits.
+ *   Any output pointer may be NULL.
  */
 int wfs_plan_schedule(wfs_plan_t plan, int32_t* field, int32_t* frames, int32_t* xcd_remap,
-                      int32_t* fft_launch, int32_t* proj_rows);
+                      int32_t* fft_launch, int32_t* proj_rows, int32_t* lag_passes);
 
 /*
  * wfs_plan_set_schedule -- pin a launch schedule (values as wfs_plan_schedule reports them;
  *   -1 keeps a choice).  WFS_EUNSUPPORTED when the plan cannot run it: field 1 or frames 1
  *   or 3 without a phase buffer, field 2 or frames 2 where a lag-domain sensor cannot stage its
  *   footprint, field 2 for single frames with FFT-path sensors, frames 1 or 2 with field 0,
- *   a proj_rows the plan does not offer.  Host only; no device work.
+ *   a proj_rows the plan does not offer; WFS_EINVAL for lag_passes other than -1, 2, 3.
+ *   Host only; no device work.
  */
 int wfs_plan_set_schedule(wfs_plan_t plan, int32_t field, int32_t frames, int32_t xcd_remap,
-                          int32_t fft_launch, int32_t proj_rows);
+                          int32_t fft_launch, int32_t proj_rows, int32_t lag_passes);
 
 /*
  * wfs_plan_footprint -- algorithmic read footprint of the projection at time step `step`:
@@ -273,9 +276,10 @@ int wfs_advance_step(wfs_plan_t plan, int64_t delta, void* stream);
 /*
  * wfs_plan_tune -- time every launch schedule the plan can run (field, frame schedule incl.
  *   overlapped frames, block
- *   order, projection tile height where the projection kernel runs and, with both paths,
+ *   order, projection tile height where the projection kernel runs, lag passes of the split
+ *   field's spot waves and, with both paths,
  *   where the FFT-path blocks run) on max(2, iters) frames in a
- *   row from `layers` and keep the fastest; only schedules whose single frames and frames in
+ *   row from `layers` and keep the fastest (the four fastest of a first pass are timed three more times each); only schedules whose single frames and frames in
  *   a row give the same bits are candidates.  Then, where the split and footprint fields both
  *   fit the kept frame schedule (they share their bits), single frames take the faster.
  *   Honours WFS_FLAG_FUSED / SPLIT / FOOTPRINT.  Synchronises; writes scratch slopes

@@ -87,9 +87,9 @@ _PROTOS = {
     "wfs_spots": (_c.c_int, [_P, _P, _c.c_int64, _c.c_uint64, _P, _P, _P]),
     "wfs_plan_schedule": (_c.c_int, [_P, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
                                      _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32),
-                                     _c.POINTER(_c.c_int32)]),
+                                     _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "wfs_plan_set_schedule": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32,
-                                         _c.c_int32]),
+                                         _c.c_int32, _c.c_int32]),
     "wfs_plan_footprint": (_c.c_int, [_P, _c.c_int64, _c.POINTER(_c.c_int64),
                                       _c.POINTER(_c.c_int64)]),
     "wfs_adjoint": (_c.c_int, [_P, _P, _P, _P, _P, _c.c_int64, _P, _P]),

@@ -107,8 +107,9 @@ hipError_t launch_forward(const FwdParams& p, int ns, hipStream_t st, const Side
 
 int foot_pitch(int ns) { return otf_pitch(ns + 2); }
 
-int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats) {
-  return otf_lds_layout(ns, n_layers, n_pix, with_taps, foot_floats).total;
+int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats,
+                  int lag_parts) {
+  return otf_lds_layout(ns, n_layers, n_pix, with_taps, foot_floats, lag_parts).total;
 }
 
 int project_lds_bytes(int n_layers, int rows) {

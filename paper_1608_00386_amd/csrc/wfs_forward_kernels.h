@@ -17,16 +17,17 @@
 namespace wfs {
 
 // Split-schedule lag-domain kernels are held to 5 waves per SIMD for n_sub <= 10 (<= 96
-// VGPRs; their LDS, < 7 KB per wave, lets 5 four-wave blocks share a CU), fewer above.
-// Measured on one 80 x 80 LGS through ten 1024^2 layers: splitting the lag row in 3 or 4
-// passes to fit 7 or 8 waves per SIMD made the kernel slower (the spot stage is bound by VALU
-// issue, not by latency).
+// VGPRs; their LDS, < 7.5 KB per wave with the lag row in 2 passes, lets 5 four-wave blocks
+// share a CU), fewer above.  LP = 3 passes shrink the partial rows so that 7 blocks share a
+// CU (n_sub = 10): slower where a launch does not fill the chip (one 80 x 80 LGS: the extra
+// pass is pure VALU), faster where it takes several rounds of blocks (8 realisations of six
+// LGS: 0.61 -> 0.58 ms per step); the plan picks per launch size and the tuner times both.
 template <int NS, bool PROJ>
 constexpr int otf_waves_per_simd() {
   return NS <= 10 ? 5 : (NS == 11 ? 4 : 3);
 }
 
-template <int NS, int FIELD, bool FFT, bool PROJ>
+template <int NS, int FIELD, bool FFT, bool PROJ, int LP = kOtfLagParts>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu((FIELD == kFieldGather || FFT) ? 1
                                                                   : otf_waves_per_simd<NS, PROJ>())))
@@ -68,14 +69,21 @@ void wfs_forward_kernel(
   // one subaperture per wave and no task loop: a loop would let the compiler hoist per-lane
   // index arithmetic out of it and hold those registers across every stage
   const int t = L * kWavesPerBlock + wave;
-  if (t < total) otf_subap<NS, FIELD>(p, t, step + frame, wsm, frame);
+  if (t < total) otf_subap<NS, FIELD, LP>(p, t, step + frame, wsm, frame);
 }
 
-template <int NS, int FIELD, bool FFT, bool PROJ>
+template <int NS, int FIELD, bool FFT, bool PROJ, int LP = kOtfLagParts>
 static hipError_t launch_fwd_mode(const FwdParams& p, int grid, int lds, hipStream_t st) {
-  hipLaunchKernelGGL((wfs_forward_kernel<NS, FIELD, FFT, PROJ>), dim3(grid), dim3(kBlock), lds,
-                     st, p);
+  hipLaunchKernelGGL((wfs_forward_kernel<NS, FIELD, FFT, PROJ, LP>), dim3(grid), dim3(kBlock),
+                     lds, st, p);
   return hipGetLastError();
+}
+
+// split field: the lag row in p.lag_parts passes (2 or 3)
+template <int NS, bool FFT, bool PROJ>
+static hipError_t launch_fwd_phase(const FwdParams& p, int grid, int lds, hipStream_t st) {
+  if (p.lag_parts == 3) return launch_fwd_mode<NS, kFieldPhase, FFT, PROJ, 3>(p, grid, lds, st);
+  return launch_fwd_mode<NS, kFieldPhase, FFT, PROJ>(p, grid, lds, st);
 }
 
 // Launch of the spot kernel for subaperture size NS (lag-domain path), mode from the params.
@@ -101,10 +109,10 @@ hipError_t launch_fwd_ns(const FwdParams& p, hipStream_t st) {
                : launch_fwd_mode<NS, kFieldGather, false, false>(p, grid, lds, st);
   }
   if (fft)
-    return proj ? launch_fwd_mode<NS, kFieldPhase, true, true>(p, grid, lds, st)
-                : launch_fwd_mode<NS, kFieldPhase, true, false>(p, grid, lds, st);
-  return proj ? launch_fwd_mode<NS, kFieldPhase, false, true>(p, grid, lds, st)
-              : launch_fwd_mode<NS, kFieldPhase, false, false>(p, grid, lds, st);
+    return proj ? launch_fwd_phase<NS, true, true>(p, grid, lds, st)
+                : launch_fwd_phase<NS, true, false>(p, grid, lds, st);
+  return proj ? launch_fwd_phase<NS, false, true>(p, grid, lds, st)
+              : launch_fwd_phase<NS, false, false>(p, grid, lds, st);
 }
 
 }  // namespace wfs

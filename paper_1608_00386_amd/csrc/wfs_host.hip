@@ -51,7 +51,8 @@ hipError_t calib_poke(float* layers, const float* base, int64_t stride, int32_t 
                       int32_t n_chunk, float amp, hipStream_t st);
 hipError_t calib_diff(const float* slopes, int32_t h, int32_t n_slopes, int32_t n_chunk,
                       float amp, float* im, int64_t ld_im, hipStream_t st);
-int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats);
+int otf_lds_bytes(int ns, int n_layers, int n_pix, bool with_taps, int foot_floats,
+                  int lag_parts = kOtfLagParts);
 int foot_pitch(int ns);
 int fft_wave_lds_bytes(int n_fft, int n_pix);
 bool fft_supported(int n_sub, int n_fft, int bin);
@@ -116,6 +117,7 @@ struct OtfGroup {
   int64_t n_tasks = 0;
   // LDS bytes per wave of this group's lag-domain waves in a launch without FFT-path blocks
   int lds_split = 0, lds_fused = 0, lds_foot = 0, lds_adj = 0;
+  int lds_split_lp[2] = {0, 0};  // split field with the lag row in 2 / 3 passes
 };
 
 struct wfs_plan_s {
@@ -157,6 +159,9 @@ struct wfs_plan_s {
   bool adj_clear_grad = true;  // the layer grids leave gaps inside the stride
   int lds_split = 0, lds_fused = 0;  // LDS bytes per lag-domain wave, per schedule
   int lds_split_otf = 0, lds_fused_otf = 0;  // same, in a launch without FFT-path blocks
+  // the split field's figures with the lag row in 2 / 3 passes, and the current pass count
+  int lds_split_lp[2] = {0, 0}, lds_split_otf_lp[2] = {0, 0};
+  int lag_parts = kOtfLagParts;
   int proj_lds = 0;          // bytes of LDS per projection block (all sensors)
   int proj_lds_fft = 0;      // same, FFT-path sensors only
   ProjTable proj_all{}, proj_fft{};  // the projection blocks of the current tile height
@@ -212,6 +217,17 @@ static void destroy_ovl(wfs_plan_s* P) {
 
 // Makes projection tile height i of the plan the current one (host only: the descriptors of
 // every height are on the device already, and each height gives the same bits).
+static void use_lag_parts(wfs_plan_s* P, int lp) {
+  const int i = lp == 3 ? 1 : 0;
+  P->lag_parts = lp;
+  P->lds_split = P->lds_split_lp[i];
+  P->lds_split_otf = P->lds_split_otf_lp[i];
+  for (OtfGroup& G : P->groups) G.lds_split = G.lds_split_lp[i];
+  P->base.lag_parts = lp;
+  P->base.lds_per_wave = P->lds_split;
+  P->base.lds_per_wave_otf = P->lds_split_otf;
+}
+
 static void use_proj_set(wfs_plan_s* P, int i) {
   const ProjSet& q = P->proj_sets[i];
   P->proj_set = i;
@@ -926,8 +942,8 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
   for (int s : fft_ids)
     lds_fft = std::max(lds_fft, fft_wave_lds_bytes(sensors[s].n_fft,
                                                    sensors[s].n_fft / sensors[s].bin));
-  auto wave_lds = [&](bool taps, bool with_fft) {
-    int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps, 0) : 0;
+  auto wave_lds = [&](bool taps, bool with_fft, int lag_parts = kOtfLagParts) {
+    int w = otf_ns ? otf_lds_bytes(otf_ns, n_layers, P->otf_max_npix, taps, 0, lag_parts) : 0;
     if (with_fft) w = std::max(w, lds_fft);
     return std::max(16, (w + 15) & ~15);
   };
@@ -939,13 +955,17 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
                 lds_wave * kWavesPerBlock);
   }
   P->lds_fused = lds_wave;
-  P->lds_split = wave_lds(false, true);
+  for (int i = 0; i < 2; ++i) {
+    P->lds_split_lp[i] = wave_lds(false, true, 2 + i);
+    P->lds_split_otf_lp[i] = wave_lds(false, false, 2 + i);
+  }
   // every group's LDS per wave, in launches without FFT-path blocks (group 0's launch with
   // them takes the larger figures above)
   bool adj_ok = true;
   for (OtfGroup& G : P->groups) {
     auto r16 = [](int x) { return std::max(16, (x + 15) & ~15); };
-    G.lds_split = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, 0));
+    for (int i = 0; i < 2; ++i)
+      G.lds_split_lp[i] = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, 0, 2 + i));
     G.lds_fused = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, true, 0));
     G.lds_foot = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, G.foot_floats));
     G.lds_adj = r16(adj_lds_bytes(G.ns, n_layers, G.max_npix));
@@ -973,9 +993,20 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
     b.foot_ent_per_frame = (int32_t)foot_ent;
   }
   P->lds_fused_otf = wave_lds(true, false);
-  P->lds_split_otf = wave_lds(false, false);
-  b.lds_per_wave = P->lds_split;
-  b.lds_per_wave_otf = P->lds_split_otf;
+  {
+    // the lag row in 3 passes where that lets more blocks share a CU and the split launch
+    // runs more than two rounds of blocks (one 80 x 80 LGS: 1,158 blocks, 2 passes; eight
+    // realisations of six: 55,584 blocks, 3 passes); wfs_plan_tune times both
+    auto per_cu = [](int lds_wave) { return std::min(8, 163840 / (lds_wave * kWavesPerBlock)); };
+    int64_t blocks = 0;
+    for (const OtfGroup& G : P->groups) blocks += (G.n_tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+    int lp = kOtfLagParts;
+    if (!P->groups.empty() &&
+        per_cu(P->groups[0].lds_split_lp[1]) > per_cu(P->groups[0].lds_split_lp[0]) &&
+        blocks > 2LL * 256 * per_cu(P->groups[0].lds_split_lp[0]))
+      lp = 3;
+    use_lag_parts(P, lp);
+  }
   P->adj_lds_per_wave = otf_ns ? P->groups[0].lds_adj : 16;
   if (!adj_ok) P->adj_lds_per_wave = 0;  // adjoint unsupported
   // FFT blocks first, padded to a multiple of 8 so the lag-domain blocks keep their XCD order
@@ -1416,7 +1447,7 @@ int wfs_spots(wfs_plan_t P, const float* phase, int64_t step, uint64_t seed, flo
 }
 
 int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xcd_remap,
-                      int32_t* fft_launch, int32_t* proj_rows) {
+                      int32_t* fft_launch, int32_t* proj_rows, int32_t* lag_passes) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_schedule: null plan");
   const bool split = P->split && P->d_phase;
   if (field) *field = P->foot ? 2 : (split ? 1 : 0);
@@ -1424,17 +1455,19 @@ int wfs_plan_schedule(wfs_plan_t P, int32_t* field, int32_t* frames, int32_t* xc
   if (xcd_remap) *xcd_remap = P->base.xcd_remap;
   if (fft_launch) *fft_launch = P->base.fft_inline;
   if (proj_rows) *proj_rows = P->proj_sets[P->proj_set].rows;
+  if (lag_passes) *lag_passes = P->lag_parts;
   return WFS_OK;
 }
 
 int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t xcd_remap,
-                          int32_t fft_launch, int32_t proj_rows) {
+                          int32_t fft_launch, int32_t proj_rows, int32_t lag_passes) {
   if (!P) return fail(WFS_EINVAL, "wfs_plan_set_schedule: null plan");
   if (field < -1 || field > 2 || frames < -1 || frames > 3 || xcd_remap < -1 ||
-      xcd_remap > 1 || fft_launch < -1 || fft_launch > 1 || proj_rows < -1)
+      xcd_remap > 1 || fft_launch < -1 || fft_launch > 1 || proj_rows < -1 ||
+      !(lag_passes == -1 || lag_passes == 2 || lag_passes == 3))
     return fail(WFS_EINVAL, "wfs_plan_set_schedule: field=%d frames=%d xcd_remap=%d "
-                "fft_launch=%d proj_rows=%d out of range", field, frames, xcd_remap, fft_launch,
-                proj_rows);
+                "fft_launch=%d proj_rows=%d lag_passes=%d out of range", field, frames,
+                xcd_remap, fft_launch, proj_rows, lag_passes);
   int ps = P->proj_set;
   if (proj_rows >= 0) {
     ps = -1;
@@ -1470,6 +1503,7 @@ int wfs_plan_set_schedule(wfs_plan_t P, int32_t field, int32_t frames, int32_t x
   if (xcd_remap >= 0) P->base.xcd_remap = xcd_remap;
   if (fft_launch >= 0) P->base.fft_inline = fft_launch;
   use_proj_set(P, ps);
+  if (lag_passes > 0) use_lag_parts(P, lag_passes);
   return WFS_OK;
 }
 
@@ -1703,14 +1737,14 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   };
   const FwdParams keep = P->base;
   const int keep_split = P->split, keep_foot = P->foot, keep_frames = P->frames;
-  const int keep_ps = P->proj_set;
+  const int keep_ps = P->proj_set, keep_lp = P->lag_parts;
   // candidates (field, frames, block order, FFT-path blocks in the lag-domain launch,
   // projection tile height), timed on nf frames in a row (the stepping loop the plan serves);
   // only schedules whose single frames and frames in a row give the same bits: the gather
   // field steps frame by frame, the split and footprint fields share their bits with
   // pipelined and one-launch frames; every tile height gives the same bits
   struct Cand {
-    int field, frames, remap, inl, ps;
+    int field, frames, remap, inl, ps, lp;
   };
   std::vector<Cand> cands;
   const bool has_fft = P->fft_tasks > 0, mixed = P->fft_tasks > 0 && P->otf_tasks > 0;
@@ -1720,49 +1754,66 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   const int n_ps = (int)P->proj_sets.size();
   // the tile heights of the projection kernel, for a schedule that launches it (the split
   // field, and the FFT-path sensors of any field)
+  // and, for the split field's spot kernel, the lag row in 2 or 3 passes
   auto add = [&](Cand c) {
     const bool proj = c.field == 1 || has_fft;
-    for (int ps = 0; ps < (proj ? n_ps : 1); ++ps) {
-      c.ps = proj ? ps : keep_ps;
-      cands.push_back(c);
-    }
+    const bool split_spots = c.field == 1 || c.frames == 1 || c.frames == 3;
+    for (int ps = 0; ps < (proj ? n_ps : 1); ++ps)
+      for (int lp = 2; lp <= (split_spots ? 3 : 2); ++lp) {
+        c.ps = proj ? ps : keep_ps;
+        c.lp = split_spots ? lp : keep_lp;
+        cands.push_back(c);
+      }
   };
   for (int remap = 0; remap < 2; ++remap)
     for (int inl = 0; inl < (mixed ? 2 : 1); ++inl) {
-      if (!(fl & (WFS_FLAG_SPLIT | WFS_FLAG_FOOTPRINT))) add({0, 0, remap, inl, 0});
+      if (!(fl & (WFS_FLAG_SPLIT | WFS_FLAG_FOOTPRINT))) add({0, 0, remap, inl, 0, 0});
       if (phase_ok && !(fl & WFS_FLAG_FUSED)) {
         if (!((fl & WFS_FLAG_FOOTPRINT) && foot1)) {
-          add({1, 0, remap, inl, 0});
-          add({1, 1, remap, inl, 0});
-          if (P->ovl.stream) add({1, 3, remap, inl, 0});
+          add({1, 0, remap, inl, 0, 0});
+          add({1, 1, remap, inl, 0, 0});
+          if (P->ovl.stream) add({1, 3, remap, inl, 0, 0});
         }
       }
       if (inl == 0 && P->foot_ok && !(fl & (WFS_FLAG_FUSED | WFS_FLAG_SPLIT)) &&
           (foot1 || phase_ok))
-        add({foot1 ? 2 : 1, 2, remap, 0, 0});
+        add({foot1 ? 2 : 1, 2, remap, 0, 0, 0});
     }
   auto apply = [&](const Cand& c) {
     P->base = keep;
     P->base.xcd_remap = c.remap;
     P->base.fft_inline = c.inl;
     use_proj_set(P, c.ps);
+    use_lag_parts(P, c.lp);
     P->split = c.field == 1;
     P->foot = c.field == 2;
     P->frames = c.frames;
   };
-  double best_t = 1e30;
-  int best_i = -1;
-  for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i) {
+  // every candidate once (after a warm-up), then the four fastest three more times each: the
+  // fastest minimum wins (single timings of a few frames differ by several per cent)
+  auto time_cand = [&](size_t i, bool warm) {
     apply(cands[i]);
-    e = run_steps(P, layers, 0, nf, 1, slopes, aux, P->frames, st);  // warm-up
-    if (e != hipSuccess) break;
+    if (warm) e = run_steps(P, layers, 0, nf, 1, slopes, aux, P->frames, st);
+    if (e != hipSuccess) return 1e30;
     (void)hipEventRecord(e0, st);
     e = run_steps(P, layers, 0, nf, 1, slopes, aux, P->frames, st);
     (void)hipEventRecord(e1, st);
     const double ms = elapsed_ms();
-    if (e == hipSuccess && ms < best_t) {
-      best_t = ms;
-      best_i = (int)i;
+    return e == hipSuccess ? ms : 1e30;
+  };
+  std::vector<std::pair<double, int>> first;
+  for (size_t i = 0; i < cands.size() && e == hipSuccess; ++i)
+    first.push_back({time_cand(i, true), (int)i});
+  std::sort(first.begin(), first.end());
+  double best_t = 1e30;
+  int best_i = -1;
+  for (size_t r = 0; r < first.size() && r < 4 && e == hipSuccess; ++r) {
+    double t = first[r].first;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+      t = std::min(t, time_cand((size_t)first[r].second, rep == 0));
+    if (e == hipSuccess && t < best_t) {
+      best_t = t;
+      best_i = first[r].second;
     }
   }
   double single_us = 0.0;
@@ -1798,6 +1849,7 @@ int wfs_plan_tune(wfs_plan_t P, const float* layers, int32_t iters, double* best
   if (e != hipSuccess) {
     P->base = keep;
     use_proj_set(P, keep_ps);
+    use_lag_parts(P, keep_lp);
     P->split = keep_split;
     P->foot = keep_foot;
     P->frames = keep_frames;

@@ -14,7 +14,7 @@ constexpr int kMaxSensors = 64;
 constexpr int kOtfMaxNsub = 12;    // lag-domain path: subapertures up to 12 x 12 pixels
 constexpr int kFftMaxNsub = 64;    // FFT path: fields up to 64 x 64 pixels
 constexpr int kFftMaxN = 128;      // FFT path: transforms up to 128 points per axis
-constexpr int kOtfLagParts = 2;    // lag-domain path: passes over each lag row
+constexpr int kOtfLagParts = 2;    // lag-domain path: default passes over each lag row
 
 enum Path : int32_t { kPathOtf = 0, kPathFft = 1 };
 
@@ -157,6 +157,7 @@ struct FwdParams {
   int32_t lds_per_wave;     // bytes (lag-domain waves, or a quarter of an FFT workgroup)
   int32_t lds_per_wave_otf; // bytes when the launch holds no FFT-path blocks
   int32_t otf_from_phase;   // lag-domain field source: 0 gather, 1 phase_in (split), 2 footprint
+  int32_t lag_parts;        // split field: passes over each lag row (2 or 3; sets its LDS)
   int32_t fft_inline;       // host side: FFT-path blocks in the same launch as the others
   // FFT path: partial binned images of the spectrum chunks ([B][fft_part_per_real] floats)
   // and per-subaperture chunk counters ([B][fft_cnt_per_real], zero between launches)

@@ -27,11 +27,11 @@ namespace wfs {
 
 __host__ __device__ constexpr int otf_pitch(int n) { return n | 1; }
 
-template <int NS>
+template <int NS, int LP = kOtfLagParts>
 struct Otf {
   static constexpr int kJobs = NS * (NS + 1) / 2;  // row pairs (dy, r), dy >= 0
   static constexpr int kLags = 2 * NS - 1;         // dx = -(NS-1) .. NS-1
-  static constexpr int kParts = kOtfLagParts;        // passes over the lag row
+  static constexpr int kParts = LP;                // passes over the lag row
   static constexpr int kChunk = (kLags + kParts - 1) / kParts;  // lag columns per pass
   // odd LDS pitches (float2) of the field rows and of the partial lag rows: lanes reading
   // different rows of E, or writing their own partial row, fall on distinct bank pairs
@@ -58,7 +58,7 @@ __host__ __device__ constexpr int otf_part_rows(int ns) {
 //   float2 (weighted lag sums) |
 //   union( taps [n_layers][2 n_sub] Tap (fused gather and adjoint only),
 //          partial lag rows (one round, one pass over the lag row at a time:
-//          [jobs][ceil((2 n_sub - 1) / kOtfLagParts) rounded up to odd] float2),
+//          [jobs][ceil((2 n_sub - 1) / lag passes) rounded up to odd] float2),
 //          P (later B) + Z (after the last round) ) |
 //   tables: s(k) [2 n_sub - 1] float2, twiddles [n_pix] float2
 // With a staged footprint (foot_floats > 0) the field stage also lays out, from offset 0
@@ -72,14 +72,15 @@ struct OtfLds {
 };
 
 __host__ __device__ inline OtfLds otf_lds_layout(int ns, int n_layers, int n_pix,
-                                                 bool with_taps = true, int foot_floats = 0) {
+                                                 bool with_taps = true, int foot_floats = 0,
+                                                 int lag_parts = kOtfLagParts) {
   OtfLds o;
   const int jobs = otf_part_rows(ns), lags = 2 * ns - 1, np2 = n_pix * n_pix;
   o.e_off = 0;
   o.aw_off = ns * otf_pitch(ns) * 8;
   const int u0 = (o.aw_off + ns * lags * 8 + 15) & ~15;
   const int taps = 2 * ns * n_layers * 16;
-  const int part = jobs * otf_pitch((lags + kOtfLagParts - 1) / kOtfLagParts) * 8;
+  const int part = jobs * otf_pitch((lags + lag_parts - 1) / lag_parts) * 8;
   o.taps_off = u0;
   o.part_off = u0;
   o.p_off = u0;  // the fold writes P after the last round has read its partial rows
@@ -538,7 +539,7 @@ __device__ __forceinline__ void otf_field(const FwdParams& p, const DevSensor& S
 // Lag sums of one round of row-pair jobs for the lag columns [IX0, IX0 + W) (held in the
 // partial-row region, kChunk columns per job), times the elongation and binning factors:
 // AW[dy][dx] (+)= w_dy Kel(dx, dy) s(dx) s(dy) sum_r part, lane per lag (dy, dx).
-template <int NS, int IX0, int W>
+template <int NS, int LP, int IX0, int W>
 __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& sb,
                                            const NaEntry& el, char* wsm, const OtfLds& lo,
                                            int j0) {
@@ -567,12 +568,12 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
     const int q = lane / W, k = lane - q * W;
     if (q < NQ) {
       const int dyA = q, dyB = NS - 1 - q, nA = NS - q;
-      const float2* rows = part + q * (NS + 1) * Otf<NS>::kPS + k;  // the pair's slots
+      const float2* rows = part + q * (NS + 1) * Otf<NS, LP>::kPS + k;  // the pair's slots
       float2 a = make_float2(0.0f, 0.0f), bsum = make_float2(0.0f, 0.0f);
 #pragma unroll
       for (int t = 0; t <= NS; ++t) {
         const bool inA = t < nA;
-        const float2 v = rows[t * Otf<NS>::kPS];
+        const float2 v = rows[t * Otf<NS, LP>::kPS];
         if (inA) {
           a.x += v.x;
           a.y += v.y;
@@ -599,7 +600,7 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
         if (r >= r0 && r < r1) {
-          const float2 v = part[(base + r - j0) * Otf<NS>::kPS + k];
+          const float2 v = part[(base + r - j0) * Otf<NS, LP>::kPS + k];
           a.x += v.x;
           a.y += v.y;
         }
@@ -622,7 +623,7 @@ __device__ __forceinline__ void otf_lagsum(const DevSensor& S, const DevSubap& s
 // registers and leaves them in the partial-row region, then the lag sums over r.  Taking the
 // lag row in kOtfLagParts passes keeps the registers and the LDS region at that fraction of a
 // row per job, at the same number of multiply-adds.
-template <int NS, int IX0, int W>
+template <int NS, int LP, int IX0, int W>
 __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap& sb,
                                               const NaEntry& el, char* wsm, const OtfLds& lo,
                                               int j0) {
@@ -661,20 +662,20 @@ __device__ __forceinline__ void otf_corr_part(const DevSensor& S, const DevSubap
       }
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) part[lane * Otf<NS>::kPS + k] = acc[k];
+    for (int k = 0; k < W; ++k) part[lane * Otf<NS, LP>::kPS + k] = acc[k];
   }
   wave_sync();
-  otf_lagsum<NS, IX0, W>(S, sb, el, wsm, lo, j0);
+  otf_lagsum<NS, LP, IX0, W>(S, sb, el, wsm, lo, j0);
 }
 
-template <int NS, int IX0 = 0>
+template <int NS, int LP, int IX0 = 0>
 __device__ __forceinline__ void otf_corr_round(const DevSensor& S, const DevSubap& sb,
                                                const NaEntry& el, char* wsm, const OtfLds& lo,
                                                int j0) {
-  constexpr int NL = Otf<NS>::kLags, CW = Otf<NS>::kChunk;
+  constexpr int NL = Otf<NS, LP>::kLags, CW = Otf<NS, LP>::kChunk;
   constexpr int W = IX0 + CW <= NL ? CW : NL - IX0;
-  otf_corr_part<NS, IX0, W>(S, sb, el, wsm, lo, j0);
-  if constexpr (IX0 + W < NL) otf_corr_round<NS, IX0 + W>(S, sb, el, wsm, lo, j0);
+  otf_corr_part<NS, LP, IX0, W>(S, sb, el, wsm, lo, j0);
+  if constexpr (IX0 + W < NL) otf_corr_round<NS, LP, IX0 + W>(S, sb, el, wsm, lo, j0);
 }
 
 // Fold modulo n_pix: P[Ky][Kx] = sum over lags (dy, dx) = (Ky, Kx) mod n_pix of AW, lane per K.
@@ -867,8 +868,9 @@ __device__ __forceinline__ void write_slopes(const FwdParams& p, const DevSensor
   }
 }
 
-// Binned noise-free (or noisy) image of one subaperture into the wave's B region.
-template <int NS, int FIELD>
+// Binned noise-free (or noisy) image of one subaperture into the wave's B region (LP: passes
+// over each lag row, which sets the partial-row region of the layout `lo`).
+template <int NS, int FIELD, int LP = kOtfLagParts>
 __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
                                          const DevSubap& sb, int sid, int b, int64_t step,
                                          char* wsm, const OtfLds& lo, int frame = 0) {
@@ -876,21 +878,23 @@ __device__ __forceinline__ void otf_spot(const FwdParams& p, const DevSensor& S,
   const NaEntry el = na_entry(p, step);
 #pragma unroll
   for (int rd = 0; rd < Otf<NS>::kRounds; ++rd)
-    otf_corr_round<NS>(S, sb, el, wsm, lo, rd * Otf<NS>::kJobsPerRound);
+    otf_corr_round<NS, LP>(S, sb, el, wsm, lo, rd * Otf<NS>::kJobsPerRound);
   otf_fold<NS>(S, wsm, lo);
   otf_image(p, S, wsm, lo);
 }
 
-template <int NS, int FIELD>
+template <int NS, int FIELD, int LP = kOtfLagParts>
 __device__ void otf_subap(const FwdParams& p, int t, int64_t step, char* wsm, int frame = 0) {
   int b, sid, v;
   t = __builtin_amdgcn_readfirstlane(t);  // wave-uniform: per-subaperture data in SGPRs
   task_of(p.otf, t, b, sid, v);
   const DevSensor S = cload(p.sen, sid);
   const DevSubap sb = cload(p.sub, S.valid_off + v);
-  const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix, false,
-                                   FIELD == kFieldFoot ? S.foot_floats : 0);
-  otf_spot<NS, FIELD>(p, S, sb, sid, b, step, wsm, lo, frame);
+  // the layout the host sized the launch with: the per-pixel gather holds its stencil taps
+  // in the union (the sensor tables follow whichever of taps, partial rows and image is last)
+  const OtfLds lo = otf_lds_layout(NS, p.n_layers, S.n_pix, FIELD == kFieldGather,
+                                   FIELD == kFieldFoot ? S.foot_floats : 0, LP);
+  otf_spot<NS, FIELD, LP>(p, S, sb, sid, b, step, wsm, lo, frame);
   const Cog c = cog_sums(p, S, sid, b, v, step + p.noise_dstep,
                          reinterpret_cast<const float*>(wsm + lo.b_off));
   write_slopes(p, S, b, v, c, frame);

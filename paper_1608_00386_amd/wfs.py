@@ -160,23 +160,25 @@ class Plan:
         schedule: field is where a frame's spot waves get the phase ("gather", "split",
         "footprint"), frames how ``forward_steps`` runs ("sequential", "pipelined",
         "one_launch", "overlapped": the next frame projected on a second stream), fft_launch where FFT-path blocks run ("side_stream" or "same_launch"),
-        proj_rows the projection kernel's pupil rows per block."""
-        v = [ctypes.c_int32() for _ in range(5)]
+        proj_rows the projection kernel's pupil rows per block, lag_passes the split field's
+        passes over each lag row (2 or 3)."""
+        v = [ctypes.c_int32() for _ in range(6)]
         L.check(self._lib.wfs_plan_schedule(self._h, *[ctypes.byref(x) for x in v]),
                 "wfs_plan_schedule")
         return dict(field=self.FIELDS[v[0].value], frames=self.FRAMES[v[1].value],
                     xcd_remap=v[2].value, fft_launch=self.FFT_LAUNCH[v[3].value],
-                    proj_rows=v[4].value)
+                    proj_rows=v[4].value, lag_passes=v[5].value)
 
     def set_schedule(self, field=None, frames=None, xcd_remap=None, fft_launch=None,
-                     proj_rows=None):
+                     proj_rows=None, lag_passes=None):
         """Pin a launch schedule (names as ``schedule`` reports them; None keeps a choice)."""
         def code(names, v):
             return -1 if v is None else (names.index(v) if isinstance(v, str) else int(v))
         L.check(self._lib.wfs_plan_set_schedule(
             self._h, code(self.FIELDS, field), code(self.FRAMES, frames),
             -1 if xcd_remap is None else int(xcd_remap), code(self.FFT_LAUNCH, fft_launch),
-            -1 if proj_rows is None else int(proj_rows)), "wfs_plan_set_schedule")
+            -1 if proj_rows is None else int(proj_rows),
+            -1 if lag_passes is None else int(lag_passes)), "wfs_plan_set_schedule")
 
     def footprint(self, step=0):
         """(distinct layer pixels read, projected pixels) per realisation at ``step``."""

@@ -156,8 +156,8 @@ def test_calls_reject_null_handles_without_a_device():
     assert L.wfs_adjoint(None, None, None, None, None, 0, None, None) == -1
     assert L.wfs_plan_destroy(None) == -1
     assert L.wfs_spots(None, None, 0, 0, None, None, None) == -1
-    assert L.wfs_plan_schedule(None, None, None, None, None, None) == -1
-    assert L.wfs_plan_set_schedule(None, -1, -1, -1, -1, -1) == -1
+    assert L.wfs_plan_schedule(None, None, None, None, None, None, None) == -1
+    assert L.wfs_plan_set_schedule(None, -1, -1, -1, -1, -1, -1) == -1
     assert L.wfs_plan_footprint(None, 0, None, None) == -1
     assert L.recon_apply(None, 1, 1, None, 1, None, 1, 1.0, 0.0, None) == -1
     assert "null" in L.wfs_last_error().decode()

@@ -296,6 +296,42 @@ def test_config0_paper_sampling_counts():
     np.testing.assert_allclose(plan1.pix_scale[0], oracle.pixel_scale(synth.config1()["sensors"][0]))
 
 
+@pytest.mark.parametrize("name", ["mixed_lgs_ngs_batch2", "config2_batch2", "cfg1",
+                                  "lgs_n4_N8_b2_20layers", "ngs_n12_N24_b3"])
+def test_lag_passes_give_the_same_bits(name):
+    """The split field's spot waves form each lag row in 2 or 3 passes (wfs_plan_set_schedule's
+    lag_passes): the same multiply-adds in the same order, so single frames, pipelined and
+    overlapped frames give the same bits either way; other values are refused."""
+    torch, W = _gpu()
+    if name == "config2_batch2":
+        cfg, B = synth.config2(batch=2), 2
+        x = synth.make_batch(cfg, range(B))
+    elif name == "cfg1":
+        cfg, B = synth.config1(), 1
+        x = synth.make_batch(cfg, [0])
+    else:
+        cfg = CASES[name]()
+        x = layers_for(cfg)
+        B = x.shape[0]
+    xt = torch.from_numpy(x).cuda()
+    plan = W.Plan(cfg, batch=B)
+    plan.set_schedule(field="split", frames="sequential", lag_passes=2)
+    ref, aref = plan.forward(xt, step=4, seed=6)
+    ref, aref = ref.clone(), aref.clone()
+    steps2, _ = plan.forward_steps(xt, 4, 3, seed=6)
+    for frames in ("sequential", "pipelined", "overlapped"):
+        plan.set_schedule(field="split", frames=frames, lag_passes=3)
+        assert plan.schedule()["lag_passes"] == 3
+        s, a = plan.forward(xt, step=4, seed=6)
+        assert torch.equal(s, ref) and torch.equal(a, aref), frames
+        s3, _ = plan.forward_steps(xt, 4, 3, seed=6)
+        assert torch.equal(s3, steps2), frames
+    for bad in (1, 4):
+        with pytest.raises(W.WfsError) as e:
+            plan.set_schedule(lag_passes=bad)
+        assert e.value.code == -1
+
+
 @pytest.mark.parametrize("name", ["mixed_lgs_ngs_batch2", "config2_batch2"])
 def test_overlapped_frames_match_single_frames_and_replay(name):
     """Overlapped frames (frame k + 1 projected on the plan's projection stream while frame

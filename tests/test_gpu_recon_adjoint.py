@@ -263,6 +263,32 @@ def test_autograd_function_uses_the_adjoint():
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
 
 
+def test_autograd_function_on_a_noisy_plan_uses_the_noise_free_adjoint():
+    """With photon and read noise on, WFSFunction's backward does not reuse the noisy forward
+    outputs: it runs the adjoint of the noise-free model (fields and spot sums recomputed), so
+    the layer gradient of sum(s^2) is J^T (2 s) with J the noise-free Jacobian and s the noisy
+    slopes the forward returned."""
+    import copy
+    torch, W = _gpu()
+    cfg = CASES["lgs_n10_N32_b4_noise"]()
+    assert any(sd["photons"] > 0 for sd in cfg["sensors"])
+    x = layers_for(cfg, scale=0.5)
+    plan = W.Plan(cfg)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    s = W.wfs_slopes(xt, plan, step=3, seed=11)
+    (s ** 2).sum().backward()
+    g = 2.0 * s.detach().cpu().numpy().astype(np.float64)
+    quiet = copy.deepcopy(cfg)
+    for sd in quiet["sensors"]:
+        sd["photons"] = 0.0
+        sd["read_noise_e"] = 0.0
+    s_quiet = oracle.forward(x.astype(np.float64), quiet, 3, noise=False)[0]
+    assert np.abs(g / 2.0 - s_quiet).max() > 1e-3  # the forward really was noisy
+    ref = oracle.adjoint(x.astype(np.float64), quiet, 3, g)
+    got = xt.grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
+
+
 def test_adjoint_dot_product_with_gpu_forward():
     """<J v, g> from a central difference of the GPU forward equals <v, J^T g> from the GPU
     adjoint (to the accuracy of an FP32 difference quotient)."""

@@ -87,6 +87,9 @@ def uneven_case(fft=True, batch=3):
 CASES = {
     "cfg0": lambda: synth.config0(),
     "lgs_n4_N8_b2": lambda: lgs_case(6, 4, 8, 2),
+    # many layers on a small subaperture: the per-pixel gather's stencil taps outgrow the
+    # lag-domain regions they share LDS with (the sensor tables must follow them)
+    "lgs_n4_N8_b2_20layers": lambda: lgs_case(6, 4, 8, 2, layers=20),
     "lgs_n10_N32_b4_noise": lambda: lgs_case(12, 10, 32, 4, layers=3, n=256, noise=True),
     "lgs_n5_N10_b2_2sens_batch3": lambda: lgs_case(9, 5, 10, 2, n_sensors=2, batch=3, noise=True),
     "ngs_n6_N12_b4_oddpix": lambda: ngs_case(5, 6, 12, 4, D=6.0, obs=1.2),
