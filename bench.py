@@ -672,29 +672,34 @@ def main():
     #   sequential split / gather: the spot launch of each frame.
     frames = r1["schedule"]["frames"]
     field = r1["schedule"]["field"]
+    lp = r1["schedule"].get("lag_passes", 2)  # last template argument of the spot kernels
     if frames == "one_launch":
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = ("wfs_forward_kernel<10, footprint> (the K frames of one call in launches "
                      "of up to 256 frames, each after the small launch that fills its frames' "
                      "stencil entries; each wave projects its subaperture from a footprint "
                      "staged in LDS)")
-        traffic_key = "wfs_forward_kernel<10, 2, false, false>"
+        traffic_key = "wfs_forward_kernel<10, 2, false, false, 2>"
     elif frames == "pipelined":
         kern_ms = (r1["gpu_ms_per_frame"] * args.steps - r1["project_ms"]) / args.steps
         kern_name = "wfs_forward_kernel<10, split> (spots of step k + projection of step k+1)"
-        traffic_key = "wfs_forward_kernel<10, 1, false, true>"
+        traffic_key = "wfs_forward_kernel<10, 1, false, true, %d>" % lp
+    elif frames == "overlapped":  # projections run beside the spots: the spot launch alone
+        kern_ms = r1["spots_ms"]
+        kern_name = "wfs_forward_kernel<10, split> (spots; projections on a second stream)"
+        traffic_key = "wfs_forward_kernel<10, 1, false, false, %d>" % lp
     elif field == "split":
         kern_ms = r1["gpu_ms_per_frame"] - r1["project_ms"]
         kern_name = "wfs_forward_kernel<10, split> (spots)"
-        traffic_key = "wfs_forward_kernel<10, 1, false, false>"
+        traffic_key = "wfs_forward_kernel<10, 1, false, false, %d>" % lp
     elif field == "footprint":
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = "wfs_forward_kernel<10, footprint> (one frame per launch)"
-        traffic_key = "wfs_forward_kernel<10, 2, false, false>"
+        traffic_key = "wfs_forward_kernel<10, 2, false, false, 2>"
     else:
         kern_ms = r1["gpu_ms_per_frame"]
         kern_name = "wfs_forward_kernel<10, gather> (per-pixel gather)"
-        traffic_key = "wfs_forward_kernel<10, 0, false, false>"
+        traffic_key = "wfs_forward_kernel<10, 0, false, false, 2>"
     in_wave_proj = field == "footprint" or frames == "one_launch"
     achieved = flops / (kern_ms * 1e-3)
     foot, n_phase = r1["plan"].footprint(0)
