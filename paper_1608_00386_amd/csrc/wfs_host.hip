@@ -36,7 +36,7 @@ hipError_t launch_adjoint_gather_tab(const FwdParams& f, const float* gpsi, floa
 int adj_tab_rows();
 int fft_adj_wave_lds_bytes(int n_fft, int n_pix);
 hipError_t launch_adjoint_fft(const AdjParams& a, int lds_per_wave, hipStream_t st);
-int adj_lds_bytes(int ns, int n_layers, int n_pix);
+int adj_lds_bytes(int ns, int n_layers, int n_pix, bool gather);
 hipError_t recon_work_floats(const float* R, int M, int N, const float* S, int B,
                              int64_t* floats);
 hipError_t recon_stream_work(hipStream_t st, int64_t floats, float** out, bool* capturing);
@@ -968,7 +968,14 @@ int wfs_plan(const wfs_layer_desc* layers, int32_t n_layers, int64_t layer_strid
       G.lds_split_lp[i] = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, 0, 2 + i));
     G.lds_fused = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, true, 0));
     G.lds_foot = r16(otf_lds_bytes(G.ns, n_layers, G.max_npix, false, G.foot_floats));
-    G.lds_adj = r16(adj_lds_bytes(G.ns, n_layers, G.max_npix));
+    // the adjoint's form (gather unless asked for atomics), as wfs_adjoint decides it
+    const bool adj_gather =
+        !(flags & WFS_FLAG_ADJOINT_ATOMIC) && P->pupil_per_real < (1LL << 30);
+    // (each wave lays out its own sensor's image size: take the largest over the sizes)
+    int adj_max = 0;
+    for (int np = 1; np <= G.max_npix; ++np)
+      adj_max = std::max(adj_max, adj_lds_bytes(G.ns, n_layers, np, adj_gather));
+    G.lds_adj = r16(adj_max);
     if (G.lds_fused * kWavesPerBlock > 65536) {
       (void)hipFree(P->d_blob);
       delete P;
