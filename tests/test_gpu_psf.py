@@ -73,9 +73,11 @@ def _compare(cfg, x, stars, steps, lambdas, n_fft, D, obs, n_pup, check_pixels=N
     return plan, psf, var
 
 
-@pytest.mark.parametrize("n_fft", [[32, 64], [128, 256], [16, 4096]])
+@pytest.mark.parametrize("n_fft", [[32, 64], [128, 256], [16, 4096], [512, 1024]])
 def test_psf_matches_oracle_small(n_fft):
-    """Two stars, two wavelengths (odd and even log2 N), frozen flow over three steps."""
+    """Two stars, two wavelengths (odd and even log2 N), frozen flow over three steps.  The
+    sizes cover every stage plan of the LDS transform: radix 16 alone (16, 256, 4096) and
+    followed by a radix-2 (32, 512), radix-4 (64, 1024) or radix-8 (128) stage."""
     n_pup = 16 if 16 in n_fft else 24
     cfg, x, n_pup, D, obs = _small(n_pup=n_pup)
     stars = [(0.0, 0.0), (15 * ARCSEC, -10 * ARCSEC)]
