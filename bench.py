@@ -222,7 +222,7 @@ def bench_batched(torch, W, steps=20, batch=8):
     proj_bytes = 4.0 * (foot + n_phase) * batch
     return dict(workload="config2: 6 LGS 80x80 + 3 NGS 2x2 (64 px, N=128), 8 realisations, "
                          "10 layers 1024^2, noise on, %d steps in one wfs_forward_steps graph "
-                         "(pipelined as tuned)" % steps,
+                         "(frame schedule as tuned)" % steps,
                 ms_per_step=gpu_ms, steps=steps,
                 single_step_ms=single_ms,
                 lgs_frames_per_s=n_lgs * batch / (gpu_ms * 1e-3),
